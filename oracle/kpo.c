@@ -577,15 +577,17 @@ void kpo_update_estimates(kpo_planner* P) {
                 NULL, P->thr);
 }
 
-/* Two node-set words for node i in iteration it: word 0 decides the move
- * V_E -> V_O, word 1 the move V_O -> V_E. */
+/* Two node-set words for node i in iteration it: one Philox block serves the
+ * node pair (2k, 2k+1) through counter (it, k, 0, 3); node 2k takes words 0
+ * and 1, node 2k+1 words 2 and 3.  The first word of the pair decides the
+ * move V_E -> V_O, the second the move V_O -> V_E. */
 static void node_words(const kpo_planner* P, int32_t i, uint32_t* w_dem, uint32_t* w_pro) {
   uint32_t key[2] = {(uint32_t)P->pb.seed, (uint32_t)(P->pb.seed >> 32)};
-  uint32_t ctr[4] = {(uint32_t)P->it, (uint32_t)i, 0u, 3u};
+  uint32_t ctr[4] = {(uint32_t)P->it, (uint32_t)i >> 1, 0u, 3u};
   uint32_t w[4];
   kpo_philox4x32_10(ctr, key, w);
-  *w_dem = w[0];
-  *w_pro = w[1];
+  *w_dem = w[2 * (i & 1)];
+  *w_pro = w[2 * (i & 1) + 1];
 }
 
 /* Alg. 4.  Lines 1-3: each x in V_E moves to V_O with probability
