@@ -1,0 +1,268 @@
+/*
+ * kp.h -- C ABI of the MI355X (gfx950) Kino-PAX tree-growth library.
+ *
+ * Kino-PAX (Perrault, Ho, Lahijanian, RA-L 2025) grows one tree of trajectory
+ * segments.  Each iteration of its main loop (Alg. 1) runs three parallel
+ * subroutines: Propagate (Alg. 2), UpdateEstimates (Alg. 3, eqs. 3-5) and
+ * UpdateNodeSets (Alg. 4); the branching factor follows eq. (6).  This
+ * library runs that loop on one GPU with hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  Host pointers are read during the call and never
+ *     kept, except where stated.  Device pointers are borrowed.
+ *   - The caller allocates all device memory: one workspace buffer of
+ *     kp_workspace_bytes() bytes (256-byte aligned) per problem.  The library
+ *     allocates no device memory of its own.
+ *   - All device work is enqueued on the HIP stream given at creation
+ *     (hipStream_t passed as void*; NULL means the default stream).
+ *   - Return value < 0 is an error; kp_last_error() then holds a message.
+ *     Arguments are checked before any device work is enqueued.  No C++
+ *     exception crosses this boundary.
+ *   - A handle is not thread-safe: use one handle per host thread / stream.
+ */
+#ifndef KP_H
+#define KP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KP_ABI_VERSION 1u
+#define KP_MAX_STATE 12
+#define KP_MAX_CONTROL 4
+#define KP_MAX_OBSTACLES 2040
+
+typedef enum {
+  KP_OK = 0,
+  KP_SOLVED = 1,          /* a new tree node reached X_goal (Alg. 4, lines 4-6) */
+  KP_TIMEOUT = 2,         /* t_max or max_iters reached (Alg. 1, line 4) */
+  KP_TREE_FULL = 3,       /* eq. (6) gave lambda = 0: |T| + |V_E| > t_e */
+  KP_FRONTIER_EMPTY = 4,  /* V_E became empty */
+  KP_E_ARG = -1,          /* invalid argument (null pointer, bad size, bad field) */
+  KP_E_DEVICE = -2,       /* a HIP call failed or a kernel reported an error */
+  KP_E_WORKSPACE = -3,    /* workspace too small or misaligned */
+  KP_E_START_INVALID = -4,/* x_init outside X_valid (Problem 1 requires x_init in X_valid) */
+  KP_E_GOAL_INVALID = -5, /* X_goal not inside X_valid (Problem 1 requires it) */
+  KP_E_ORDER = -6         /* calls made out of the Alg. 1 order */
+} kp_status;
+
+enum { KP_DYN_DI6 = 0, KP_DYN_QUAD12 = 1 };   /* 6D double integrator, 12D quadcopter */
+enum { KP_INT_EULER = 0, KP_INT_RK4 = 1 };     /* explicit Euler, classic RK4 */
+
+/*
+ * Problem 1 plus the planner's hyperparameters.  All values are copied at
+ * kp_create_problem(); the obstacle array is copied too.
+ *
+ * Dynamics (eq. 1).  KP_DYN_DI6: state (px py pz vx vy vz), control (ax ay az).
+ * KP_DYN_QUAD12: state (px py pz, phi theta psi, vx vy vz, p q r), control
+ * (thrust, tau_x, tau_y, tau_z); dyn_params = (mass, gravity, Ixx, Iyy, Izz).
+ * A segment integrates `steps` steps of size `h` under one control (eq. 2).
+ *
+ * X_valid: x_lo <= x <= x_hi componentwise (closed), and every swept box of
+ * two consecutive positions, grown by `margin`, clear of every obstacle.  The
+ * first three state components are positions; x_lo[0..2], x_hi[0..2] is the
+ * workspace W.  Obstacles are closed boxes, n_obstacles x 6 floats
+ * (lo x, lo y, lo z, hi x, hi y, hi z), row-major.
+ *
+ * X_goal: the closed ball of goal_radius around goal_center (positions).
+ *
+ * Decomposition R (Sec. III-A.1): grid[0] x grid[1] x grid[2] regions over W,
+ * each split into sub^3 sub-regions (1 <= sub <= 4).
+ *
+ * node_cap is t_e (Sec. IV-A), lambda_max the cap in eq. (6); delta (eq. 3)
+ * and epsilon (eq. 5) are the constants of the region score and acceptance
+ * probability.  seed keys the counter-based random generator.  t_max_ms is
+ * Alg. 1's time budget for kp_plan; max_iters bounds the iterations too.
+ * iters_per_sync: iterations kp_plan enqueues between two reads of the
+ * device status word (0 = library default); results do not depend on it.
+ */
+typedef struct {
+  uint32_t abi_version;        /* must be KP_ABI_VERSION */
+  int32_t dynamics;            /* KP_DYN_* */
+  int32_t integrator;          /* KP_INT_* */
+  int32_t steps;               /* >= 1 */
+  float h;                     /* > 0 */
+  float dyn_params[8];
+  float u_lo[KP_MAX_CONTROL], u_hi[KP_MAX_CONTROL];
+  float x_lo[KP_MAX_STATE], x_hi[KP_MAX_STATE];
+  const float* obstacles;      /* host pointer, n_obstacles * 6 floats */
+  int32_t n_obstacles;         /* 0 .. KP_MAX_OBSTACLES */
+  float margin;                /* >= 0 */
+  float x_init[KP_MAX_STATE];
+  float goal_center[3];
+  float goal_radius;
+  int32_t grid[3];             /* regions per axis, product <= 65536 */
+  int32_t sub;                 /* 1..4 */
+  int32_t node_cap;            /* t_e, 1 .. 2^30 */
+  int32_t lambda_max;          /* 1 .. 255 */
+  double delta;                /* > 0 */
+  double epsilon;              /* in (0, 1] */
+  uint64_t seed;
+  double t_max_ms;
+  int32_t max_iters;
+  int32_t iters_per_sync;
+} kp_problem_desc;
+
+typedef struct kp_problem kp_problem;
+
+/* Result of kp_plan. */
+typedef struct {
+  int32_t status;          /* KP_SOLVED, KP_TIMEOUT, KP_TREE_FULL, KP_FRONTIER_EMPTY */
+  int32_t goal_id;         /* tree node in X_goal, or -1 */
+  int32_t iterations;      /* iterations of Alg. 1's loop executed */
+  int32_t n_nodes;         /* |T| at the end */
+  int32_t path_len;        /* nodes on the root-to-goal path (0 if none) */
+  int32_t pad;
+  double elapsed_ms;       /* wall clock of the loop, host side */
+  uint64_t lanes_total;    /* expansions attempted: sum of |V_E| * lambda */
+  uint64_t valid_total;    /* valid expansions: sum of n_valid increments */
+} kp_plan_result;
+
+/* Device counters after the last completed call (synchronises the stream). */
+typedef struct {
+  int32_t n_nodes;         /* |T| */
+  int32_t n_frontier;      /* |V_E| for the next expansion */
+  int32_t lambda;          /* eq. (6) for the next expansion */
+  int32_t iteration;       /* iterations completed */
+  int32_t goal_id;         /* -1 if none */
+  int32_t done_code;       /* 0 while running, else a kp_status > 0 */
+  int32_t n_new;           /* |V_U| of the last expansion */
+  int32_t device_error;    /* nonzero if a kernel hit an internal limit */
+  uint64_t lanes_total, valid_total, invalid_total;
+  uint64_t steps_total;    /* integration steps executed */
+  uint64_t box_tests_total;/* swept-box vs obstacle tests executed */
+} kp_iter_stats;
+
+/*
+ * Host copy of the planner state (kp_copy_tree / kp_load_tree).  The caller
+ * owns every buffer.  Node arrays are structure-of-arrays with n_nodes
+ * columns: x is [n][n_nodes] floats (n = 6 or 12), u is [m][n_nodes] floats
+ * (m = 3 or 4; the control of the edge into each node, zero for the root).
+ * cell = region * 64 + sub-region index; flag 1 = V_E, 0 = V_O; birth = the
+ * iteration that created the node (-1 for the root); sample = the expansion
+ * index of that node's creation (0 for the root).  Region arrays have
+ * R = grid[0]*grid[1]*grid[2] entries: visited has bit k set when sub-region
+ * k of the region holds a tree node; thr is P_accept * 2^32 (2^32 for P = 1).
+ */
+typedef struct {
+  int32_t n_nodes;
+  int32_t iteration;
+  float* x;
+  float* u;
+  int32_t* parent;
+  uint32_t* cell;
+  uint8_t* flag;
+  int32_t* birth;
+  uint8_t* sample;
+  uint64_t* nv;
+  uint64_t* ni;
+  uint64_t* visited;
+  uint8_t* avail;
+  uint64_t* thr;
+} kp_tree_host;
+
+/*
+ * One record per expansion lane of kp_expand, written when a trace buffer is
+ * passed (lane = frontier position * lambda + sample).  96 bytes, device
+ * memory of at least kp_trace_bytes() bytes.
+ */
+typedef struct {
+  int32_t parent;          /* tree node expanded */
+  int32_t sample;          /* 0 .. lambda-1 */
+  float u[4];              /* sampled control */
+  float x[12];             /* x': segment end, or the state at the first failing step */
+  int32_t steps;           /* integration steps taken */
+  int32_t valid;
+  uint32_t cell;           /* sub-region of x' (region * 64 + index) */
+  int32_t goal;            /* valid, accepted and in X_goal */
+  int32_t accept;          /* added to V_U */
+  int32_t new_id;          /* tree id given to the accepted sample, else -1 */
+} kp_trace_record;
+
+/* Bytes of workspace needed for `desc` (0 if desc is invalid). */
+size_t kp_workspace_bytes(const kp_problem_desc* desc);
+
+/* Bytes of trace buffer kp_expand needs for the current state. */
+size_t kp_trace_bytes(const kp_problem* h);
+
+/*
+ * Alg. 1, lines 1-3: checks the description, copies it and the obstacles,
+ * carves the workspace and initialises the tree with the root x_init in V_E
+ * and every P_accept = 1.  dev_workspace: device pointer, >= the size from
+ * kp_workspace_bytes, borrowed for the handle's lifetime.  hip_stream: a
+ * hipStream_t borrowed for the handle's lifetime.  Returns KP_E_START_INVALID
+ * / KP_E_GOAL_INVALID when Problem 1's x_init in X_valid / X_goal in X_valid
+ * fail.  On success *out receives the handle; synchronises the stream.
+ */
+kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, size_t bytes,
+                            void* hip_stream, kp_problem** out);
+
+/* Frees the handle (not the workspace).  Synchronises the stream. */
+kp_status kp_destroy_problem(kp_problem* h);
+
+/* Back to Alg. 1 line 3 with a new seed; the workspace is re-initialised. */
+kp_status kp_reset(kp_problem* h, uint64_t seed);
+
+/*
+ * Alg. 2 (Propagate) with eq. (6): frontier V_E in ascending id order,
+ * lambda, then |V_E| * lambda expansions (random control, PropagateODE,
+ * validity, sub-region, n_valid / n_invalid, acceptance); accepted samples
+ * are written after the tree's last node in (frontier position, sample)
+ * order -- V_U, not yet part of T.  Enqueue only.  dev_trace: NULL or a
+ * device buffer of kp_trace_bytes() bytes receiving one kp_trace_record per
+ * lane.
+ */
+kp_status kp_expand(kp_problem* h, void* dev_trace);
+
+/* Alg. 3 (UpdateEstimates, eqs. 3-5) over R_avail.  Enqueue only.
+ * KP_E_ORDER unless called after kp_expand. */
+kp_status kp_update_regions(kp_problem* h);
+
+/*
+ * Alg. 4 (UpdateNodeSets): V_E -> V_O with probability 1 - P_accept, V_U into
+ * T and V_E with the goal test, V_O -> V_E with probability P_accept unless a
+ * goal was found; then the next frontier and lambda.  goal_id: NULL (enqueue
+ * only) or a host int receiving the goal node id or -1 (synchronises).
+ * KP_E_ORDER unless called after kp_update_regions.
+ */
+kp_status kp_update_tree(kp_problem* h, int32_t* goal_id);
+
+/* Alg. 1's loop until a goal node, a full tree, an empty frontier or the
+ * time / iteration budget.  Synchronous. */
+kp_status kp_plan(kp_problem* h, kp_plan_result* out);
+
+/* Counters (synchronises the stream). */
+kp_status kp_get_stats(kp_problem* h, kp_iter_stats* out);
+
+/* Copy the whole state to host buffers (layout above).  Synchronous.
+ * out->n_nodes and out->iteration are outputs; every array must hold
+ * node_cap (node arrays) or R (region arrays) entries. */
+kp_status kp_copy_tree(kp_problem* h, kp_tree_host* out);
+
+/* Replace the state with a host copy (n_nodes >= 1, same layout); the next
+ * call must be kp_expand.  Synchronous. */
+kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in);
+
+/* Node ids from the root to `node` ("return trajectory x_init to x",
+ * Alg. 4 line 5).  ids: host array of cap entries; *len receives the path
+ * length.  KP_E_ARG if node is out of range or the path exceeds cap. */
+kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, int32_t* len);
+
+/* Per-kernel timing with HIP events on the handle's stream (0 = off).  While
+ * on, every kernel launch is bracketed by two events; totals accumulate until
+ * the next call with on = 1.  kp_kernel_times fills, for kernel index k
+ * (0 propagate, 1 region estimates, 2 node sets, 3 frontier), the launch
+ * count and the summed duration in milliseconds.  Synchronises. */
+kp_status kp_set_profiling(kp_problem* h, int32_t on);
+kp_status kp_kernel_times(kp_problem* h, int32_t kernel, int64_t* launches, double* total_ms);
+
+const char* kp_status_str(kp_status s);
+const char* kp_last_error(const kp_problem* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KP_H */

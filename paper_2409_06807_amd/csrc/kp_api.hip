@@ -1,0 +1,743 @@
+// Host side of the C ABI declared in include/kp.h: argument checks, workspace
+// carving, the Alg. 1 loop, state copies and per-kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kp.h"
+#include "kp_internal.h"
+
+using namespace kp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kProfKernels = 4;  // propagate, region, node sets, frontier
+constexpr int kEventPool = 512;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  size_t ctl, x, u, parent, cell, flag, birth, sample, F;
+  size_t nv, ni, visited, thr, avail, obs, st_front, st_nodes, st_prop, path;
+  size_t total;
+  int capP, tiles_node, tiles_prop;
+};
+
+int state_dim(int dyn) { return dyn == KP_DYN_DI6 ? 6 : 12; }
+int ctrl_dim(int dyn) { return dyn == KP_DYN_DI6 ? 3 : 4; }
+
+// Returns an empty string if the description is acceptable.
+std::string check_desc(const kp_problem_desc* d) {
+  if (!d) return "desc is NULL";
+  if (d->abi_version != KP_ABI_VERSION) return "abi_version mismatch";
+  if (d->dynamics != KP_DYN_DI6 && d->dynamics != KP_DYN_QUAD12) return "unknown dynamics";
+  if (d->integrator != KP_INT_EULER && d->integrator != KP_INT_RK4) return "unknown integrator";
+  if (d->steps < 1 || d->steps > 4096) return "steps must be in [1, 4096]";
+  if (!(d->h > 0.0f) || !std::isfinite(d->h)) return "h must be positive";
+  if (d->n_obstacles < 0 || d->n_obstacles > KP_MAX_OBSTACLES) return "n_obstacles out of range";
+  if (d->n_obstacles > 0 && !d->obstacles) return "obstacles is NULL";
+  if (!(d->margin >= 0.0f)) return "margin must be >= 0";
+  for (int a = 0; a < 3; ++a) {
+    if (d->grid[a] < 1) return "grid entries must be >= 1";
+    if (!(d->x_hi[a] > d->x_lo[a])) return "workspace bounds must satisfy x_lo < x_hi";
+  }
+  if ((long long)d->grid[0] * d->grid[1] * d->grid[2] > 65536) return "more than 65536 regions";
+  if ((long long)d->grid[0] * d->sub > 1 << 20 || (long long)d->grid[1] * d->sub > 1 << 20 ||
+      (long long)d->grid[2] * d->sub > 1 << 20)
+    return "too many cells per axis";
+  if (d->sub < 1 || d->sub > 4) return "sub must be in [1, 4]";
+  if (d->node_cap < 1 || d->node_cap > (1 << 30)) return "node_cap must be in [1, 2^30]";
+  if (d->lambda_max < 1 || d->lambda_max > 255) return "lambda_max must be in [1, 255]";
+  if (!(d->delta > 0.0)) return "delta must be > 0";
+  if (!(d->epsilon > 0.0) || d->epsilon > 1.0) return "epsilon must be in (0, 1]";
+  const int n = state_dim(d->dynamics), m = ctrl_dim(d->dynamics);
+  for (int j = 0; j < m; ++j)
+    if (!(d->u_hi[j] >= d->u_lo[j])) return "control box must satisfy u_lo <= u_hi";
+  for (int i = 0; i < n; ++i)
+    if (!(d->x_hi[i] >= d->x_lo[i])) return "state box must satisfy x_lo <= x_hi";
+  if (!(d->goal_radius >= 0.0f)) return "goal_radius must be >= 0";
+  if (d->max_iters < 0) return "max_iters must be >= 0";
+  if (d->iters_per_sync < 0 || d->iters_per_sync > 4096) return "iters_per_sync out of range";
+  return std::string();
+}
+
+Layout make_layout(const kp_problem_desc* d) {
+  Layout L{};
+  const int n = state_dim(d->dynamics), m = ctrl_dim(d->dynamics);
+  const size_t R = (size_t)d->grid[0] * d->grid[1] * d->grid[2];
+  const size_t capP = align_up((size_t)d->node_cap + 1, kNodeTile);
+  L.capP = (int)capP;
+  L.tiles_node = (int)(capP / kNodeTile + 2);
+  L.tiles_prop = (int)((size_t)d->node_cap / kPropBlock + 2);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, kAlign);
+    return o;
+  };
+  L.ctl = take(sizeof(Ctl));
+  L.x = take(capP * n * 4);
+  L.u = take(capP * m * 4);
+  L.parent = take(capP * 4);
+  L.cell = take(capP * 4);
+  L.flag = take(capP);
+  L.birth = take(capP * 4);
+  L.sample = take(capP);
+  L.F = take(capP * 4);
+  L.nv = take(R * 8);
+  L.ni = take(R * 8);
+  L.visited = take(R * 8);
+  L.thr = take(R * 8);
+  L.avail = take(R);
+  L.obs = take((size_t)(d->n_obstacles > 0 ? d->n_obstacles : 1) * 6 * 4);
+  L.st_front = take((size_t)L.tiles_node * 8);
+  L.st_nodes = take((size_t)L.tiles_node * 8);
+  L.st_prop = take((size_t)L.tiles_prop * 8);
+  L.path = take((size_t)(kMaxPath + 1) * 4);
+  L.total = off;
+  return L;
+}
+
+// Distance-squared from a point to a closed box, in double.
+double point_box_d2(const double* c, const double* lo, const double* hi) {
+  double d2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double t = 0.0;
+    if (c[a] < lo[a]) t = lo[a] - c[a];
+    else if (c[a] > hi[a]) t = c[a] - hi[a];
+    d2 += t * t;
+  }
+  return d2;
+}
+
+}  // namespace
+
+struct kp_problem {
+  kp_problem_desc desc;
+  std::vector<float> obs;  // row-major copy
+  Params prm;
+  Dev dev;
+  Layout L;
+  hipStream_t stream;
+  int n, m, R;
+  int cu_count;
+  int grid_prop_max;
+  int grid_node_max;
+  int stage;  // 0: next is kp_expand; 1: next is kp_update_regions; 2: next is kp_update_tree
+  Ctl* hctl;  // pinned host mirror of the control block
+  std::string err;
+  // profiling
+  bool prof;
+  hipEvent_t ev[kEventPool][2];
+  int ev_kernel[kEventPool];
+  int ev_used;
+  long long prof_launches[kProfKernels];
+  double prof_ms[kProfKernels];
+  bool events_made;
+};
+
+namespace {
+
+kp_status fail(kp_problem* h, kp_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+kp_status hip_fail(kp_problem* h, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, KP_E_DEVICE, msg);
+}
+
+void fill_params(kp_problem* h) {
+  const kp_problem_desc& d = h->desc;
+  Params& p = h->prm;
+  std::memset(&p, 0, sizeof(p));
+  p.n = h->n;
+  p.m = h->m;
+  p.K = d.steps;
+  p.cap = d.node_cap;
+  p.lambda_max = d.lambda_max;
+  p.n_obs = d.n_obstacles;
+  p.S = d.sub;
+  p.R = h->R;
+  for (int a = 0; a < 3; ++a) {
+    p.G[a] = d.grid[a];
+    p.na[a] = d.grid[a] * d.sub;
+    p.w_lo[a] = d.x_lo[a];
+    p.inv_w[a] = (float)((double)p.na[a] / ((double)d.x_hi[a] - (double)d.x_lo[a]));
+    p.goal_c[a] = d.goal_center[a];
+  }
+  p.h = d.h;
+  p.margin = d.margin;
+  p.goal_r2 = d.goal_radius * d.goal_radius;
+  for (int i = 0; i < 12; ++i) {
+    p.x_lo[i] = d.x_lo[i];
+    p.x_hi[i] = d.x_hi[i];
+  }
+  for (int j = 0; j < 4; ++j) {
+    p.u_lo[j] = d.u_lo[j];
+    p.u_hi[j] = d.u_hi[j];
+  }
+  p.mass = d.dyn_params[0];
+  p.grav = d.dyn_params[1];
+  p.Ixx = d.dyn_params[2];
+  p.Iyy = d.dyn_params[3];
+  p.Izz = d.dyn_params[4];
+  p.inv_m = 1.0f / p.mass;
+  p.inv_Ixx = 1.0f / p.Ixx;
+  p.inv_Iyy = 1.0f / p.Iyy;
+  p.inv_Izz = 1.0f / p.Izz;
+  p.dIyz = p.Iyy - p.Izz;
+  p.dIzx = p.Izz - p.Ixx;
+  p.dIxy = p.Ixx - p.Iyy;
+  p.key0 = (uint32_t)d.seed;
+  p.key1 = (uint32_t)(d.seed >> 32);
+  p.delta = d.delta;
+  p.eps = d.epsilon;
+  // Culling radius: a step is collision-checked only when it starts from a
+  // state inside the velocity bounds, so each step moves a position by at
+  // most h * (v_max + h * a_max) per axis (Euler: h * v_max).
+  const int vo = (d.dynamics == KP_DYN_DI6) ? 3 : 6;
+  double vmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    vmax = std::fmax(vmax, std::fabs((double)d.x_lo[vo + a]));
+    vmax = std::fmax(vmax, std::fabs((double)d.x_hi[vo + a]));
+  }
+  double amax = 0.0;
+  if (d.dynamics == KP_DYN_DI6) {
+    for (int j = 0; j < 3; ++j)
+      amax = std::fmax(amax, std::fmax(std::fabs((double)d.u_lo[j]), std::fabs((double)d.u_hi[j])));
+  } else {
+    const double tmax = std::fmax(std::fabs((double)d.u_lo[0]), std::fabs((double)d.u_hi[0]));
+    amax = tmax / std::fabs((double)d.dyn_params[0]) + std::fabs((double)d.dyn_params[1]);
+  }
+  const double hh = d.h;
+  const double per_step = (d.integrator == KP_INT_EULER) ? hh * vmax : hh * (vmax + hh * amax);
+  double rc = d.steps * per_step * (1.0 + 1e-4) + 1e-3;
+  if (!std::isfinite(rc)) rc = 3.0e38;
+  p.rc = (float)rc;
+}
+
+void carve(kp_problem* h, void* ws) {
+  char* b = static_cast<char*>(ws);
+  const Layout& L = h->L;
+  Dev& v = h->dev;
+  v.ctl = reinterpret_cast<Ctl*>(b + L.ctl);
+  v.x = reinterpret_cast<float*>(b + L.x);
+  v.u = reinterpret_cast<float*>(b + L.u);
+  v.parent = reinterpret_cast<int32_t*>(b + L.parent);
+  v.cell = reinterpret_cast<uint32_t*>(b + L.cell);
+  v.flag = reinterpret_cast<uint8_t*>(b + L.flag);
+  v.birth = reinterpret_cast<int32_t*>(b + L.birth);
+  v.sample = reinterpret_cast<uint8_t*>(b + L.sample);
+  v.F = reinterpret_cast<int32_t*>(b + L.F);
+  v.nv = reinterpret_cast<unsigned long long*>(b + L.nv);
+  v.ni = reinterpret_cast<unsigned long long*>(b + L.ni);
+  v.visited = reinterpret_cast<unsigned long long*>(b + L.visited);
+  v.thr = reinterpret_cast<unsigned long long*>(b + L.thr);
+  v.avail = reinterpret_cast<uint8_t*>(b + L.avail);
+  v.obs = reinterpret_cast<float*>(b + L.obs);
+  v.st_front = reinterpret_cast<unsigned long long*>(b + L.st_front);
+  v.st_nodes = reinterpret_cast<unsigned long long*>(b + L.st_nodes);
+  v.st_prop = reinterpret_cast<unsigned long long*>(b + L.st_prop);
+  v.path = reinterpret_cast<int32_t*>(b + L.path);
+  v.capP = L.capP;
+  v.tiles_node = L.tiles_node;
+  v.tiles_prop = L.tiles_prop;
+}
+
+kp_status sync_ctl(kp_problem* h) {
+  hipError_t e = hipMemcpyAsync(h->hctl, h->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "status copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+  if (h->hctl->err) return fail(h, KP_E_DEVICE, "a kernel hit an internal wait limit");
+  return KP_OK;
+}
+
+// profiling: bracket a launch with a pair of events
+int prof_begin(kp_problem* h, int kernel) {
+  if (!h->prof || h->ev_used >= kEventPool) return -1;
+  const int k = h->ev_used++;
+  h->ev_kernel[k] = kernel;
+  (void)hipEventRecord(h->ev[k][0], h->stream);
+  return k;
+}
+void prof_end(kp_problem* h, int k) {
+  if (k >= 0) (void)hipEventRecord(h->ev[k][1], h->stream);
+}
+void prof_collect(kp_problem* h) {
+  if (!h->prof || h->ev_used == 0) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (int k = 0; k < h->ev_used; ++k) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->ev[k][0], h->ev[k][1]) == hipSuccess) {
+      h->prof_ms[h->ev_kernel[k]] += ms;
+      h->prof_launches[h->ev_kernel[k]] += 1;
+    }
+  }
+  h->ev_used = 0;
+}
+
+kp_status do_frontier(kp_problem* h) {
+  const int tiles = (h->L.capP + kNodeTile - 1) / kNodeTile;
+  int grid = tiles < h->grid_node_max ? tiles : h->grid_node_max;
+  if (grid < 1) grid = 1;
+  const int pk = prof_begin(h, 3);
+  hipError_t e = launch_frontier(h->prm, h->dev, grid, h->stream);
+  prof_end(h, pk);
+  if (e != hipSuccess) return hip_fail(h, e, "frontier launch");
+  return KP_OK;
+}
+
+// grids from the last host-known sizes (exact after a status read; upper
+// bounds otherwise -- the kernels read the true sizes from device memory)
+kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub) {
+  long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
+  int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
+  if (grid < 1) grid = 1;
+  const int pk = prof_begin(h, 0);
+  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm, h->dev, trace,
+                                  grid, h->stream);
+  prof_end(h, pk);
+  if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
+  return KP_OK;
+}
+
+kp_status do_region(kp_problem* h) {
+  const int pk = prof_begin(h, 1);
+  hipError_t e = launch_region(h->prm, h->dev, h->stream);
+  prof_end(h, pk);
+  if (e != hipSuccess) return hip_fail(h, e, "region launch");
+  return KP_OK;
+}
+
+kp_status do_nodesets(kp_problem* h, long long nodes_ub) {
+  long long tiles = (nodes_ub + kNodeTile - 1) / kNodeTile;
+  int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
+  if (grid < 1) grid = 1;
+  const int pk = prof_begin(h, 2);
+  hipError_t e = launch_nodesets(h->prm, h->dev, grid, h->stream);
+  prof_end(h, pk);
+  if (e != hipSuccess) return hip_fail(h, e, "node sets launch");
+  return KP_OK;
+}
+
+kp_status init_state(kp_problem* h) {
+  hipError_t e = launch_zero(h->prm, h->dev, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "zero launch");
+  Vec12 xi;
+  for (int k = 0; k < 12; ++k) xi.v[k] = h->desc.x_init[k];
+  e = launch_root(h->prm, h->dev, xi, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "root launch");
+  kp_status st = do_frontier(h);
+  if (st != KP_OK) return st;
+  h->stage = 0;
+  return sync_ctl(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kp_workspace_bytes(const kp_problem_desc* desc) {
+  if (!check_desc(desc).empty()) return 0;
+  return make_layout(desc).total;
+}
+
+size_t kp_trace_bytes(const kp_problem* h) {
+  if (!h) return 0;
+  return (size_t)h->desc.node_cap * sizeof(TraceRec);
+}
+
+kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, size_t bytes,
+                            void* hip_stream, kp_problem** out) {
+  if (!out) return KP_E_ARG;
+  *out = nullptr;
+  const std::string why = check_desc(desc);
+  if (!why.empty()) return KP_E_ARG;
+  if (!dev_workspace) return KP_E_ARG;
+  const Layout L = make_layout(desc);
+  if (bytes < L.total || (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0)
+    return KP_E_WORKSPACE;
+  // Problem 1 requires x_init in X_valid and X_goal inside X_valid.
+  const int n = state_dim(desc->dynamics);
+  for (int i = 0; i < n; ++i) {
+    const float v = desc->x_init[i];
+    if (!std::isfinite(v) || v < desc->x_lo[i] || v > desc->x_hi[i]) return KP_E_START_INVALID;
+  }
+  double xi[3] = {desc->x_init[0], desc->x_init[1], desc->x_init[2]};
+  double gc[3] = {desc->goal_center[0], desc->goal_center[1], desc->goal_center[2]};
+  const double mg = desc->margin;
+  for (int k = 0; k < desc->n_obstacles; ++k) {
+    const float* o = desc->obstacles + 6 * k;
+    double lo[3] = {o[0] - mg, o[1] - mg, o[2] - mg};
+    double hi[3] = {o[3] + mg, o[4] + mg, o[5] + mg};
+    if (point_box_d2(xi, lo, hi) == 0.0) return KP_E_START_INVALID;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (gc[a] - desc->goal_radius < desc->x_lo[a] || gc[a] + desc->goal_radius > desc->x_hi[a])
+      return KP_E_GOAL_INVALID;
+  }
+  for (int k = 0; k < desc->n_obstacles; ++k) {
+    const float* o = desc->obstacles + 6 * k;
+    double lo[3] = {o[0], o[1], o[2]};
+    double hi[3] = {o[3], o[4], o[5]};
+    const double r = (double)desc->goal_radius + mg;
+    if (point_box_d2(gc, lo, hi) <= r * r) return KP_E_GOAL_INVALID;
+  }
+
+  kp_problem* h = new (std::nothrow) kp_problem();
+  if (!h) return KP_E_ARG;
+  h->desc = *desc;
+  h->desc.obstacles = nullptr;
+  h->obs.assign(desc->obstacles, desc->obstacles + (size_t)6 * desc->n_obstacles);
+  h->n = n;
+  h->m = ctrl_dim(desc->dynamics);
+  h->R = desc->grid[0] * desc->grid[1] * desc->grid[2];
+  h->L = L;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->prof = false;
+  h->ev_used = 0;
+  h->events_made = false;
+  for (int k = 0; k < kProfKernels; ++k) {
+    h->prof_launches[k] = 0;
+    h->prof_ms[k] = 0.0;
+  }
+  fill_params(h);
+  carve(h, dev_workspace);
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    delete h;
+    return KP_E_DEVICE;
+  }
+  int bp = 1, bn = 1;
+  occupancy_propagate(desc->dynamics, desc->integrator, desc->n_obstacles, &bp);
+  occupancy_nodes(&bn);
+  h->grid_prop_max = bp * h->cu_count;
+  h->grid_node_max = bn * h->cu_count;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->hctl), sizeof(Ctl), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete h;
+    return KP_E_DEVICE;
+  }
+  std::memset(h->hctl, 0, sizeof(Ctl));
+  // obstacles as SoA: lo x[], lo y[], lo z[], hi x[], hi y[], hi z[]
+  std::vector<float> soa((size_t)6 * (desc->n_obstacles > 0 ? desc->n_obstacles : 1), 0.0f);
+  for (int k = 0; k < desc->n_obstacles; ++k)
+    for (int c = 0; c < 6; ++c) soa[(size_t)c * desc->n_obstacles + k] = h->obs[(size_t)6 * k + c];
+  e = hipMemcpyAsync(h->dev.obs, soa.data(), soa.size() * sizeof(float), hipMemcpyHostToDevice,
+                     h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->dev.ctl, 0, sizeof(Ctl), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipHostFree(h->hctl);
+    delete h;
+    return KP_E_DEVICE;
+  }
+  kp_status st = init_state(h);
+  if (st != KP_OK) {
+    (void)hipHostFree(h->hctl);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return KP_OK;
+}
+
+kp_status kp_destroy_problem(kp_problem* h) {
+  if (!h) return KP_E_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->events_made) {
+    for (int k = 0; k < kEventPool; ++k) {
+      (void)hipEventDestroy(h->ev[k][0]);
+      (void)hipEventDestroy(h->ev[k][1]);
+    }
+  }
+  (void)hipHostFree(h->hctl);
+  delete h;
+  return KP_OK;
+}
+
+kp_status kp_reset(kp_problem* h, uint64_t seed) {
+  if (!h) return KP_E_ARG;
+  h->desc.seed = seed;
+  h->prm.key0 = (uint32_t)seed;
+  h->prm.key1 = (uint32_t)(seed >> 32);
+  return init_state(h);
+}
+
+kp_status kp_expand(kp_problem* h, void* dev_trace) {
+  if (!h) return KP_E_ARG;
+  if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_expand must follow kp_update_tree");
+  const long long ub = (long long)h->desc.node_cap - h->hctl->N;
+  kp_status st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1);
+  if (st != KP_OK) return st;
+  h->stage = 1;
+  return KP_OK;
+}
+
+kp_status kp_update_regions(kp_problem* h) {
+  if (!h) return KP_E_ARG;
+  if (h->stage != 1) return fail(h, KP_E_ORDER, "kp_update_regions must follow kp_expand");
+  kp_status st = do_region(h);
+  if (st != KP_OK) return st;
+  h->stage = 2;
+  return KP_OK;
+}
+
+kp_status kp_update_tree(kp_problem* h, int32_t* goal_id) {
+  if (!h) return KP_E_ARG;
+  if (h->stage != 2) return fail(h, KP_E_ORDER, "kp_update_tree must follow kp_update_regions");
+  kp_status st = do_nodesets(h, h->desc.node_cap);
+  if (st != KP_OK) return st;
+  h->stage = 0;
+  if (goal_id) {
+    st = sync_ctl(h);
+    if (st != KP_OK) return st;
+    *goal_id = (h->hctl->goal_id == kNoGoal) ? -1 : h->hctl->goal_id;
+  }
+  return KP_OK;
+}
+
+kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
+  if (!h || !out) return KP_E_ARG;
+  if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_plan must start after a complete iteration");
+  std::memset(out, 0, sizeof(*out));
+  const auto t0 = std::chrono::steady_clock::now();
+  kp_status st = sync_ctl(h);
+  if (st != KP_OK) return st;
+  const uint32_t it0 = h->hctl->iters_done;
+  const int per_sync = h->desc.iters_per_sync > 0 ? h->desc.iters_per_sync : 1;
+  const long long cap = h->desc.node_cap;
+  int status = KP_TIMEOUT;
+  for (;;) {
+    const Ctl& c = *h->hctl;
+    if (c.done) {
+      status = c.done;
+      break;
+    }
+    const long long done_iters = (long long)c.iters_done - it0;
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (done_iters >= h->desc.max_iters || ms >= h->desc.t_max_ms) break;
+    long long batch = per_sync;
+    if (batch > h->desc.max_iters - done_iters) batch = h->desc.max_iters - done_iters;
+    for (long long b = 0; b < batch; ++b) {
+      // exact sizes for the first iteration of a batch, bounds after it
+      const long long lanes_ub = (b == 0) ? c.lanes : cap - c.N;
+      const long long nodes_ub = (b == 0) ? (long long)c.N + c.lanes : cap;
+      if ((st = do_propagate(h, nullptr, lanes_ub)) != KP_OK) return st;
+      if ((st = do_region(h)) != KP_OK) return st;
+      if ((st = do_nodesets(h, nodes_ub)) != KP_OK) return st;
+    }
+    if ((st = sync_ctl(h)) != KP_OK) return st;
+    prof_collect(h);
+  }
+  const Ctl& c = *h->hctl;
+  out->elapsed_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  out->status = status;
+  out->goal_id = (c.goal_id == kNoGoal) ? -1 : c.goal_id;
+  out->iterations = (int32_t)(c.iters_done - it0);
+  out->n_nodes = c.N;
+  out->lanes_total = c.lanes_total;
+  out->valid_total = c.valid_total;
+  out->path_len = 0;
+  if (out->goal_id >= 0) {
+    int32_t len = 0;
+    if (kp_get_path(h, out->goal_id, nullptr, 0, &len) == KP_OK) out->path_len = len;
+  }
+  return (kp_status)status;
+}
+
+kp_status kp_get_stats(kp_problem* h, kp_iter_stats* out) {
+  if (!h || !out) return KP_E_ARG;
+  hipError_t e = hipMemcpyAsync(h->hctl, h->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stats copy");
+  const Ctl& c = *h->hctl;
+  out->n_nodes = c.N;
+  out->n_frontier = c.nF;
+  out->lambda = c.lambda;
+  out->iteration = c.it;
+  out->goal_id = (c.goal_id == kNoGoal) ? -1 : c.goal_id;
+  out->done_code = c.done;
+  out->n_new = c.nU;
+  out->device_error = (int32_t)c.err;
+  out->lanes_total = c.lanes_total;
+  out->valid_total = c.valid_total;
+  out->invalid_total = c.invalid_total;
+  out->steps_total = c.steps_total;
+  out->box_tests_total = c.box_total;
+  return KP_OK;
+}
+
+kp_status kp_copy_tree(kp_problem* h, kp_tree_host* o) {
+  if (!h || !o || !o->x || !o->u || !o->parent || !o->cell || !o->flag || !o->birth ||
+      !o->sample || !o->nv || !o->ni || !o->visited || !o->avail || !o->thr)
+    return fail(h, KP_E_ARG, "kp_copy_tree: null buffer");
+  kp_status st = sync_ctl(h);
+  if (st != KP_OK) return st;
+  // after kp_expand the accepted samples (V_U) already sit after the tree
+  const int32_t N = h->hctl->N + (h->stage == 0 ? 0 : h->hctl->nU);
+  o->n_nodes = N;
+  o->iteration = h->hctl->it;
+  const size_t pitch = (size_t)h->L.capP * 4;
+  hipError_t e = hipSuccess;
+  if (N > 0) {
+    e = hipMemcpy2DAsync(o->x, (size_t)N * 4, h->dev.x, pitch, (size_t)N * 4, h->n,
+                         hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(o->u, (size_t)N * 4, h->dev.u, pitch, (size_t)N * 4, h->m,
+                           hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(o->parent, h->dev.parent, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(o->cell, h->dev.cell, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(o->flag, h->dev.flag, (size_t)N, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(o->birth, h->dev.birth, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(o->sample, h->dev.sample, (size_t)N, hipMemcpyDeviceToHost, h->stream);
+  }
+  const size_t R = (size_t)h->R;
+  if (e == hipSuccess) e = hipMemcpyAsync(o->nv, h->dev.nv, R * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(o->ni, h->dev.ni, R * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o->visited, h->dev.visited, R * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(o->avail, h->dev.avail, R, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(o->thr, h->dev.thr, R * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "tree copy");
+  return KP_OK;
+}
+
+kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in) {
+  if (!h || !in || !in->x || !in->u || !in->parent || !in->cell || !in->flag || !in->birth ||
+      !in->sample || !in->nv || !in->ni || !in->visited || !in->avail || !in->thr)
+    return fail(h, KP_E_ARG, "kp_load_tree: null buffer");
+  const int32_t N = in->n_nodes;
+  if (N < 1 || N > h->desc.node_cap || in->iteration < 0)
+    return fail(h, KP_E_ARG, "kp_load_tree: n_nodes out of range");
+  for (int32_t i = 0; i < N; ++i) {
+    if (in->parent[i] >= i || (i > 0 && in->parent[i] < 0) || (i == 0 && in->parent[0] != -1))
+      return fail(h, KP_E_ARG, "kp_load_tree: parent links must point to smaller ids");
+    if ((in->cell[i] >> 6) >= (uint32_t)h->R)
+      return fail(h, KP_E_ARG, "kp_load_tree: cell out of range");
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  const size_t pitch = (size_t)h->L.capP * 4;
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(h->dev.x, pitch, in->x, (size_t)N * 4, (size_t)N * 4, h->n,
+                         hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(h->dev.u, pitch, in->u, (size_t)N * 4, (size_t)N * 4, h->m,
+                         hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev.parent, in->parent, (size_t)N * 4, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev.cell, in->cell, (size_t)N * 4, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev.flag, in->flag, (size_t)N, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev.birth, in->birth, (size_t)N * 4, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev.sample, in->sample, (size_t)N, hipMemcpyHostToDevice, h->stream);
+  const size_t R = (size_t)h->R;
+  if (e == hipSuccess) e = hipMemcpyAsync(h->dev.nv, in->nv, R * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->dev.ni, in->ni, R * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev.visited, in->visited, R * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->dev.avail, in->avail, R, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->dev.thr, in->thr, R * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "tree load");
+  e = launch_set_ctl(h->dev, N, in->iteration, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "control load");
+  kp_status st = do_frontier(h);
+  if (st != KP_OK) return st;
+  h->stage = 0;
+  return sync_ctl(h);
+}
+
+kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, int32_t* len) {
+  if (!h || !len) return KP_E_ARG;
+  kp_status st = sync_ctl(h);
+  if (st != KP_OK) return st;
+  if (node < 0 || node >= h->hctl->N) return fail(h, KP_E_ARG, "kp_get_path: node out of range");
+  hipError_t e = launch_path(h->dev, node, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "path launch");
+  int32_t n = 0;
+  e = hipMemcpyAsync(&n, h->dev.path, 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "path length copy");
+  *len = n;
+  if (n > kMaxPath) return fail(h, KP_E_ARG, "kp_get_path: path longer than the path buffer");
+  if (!ids) return KP_OK;
+  if (n > cap) return fail(h, KP_E_ARG, "kp_get_path: ids buffer too small");
+  e = hipMemcpyAsync(ids, h->dev.path + 1, (size_t)n * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "path copy");
+  return KP_OK;
+}
+
+kp_status kp_set_profiling(kp_problem* h, int32_t on) {
+  if (!h) return KP_E_ARG;
+  prof_collect(h);
+  if (on && !h->events_made) {
+    for (int k = 0; k < kEventPool; ++k) {
+      if (hipEventCreate(&h->ev[k][0]) != hipSuccess || hipEventCreate(&h->ev[k][1]) != hipSuccess)
+        return fail(h, KP_E_DEVICE, "event creation failed");
+    }
+    h->events_made = true;
+  }
+  if (on) {
+    for (int k = 0; k < kProfKernels; ++k) {
+      h->prof_launches[k] = 0;
+      h->prof_ms[k] = 0.0;
+    }
+  }
+  h->prof = on != 0;
+  return KP_OK;
+}
+
+kp_status kp_kernel_times(kp_problem* h, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!h || !launches || !total_ms || kernel < 0 || kernel >= kProfKernels) return KP_E_ARG;
+  prof_collect(h);
+  *launches = h->prof_launches[kernel];
+  *total_ms = h->prof_ms[kernel];
+  return KP_OK;
+}
+
+const char* kp_status_str(kp_status s) {
+  switch (s) {
+    case KP_OK: return "ok";
+    case KP_SOLVED: return "solved";
+    case KP_TIMEOUT: return "timeout";
+    case KP_TREE_FULL: return "tree full";
+    case KP_FRONTIER_EMPTY: return "frontier empty";
+    case KP_E_ARG: return "invalid argument";
+    case KP_E_DEVICE: return "device error";
+    case KP_E_WORKSPACE: return "workspace too small or misaligned";
+    case KP_E_START_INVALID: return "x_init is not a valid state";
+    case KP_E_GOAL_INVALID: return "goal region is not inside the valid set";
+    case KP_E_ORDER: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* kp_last_error(const kp_problem* h) { return h ? h->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal definitions shared by the kernels (kp_kernels.hip) and the host
+// library (kp_api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kp {
+
+constexpr int kPropBlock = 256;      // lanes per propagate tile (4 waves)
+constexpr int kNodeBlock = 256;      // threads per node-pass block
+constexpr int kNodeTile = 1024;      // nodes per node-pass tile (4 per thread)
+constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
+constexpr int kMaxPath = 65536;      // longest path kp_get_path can return
+constexpr int kDoneNone = 0;
+constexpr int32_t kNoGoal = 0x7fffffff;
+
+// Device control block: sizes and counters of the running iteration.  Written
+// only by single threads (finalisers) or by atomics, read at block start.
+struct alignas(256) Ctl {
+  int32_t N;          // |T|
+  int32_t nF;         // |V_E| for the next expansion
+  int32_t lambda;     // eq. (6)
+  int32_t lanes;      // nF * lambda
+  int32_t nU;         // |V_U| of the last expansion
+  int32_t it;         // iteration number (Philox counter word 0)
+  int32_t goal_id;    // smallest new node id in X_goal, kNoGoal if none
+  int32_t done;       // 0 running, else KP_SOLVED / KP_TREE_FULL / KP_FRONTIER_EMPTY
+  uint32_t epoch;     // tags look-back status words; bumped once per iteration
+  uint32_t tk_front, tk_prop, tk_nodes;   // tile tickets
+  uint32_t bd_front, bd_prop, bd_nodes;   // blocks finished (last-block finalisation)
+  uint32_t err;       // nonzero: a look-back wait hit its spin limit
+  uint32_t iters_done;
+  uint32_t pad0;
+  unsigned long long lanes_total, valid_total, invalid_total, steps_total, box_total;
+};
+
+// Problem constants, passed by value to every kernel.
+struct Params {
+  int32_t n, m, K, cap;
+  int32_t lambda_max, n_obs, S, R;
+  int32_t G[3];
+  int32_t na[3];        // fine cells per axis = G * S
+  float h, margin, goal_r2, rc;
+  float goal_c[3];
+  float w_lo[3];        // workspace lower corner
+  float inv_w[3];       // fine cells per unit length
+  float x_lo[12], x_hi[12];
+  float u_lo[4], u_hi[4];
+  float mass, grav, Ixx, Iyy, Izz;
+  float inv_m, inv_Ixx, inv_Iyy, inv_Izz;
+  float dIyz, dIzx, dIxy;   // Iyy - Izz, Izz - Ixx, Ixx - Iyy
+  uint32_t key0, key1;
+  double delta, eps;
+};
+
+// Device pointers carved from the caller's workspace.
+struct Dev {
+  Ctl* ctl;
+  float* x;            // [n][capP]
+  float* u;            // [m][capP]
+  int32_t* parent;     // [capP]
+  uint32_t* cell;      // [capP]
+  uint8_t* flag;       // [capP]  1 = V_E
+  int32_t* birth;      // [capP]
+  uint8_t* sample;     // [capP]
+  int32_t* F;          // [capP] frontier list
+  unsigned long long* nv;       // [R]
+  unsigned long long* ni;       // [R]
+  unsigned long long* visited;  // [R]
+  unsigned long long* thr;      // [R]
+  uint8_t* avail;      // [R]
+  float* obs;          // [6][n_obs] SoA
+  unsigned long long* st_front;  // look-back status, one word per tile
+  unsigned long long* st_prop;
+  unsigned long long* st_nodes;
+  int32_t* path;       // [kMaxPath + 1]
+  int32_t capP;        // padded node capacity (multiple of kNodeTile)
+  int32_t tiles_node;  // entries of st_front / st_nodes
+  int32_t tiles_prop;  // entries of st_prop
+  int32_t pad;
+};
+
+struct TraceRec {
+  int32_t parent, sample;
+  float u[4];
+  float x[12];
+  int32_t steps, valid;
+  uint32_t cell;
+  int32_t goal, accept, new_id;
+};
+static_assert(sizeof(TraceRec) == 96, "trace record layout");
+
+// Launchers (kp_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_zero(const Params& p, const Dev& d, hipStream_t s);
+struct Vec12 { float v[12]; };
+hipError_t launch_root(const Params& p, const Dev& d, Vec12 x_init, hipStream_t s);
+hipError_t launch_frontier(const Params& p, const Dev& d, int grid, hipStream_t s);
+hipError_t launch_propagate(int dyn, int integ, const Params& p, const Dev& d, TraceRec* trace,
+                            int grid, hipStream_t s);
+hipError_t launch_region(const Params& p, const Dev& d, hipStream_t s);
+hipError_t launch_nodesets(const Params& p, const Dev& d, int grid, hipStream_t s);
+hipError_t launch_path(const Dev& d, int32_t node, hipStream_t s);
+hipError_t launch_set_ctl(const Dev& d, int32_t N, int32_t it, hipStream_t s);
+int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu);
+int occupancy_nodes(int* blocks_per_cu);
+size_t propagate_lds_bytes(int n_obs);
+
+}  // namespace kp

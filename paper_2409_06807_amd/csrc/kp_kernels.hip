@@ -1,0 +1,895 @@
+// Kino-PAX iteration kernels for gfx950 (CDNA4, wave64).
+//
+// One iteration of the main loop (Alg. 1) is three launches on one stream:
+//   k_propagate  Alg. 2 + the branching factor of eq. (6): one lane per
+//                (frontier node, sample); Philox controls; Euler / RK4
+//                segment integration with per-step validity (state box +
+//                swept box against LDS-staged obstacles, culled per wave);
+//                sub-region map; wave-aggregated n_valid / n_invalid atomics;
+//                acceptance; stable compaction of accepted samples (ballot +
+//                wave scan + decoupled look-back across tiles) straight into
+//                the tree tail.
+//   k_region     Alg. 3: FreeVol, Cov, Score (eqs. 3-4) and P_accept (eq. 5)
+//                for R_avail in one workgroup; the score sum is an exact
+//                integer sum, so the result is independent of thread order.
+//   k_nodesets   Alg. 4: demote / admit (visited, R_avail, goal) / promote in
+//                one pass over the tree, fused with the frontier compaction
+//                for the next iteration; the last block applies eq. (6).
+// All kernels are persistent: blocks take tiles from an atomic ticket, so a
+// grid sized from occupancy covers any |V_E| * lambda or |T| read from device
+// memory, and the host never needs these sizes to launch.
+#include "kp_internal.h"
+
+#include "kp.h"
+
+namespace kp {
+
+// ---------------------------------------------------------------------------
+// wave / block helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long lanes_below() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Exclusive prefix of small per-lane counts (0..7) across the wave from three
+// ballots of the count's bit planes.
+__device__ __forceinline__ uint32_t wave_excl_small(uint32_t c, uint32_t* total) {
+  const unsigned long long b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
+  const unsigned long long lo = lanes_below();
+  *total = __popcll(b0) + 2u * __popcll(b1) + 4u * __popcll(b2);
+  return __popcll(b0 & lo) + 2u * __popcll(b1 & lo) + 4u * __popcll(b2 & lo);
+}
+
+// Decoupled look-back over per-tile status words: (30-bit epoch tag | 2-bit
+// flag | 32-bit value); flag 1 = tile aggregate, 2 = inclusive prefix.  A tile
+// only waits for tiles with smaller tickets, all held by running blocks, so
+// the wait always ends; the spin bound only guards against a broken invariant.
+__device__ uint32_t lookback_prefix(unsigned long long* st, uint32_t tile, uint32_t agg,
+                                    uint32_t epoch, uint32_t* err) {
+  const unsigned long long tag = (unsigned long long)(epoch & 0x3fffffffu) << 34;
+  if (tile == 0) {
+    __hip_atomic_store(&st[0], tag | (2ull << 32) | agg, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return 0u;
+  }
+  __hip_atomic_store(&st[tile], tag | (1ull << 32) | agg, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t excl = 0;
+  int32_t j = (int32_t)tile - 1;
+  uint32_t spins = 0;
+  while (j >= 0) {
+    const unsigned long long w =
+        __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t fl = (uint32_t)(w >> 32) & 3u;
+    if ((uint32_t)(w >> 34) != (epoch & 0x3fffffffu) || fl == 0u) {
+      if (++spins > (1u << 22)) {
+        atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (uint32_t)w;
+    if (fl == 2u) break;
+    --j;
+  }
+  __hip_atomic_store(&st[tile], tag | (2ull << 32) | (unsigned long long)(excl + agg),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+__device__ __forceinline__ uint32_t tile_total(unsigned long long* st, uint32_t ntiles) {
+  if (ntiles == 0) return 0u;
+  const unsigned long long w =
+      __hip_atomic_load(&st[ntiles - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (uint32_t)w;
+}
+
+// Block-wide (4 waves) exclusive offsets: per-wave totals in s_wt, then thread
+// 0 resolves the tile's global prefix.  Returns the wave's offset inside the
+// tile; *prefix receives the tile's global exclusive prefix.
+__device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t* s_wt,
+                                                  uint32_t* s_pref, unsigned long long* st,
+                                                  uint32_t tile, uint32_t epoch, uint32_t* err,
+                                                  uint32_t* prefix) {
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == 0) s_wt[w] = wave_total;
+  __syncthreads();
+  uint32_t off = 0, agg = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t = s_wt[k];
+    off += (k < w) ? t : 0u;
+    agg += t;
+  }
+  if (threadIdx.x == 0) *s_pref = lookback_prefix(st, tile, agg, epoch, err);
+  __syncthreads();
+  *prefix = *s_pref;
+  return off;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the control map
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  U4 o;
+  o.w[0] = c0;
+  o.w[1] = c1;
+  o.w[2] = c2;
+  o.w[3] = c3;
+  return o;
+}
+
+// top 24 bits as a fraction in [0,1), then lo + (hi - lo) * r with one rounding
+__device__ __forceinline__ float ctrl_map(uint32_t w, float lo, float hi) {
+  const float r = (float)(w >> 8) * 0x1p-24f;
+  return __builtin_fmaf(hi - lo, r, lo);
+}
+
+// ---------------------------------------------------------------------------
+// dynamics (eq. 1) and one integration step (eq. 2), FP32
+// ---------------------------------------------------------------------------
+template <int DYN>
+struct Dim;
+template <>
+struct Dim<KP_DYN_DI6> {
+  static constexpr int n = 6, m = 3;
+};
+template <>
+struct Dim<KP_DYN_QUAD12> {
+  static constexpr int n = 12, m = 4;
+};
+
+template <int DYN>
+__device__ __forceinline__ void deriv(const Params& p, const float* x, const float* u, float* dx);
+
+template <>
+__device__ __forceinline__ void deriv<KP_DYN_DI6>(const Params& p, const float* x, const float* u,
+                                                 float* dx) {
+  dx[0] = x[3];
+  dx[1] = x[4];
+  dx[2] = x[5];
+  dx[3] = u[0];
+  dx[4] = u[1];
+  dx[5] = u[2];
+}
+
+// rigid-body quadcopter, ZYX Euler angles, inertial velocity, body rates
+template <>
+__device__ __forceinline__ void deriv<KP_DYN_QUAD12>(const Params& p, const float* x,
+                                                    const float* u, float* dx) {
+  float sf, cf, st, ct, sp, cp;
+  sincosf(x[3], &sf, &cf);
+  sincosf(x[4], &st, &ct);
+  sincosf(x[5], &sp, &cp);
+  const float ict = 1.0f / ct;
+  const float P = x[9], Q = x[10], R = x[11];
+  const float a = __builtin_fmaf(Q, sf, R * cf);
+  dx[0] = x[6];
+  dx[1] = x[7];
+  dx[2] = x[8];
+  dx[3] = __builtin_fmaf(a * st, ict, P);
+  dx[4] = __builtin_fmaf(Q, cf, -(R * sf));
+  dx[5] = a * ict;
+  const float tm = u[0] * p.inv_m;
+  const float cfst = cf * st;
+  dx[6] = tm * __builtin_fmaf(cfst, cp, sf * sp);
+  dx[7] = tm * __builtin_fmaf(cfst, sp, -(sf * cp));
+  dx[8] = __builtin_fmaf(tm, cf * ct, -p.grav);
+  dx[9] = __builtin_fmaf(p.dIyz * Q, R, u[1]) * p.inv_Ixx;
+  dx[10] = __builtin_fmaf(p.dIzx * P, R, u[2]) * p.inv_Iyy;
+  dx[11] = __builtin_fmaf(p.dIxy * P, Q, u[3]) * p.inv_Izz;
+}
+
+template <int DYN, int INTEG>
+__device__ __forceinline__ void integ_step(const Params& p, float* x, const float* u) {
+  constexpr int n = Dim<DYN>::n;
+  const float h = p.h;
+  float k1[n];
+  deriv<DYN>(p, x, u, k1);
+  if constexpr (INTEG == KP_INT_EULER) {
+#pragma unroll
+    for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h, k1[i], x[i]);
+  } else {
+    const float hh = 0.5f * h;
+    const float h6 = h * (1.0f / 6.0f);
+    float t[n], k[n], acc[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      acc[i] = k1[i];
+      t[i] = __builtin_fmaf(hh, k1[i], x[i]);
+    }
+    deriv<DYN>(p, t, u, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
+      t[i] = __builtin_fmaf(hh, k[i], x[i]);
+    }
+    deriv<DYN>(p, t, u, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
+      t[i] = __builtin_fmaf(h, k[i], x[i]);
+    }
+    deriv<DYN>(p, t, u, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
+  }
+}
+
+template <int DYN>
+__device__ __forceinline__ bool state_ok(const Params& p, const float* x) {
+  constexpr int n = Dim<DYN>::n;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < n; ++i) ok = ok && (x[i] >= p.x_lo[i]) && (x[i] <= p.x_hi[i]);
+  return ok;  // NaN fails both comparisons
+}
+
+// fine cell (region * 64 + sub-cell) of a finite position, clamped to W
+__device__ __forceinline__ uint32_t cell_of(const Params& p, float px, float py, float pz) {
+  const float q[3] = {px, py, pz};
+  int c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float t = (q[a] - p.w_lo[a]) * p.inv_w[a];
+    t = fminf(fmaxf(t, 0.0f), (float)(p.na[a] - 1));
+    c[a] = (int)floorf(t);
+  }
+  const int S = p.S;
+  const uint32_t region = (uint32_t)(((c[2] / S) * p.G[1] + (c[1] / S)) * p.G[0] + (c[0] / S));
+  const uint32_t local = (uint32_t)(((c[2] % S) * S + (c[1] % S)) * S + (c[0] % S));
+  return region * 64u + local;
+}
+
+// ---------------------------------------------------------------------------
+// k_zero / k_root / k_set_ctl: (re)initialisation, Alg. 1 lines 1-3
+// ---------------------------------------------------------------------------
+__global__ void k_zero(Params p, Dev d) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < p.R; r += stride) {
+    d.nv[r] = 0ull;
+    d.ni[r] = 0ull;
+    d.visited[r] = 0ull;
+    d.thr[r] = 1ull << 32;
+    d.avail[r] = 0;
+  }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.tiles_node; t += stride) {
+    d.st_front[t] = 0ull;
+    d.st_nodes[t] = 0ull;
+  }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.tiles_prop; t += stride)
+    d.st_prop[t] = 0ull;
+}
+
+__global__ void k_root(Params p, Dev d, Vec12 xi) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  Ctl* c = d.ctl;
+  for (int k = 0; k < p.n; ++k) d.x[(size_t)k * d.capP] = xi.v[k];
+  for (int k = 0; k < p.m; ++k) d.u[(size_t)k * d.capP] = 0.0f;
+  const uint32_t cl = cell_of(p, xi.v[0], xi.v[1], xi.v[2]);
+  d.parent[0] = -1;
+  d.cell[0] = cl;
+  d.flag[0] = 1;
+  d.birth[0] = -1;
+  d.sample[0] = 0;
+  d.visited[cl >> 6] = 1ull << (cl & 63u);
+  d.avail[cl >> 6] = 1;
+  const float dx = xi.v[0] - p.goal_c[0], dy = xi.v[1] - p.goal_c[1], dz = xi.v[2] - p.goal_c[2];
+  const bool in_goal = dx * dx + dy * dy + dz * dz <= p.goal_r2;
+  c->N = 1;
+  c->nF = 0;
+  c->lambda = 0;
+  c->lanes = 0;
+  c->nU = 0;
+  c->it = 0;
+  c->goal_id = in_goal ? 0 : kNoGoal;
+  c->done = in_goal ? KP_SOLVED : 0;
+  c->epoch = c->epoch + 1u;
+  c->tk_front = c->tk_prop = c->tk_nodes = 0u;
+  c->bd_front = c->bd_prop = c->bd_nodes = 0u;
+  c->err = 0u;
+  c->iters_done = 0u;
+  c->lanes_total = c->valid_total = c->invalid_total = c->steps_total = c->box_total = 0ull;
+}
+
+// state loaded from the host: counters for |T| = N at iteration `it`
+__global__ void k_set_ctl(Dev d, int32_t N, int32_t it) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  Ctl* c = d.ctl;
+  c->N = N;
+  c->nF = 0;
+  c->lambda = 0;
+  c->lanes = 0;
+  c->nU = 0;
+  c->it = it;
+  c->goal_id = kNoGoal;
+  c->done = 0;
+  c->epoch = c->epoch + 1u;
+  c->tk_front = c->tk_prop = c->tk_nodes = 0u;
+  c->bd_front = c->bd_prop = c->bd_nodes = 0u;
+  c->err = 0u;
+  c->lanes_total = c->valid_total = c->invalid_total = c->steps_total = c->box_total = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// frontier compaction shared by k_frontier and k_nodesets
+// ---------------------------------------------------------------------------
+// E-bits of the four nodes held by this thread -> F, in ascending id order.
+__device__ __forceinline__ void compact_frontier(const Dev& d, unsigned long long* st,
+                                                 uint32_t ebits, uint32_t base, uint32_t tile,
+                                                 uint32_t epoch, uint32_t* s_wt, uint32_t* s_pref) {
+  uint32_t wt;
+  const uint32_t c = __popc(ebits);
+  const uint32_t ex = wave_excl_small(c, &wt);
+  uint32_t prefix;
+  const uint32_t woff =
+      block_offsets(wt, s_wt, s_pref, st, tile, epoch, &d.ctl->err, &prefix);
+  uint32_t pos = prefix + woff + ex;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (ebits & (1u << k)) d.F[pos++] = (int32_t)(base + k);
+}
+
+// last-block finalisation of the frontier: |V_E|, eq. (6), termination codes
+__device__ __forceinline__ void finalize_frontier(const Params& p, Ctl* c, uint32_t nF,
+                                                  int32_t N) {
+  int32_t lam = 0;
+  if (nF > 0) {
+    lam = (p.cap - N) / (int32_t)nF;
+    if (lam > p.lambda_max) lam = p.lambda_max;
+  }
+  c->nF = (int32_t)nF;
+  c->lambda = lam;
+  c->lanes = (int32_t)nF * lam;
+  if (c->done == 0) {
+    if (nF == 0) c->done = KP_FRONTIER_EMPTY;
+    else if (lam == 0) c->done = KP_TREE_FULL;
+  }
+}
+
+__global__ __launch_bounds__(kNodeBlock) void k_frontier(Params p, Dev d) {
+  Ctl* c = d.ctl;
+  const int32_t N = c->N;
+  const int done = c->done;
+  const uint32_t epoch = c->epoch;
+  const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
+  __shared__ uint32_t s_tile, s_pref, s_wt[4];
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_front, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const uint32_t base = tile * kNodeTile + threadIdx.x * 4u;
+    const uint32_t fw = *reinterpret_cast<const uint32_t*>(d.flag + base);
+    uint32_t eb = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (base + k < (uint32_t)N && ((fw >> (8 * k)) & 0xffu)) eb |= 1u << k;
+    compact_frontier(d, d.st_front, eb, base, tile, epoch, s_wt, &s_pref);
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&c->bd_front, 1u);
+    if (prev == gridDim.x - 1u) {
+      __threadfence();
+      if (!done) finalize_frontier(p, c, tile_total(d.st_front, ntiles), N);
+      c->tk_front = 0u;
+      c->bd_front = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_propagate: Alg. 2
+// ---------------------------------------------------------------------------
+size_t propagate_lds_bytes(int n_obs) {
+  const size_t b = (size_t)n_obs * (6 * sizeof(float) + 4 * sizeof(uint16_t));
+  return b < 16 ? 16 : b;
+}
+
+template <int DYN, int INTEG>
+__global__ __launch_bounds__(kPropBlock) void k_propagate(Params p, Dev d, TraceRec* trace) {
+  constexpr int n = Dim<DYN>::n;
+  constexpr int m = Dim<DYN>::m;
+  extern __shared__ float lds[];
+  Ctl* c = d.ctl;
+  const int done = c->done;
+  const int32_t lanes = c->lanes;
+  const int32_t lam = c->lambda;
+  const int32_t N = c->N;
+  const uint32_t it = (uint32_t)c->it;
+  const uint32_t epoch = c->epoch;
+  const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + kPropBlock - 1) / kPropBlock);
+  const int n_obs = p.n_obs;
+  const int wave = threadIdx.x >> 6;
+  float* o_lx = lds;
+  float* o_ly = lds + n_obs;
+  float* o_lz = lds + 2 * n_obs;
+  float* o_hx = lds + 3 * n_obs;
+  float* o_hy = lds + 4 * n_obs;
+  float* o_hz = lds + 5 * n_obs;
+  uint16_t* cand = reinterpret_cast<uint16_t*>(lds + 6 * n_obs) + wave * n_obs;
+  __shared__ uint32_t s_tile, s_pref, s_wt[4];
+
+  if (ntiles > 0)
+    for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) lds[k] = d.obs[k];
+  __syncthreads();
+
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_prop, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+
+    const int32_t g = (int32_t)(tile * kPropBlock + threadIdx.x);
+    const bool active = g < lanes;
+    int32_t e = 0, s = 0, f = 0;
+    float x[n];
+    float u[m];
+    uint32_t w_acc = 0;
+    if (active) {
+      e = g / lam;
+      s = g - e * lam;
+      f = d.F[e];
+#pragma unroll
+      for (int k = 0; k < n; ++k) x[k] = d.x[(size_t)k * d.capP + f];
+      const U4 w = philox(it, (uint32_t)f, (uint32_t)s, 0u, p.key0, p.key1);
+#pragma unroll
+      for (int j = 0; j < m; ++j) u[j] = ctrl_map(w.w[j], p.u_lo[j], p.u_hi[j]);
+      if constexpr (m < 4) {
+        w_acc = w.w[3];
+      } else {
+        const U4 w1 = philox(it, (uint32_t)f, (uint32_t)s, 1u, p.key0, p.key1);
+        w_acc = w1.w[0];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < n; ++k) x[k] = 0.0f;
+#pragma unroll
+      for (int j = 0; j < m; ++j) u[j] = 0.0f;
+    }
+
+    // Per-wave obstacle culling.  Until its first failing step, a segment
+    // stays within rc (per axis) of its parent: every checked step starts
+    // from a state inside the velocity bounds.  Obstacles that overlap the
+    // union of the wave's parent boxes grown by rc + margin are copied to a
+    // wave-private candidate list; the step loop then reads only those, with
+    // wave-uniform indices (LDS broadcast).
+    const float big = 3.0e38f;
+    const float bx0 = wave_min(active ? x[0] - p.rc : big);
+    const float by0 = wave_min(active ? x[1] - p.rc : big);
+    const float bz0 = wave_min(active ? x[2] - p.rc : big);
+    const float bx1 = wave_max(active ? x[0] + p.rc : -big);
+    const float by1 = wave_max(active ? x[1] + p.rc : -big);
+    const float bz1 = wave_max(active ? x[2] + p.rc : -big);
+    uint32_t ncand = 0;
+    for (int k0 = 0; k0 < n_obs; k0 += 64) {
+      const int k = k0 + (int)__lane_id();
+      bool ov = false;
+      if (k < n_obs) {
+        ov = (o_lx[k] <= bx1 + p.margin) && (bx0 - p.margin <= o_hx[k]) &&
+             (o_ly[k] <= by1 + p.margin) && (by0 - p.margin <= o_hy[k]) &&
+             (o_lz[k] <= bz1 + p.margin) && (bz0 - p.margin <= o_hz[k]);
+      }
+      const unsigned long long b = __ballot(ov);
+      if (ov) cand[ncand + __popcll(b & lanes_below())] = (uint16_t)k;
+      ncand += (uint32_t)__popcll(b);
+    }
+    __syncthreads();  // candidate lists written by lanes are read wave-wide below
+
+    // Segment integration with per-step validity; x' is the segment end or
+    // the first failing state.
+    bool alive = active;
+    bool valid = active;
+    int32_t steps = 0;
+    uint32_t box_tests = 0;
+    for (int j = 0; j < p.K; ++j) {
+      if (__ballot(alive) == 0ull) break;
+      if (alive) {
+        const float px = x[0], py = x[1], pz = x[2];
+        integ_step<DYN, INTEG>(p, x, u);
+        steps = j + 1;
+        bool ok = state_ok<DYN>(p, x);
+        if (ok) {
+          const float lx = fminf(px, x[0]) - p.margin, hx = fmaxf(px, x[0]) + p.margin;
+          const float ly = fminf(py, x[1]) - p.margin, hy = fmaxf(py, x[1]) + p.margin;
+          const float lz = fminf(pz, x[2]) - p.margin, hz = fmaxf(pz, x[2]) + p.margin;
+          bool hit = false;
+          for (uint32_t q = 0; q < ncand; ++q) {
+            const int k = cand[q];
+            hit |= (lx <= o_hx[k]) & (o_lx[k] <= hx) & (ly <= o_hy[k]) & (o_ly[k] <= hy) &
+                   (lz <= o_hz[k]) & (o_lz[k] <= hz);
+          }
+          box_tests += ncand;
+          ok = !hit;
+        }
+        if (!ok) {
+          alive = false;
+          valid = false;
+        }
+      }
+    }
+
+    // sub-region, counts, acceptance (Alg. 2 lines 5-11)
+    uint32_t cl = 0;
+    bool accept = false, goal = false;
+    if (active) {
+      const bool fin = __builtin_isfinite(x[0]) && __builtin_isfinite(x[1]) &&
+                       __builtin_isfinite(x[2]);
+      cl = fin ? cell_of(p, x[0], x[1], x[2]) : d.cell[f];
+      if (valid) {
+        const uint32_t r = cl >> 6;
+        const bool unvisited = ((d.visited[r] >> (cl & 63u)) & 1ull) == 0ull;
+        accept = unvisited || ((unsigned long long)w_acc < d.thr[r]);
+        const float dx = x[0] - p.goal_c[0], dy = x[1] - p.goal_c[1], dz = x[2] - p.goal_c[2];
+        goal = accept && (dx * dx + dy * dy + dz * dz <= p.goal_r2);
+      }
+    }
+    // n_valid / n_invalid: one atomic per distinct (region, validity) in the wave
+    {
+      const uint32_t key = active ? ((cl >> 6) << 1) | (valid ? 1u : 0u) : 0xffffffffu;
+      unsigned long long pending = __ballot(active);
+      while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const uint32_t k0 = (uint32_t)__shfl((int)key, leader);
+        const unsigned long long match = __ballot(key == k0);
+        if ((int)__lane_id() == leader) {
+          unsigned long long* ctr = (k0 & 1u) ? d.nv : d.ni;
+          atomicAdd(&ctr[k0 >> 1], (unsigned long long)__popcll(match));
+        }
+        pending &= ~match;
+      }
+    }
+
+    // stable compaction of accepted samples: id = |T| + rank in lane order
+    const unsigned long long ab = __ballot(accept);
+    const uint32_t rank = (uint32_t)__popcll(ab & lanes_below());
+    uint32_t prefix;
+    const uint32_t woff = block_offsets((uint32_t)__popcll(ab), s_wt, &s_pref, d.st_prop, tile,
+                                        epoch, &c->err, &prefix);
+    int32_t id = -1;
+    if (accept) {
+      id = N + (int32_t)(prefix + woff + rank);
+      if (id >= N + lanes) {  // cannot happen with a consistent look-back; never write past it
+        atomicOr(&c->err, 2u);
+        accept = false;
+        goal = false;
+        id = -1;
+      }
+    }
+    if (accept) {
+#pragma unroll
+      for (int k = 0; k < n; ++k) d.x[(size_t)k * d.capP + id] = x[k];
+#pragma unroll
+      for (int j = 0; j < m; ++j) d.u[(size_t)j * d.capP + id] = u[j];
+      d.parent[id] = f;
+      d.cell[id] = cl;
+      d.flag[id] = 1;
+      d.birth[id] = (int32_t)it;
+      d.sample[id] = (uint8_t)s;
+      if (goal) atomicMin(&c->goal_id, id);
+    }
+    if (trace != nullptr && active) {
+      TraceRec* t = trace + g;
+      t->parent = f;
+      t->sample = s;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t->u[j] = (j < m) ? u[j] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) t->x[k] = (k < n) ? x[k] : 0.0f;
+      t->steps = steps;
+      t->valid = valid ? 1 : 0;
+      t->cell = cl;
+      t->goal = goal ? 1 : 0;
+      t->accept = accept ? 1 : 0;
+      t->new_id = id;
+    }
+    // counters
+    {
+      const unsigned long long nl = __popcll(__ballot(active));
+      const unsigned long long nvv = __popcll(__ballot(active && valid));
+      const unsigned long long st = wave_sum_u64((unsigned long long)steps);
+      const unsigned long long bt = wave_sum_u64((unsigned long long)box_tests);
+      if (__lane_id() == 0 && nl) {
+        atomicAdd(&c->lanes_total, nl);
+        atomicAdd(&c->valid_total, nvv);
+        atomicAdd(&c->invalid_total, nl - nvv);
+        atomicAdd(&c->steps_total, st);
+        atomicAdd(&c->box_total, bt);
+      }
+    }
+    __syncthreads();
+  }
+
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&c->bd_prop, 1u);
+    if (prev == gridDim.x - 1u) {
+      __threadfence();
+      if (!done) c->nU = (int32_t)tile_total(d.st_prop, ntiles);
+      c->tk_prop = 0u;
+      c->bd_prop = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_region: Alg. 3 (eqs. 3-5), one workgroup
+// ---------------------------------------------------------------------------
+// Score without the common factor vol^4; fixed FP64 operation order.
+__device__ __forceinline__ double region_score(double delta, unsigned long long nv,
+                                               unsigned long long ni, int cov) {
+  const double a = delta + (double)nv;
+  const double b = a + (double)ni;
+  const double phi = a / b;
+  const double phi2 = phi * phi;
+  const double num = phi2 * phi2;
+  const double nn = (double)(nv + ni);
+  const double den = (1.0 + (double)cov) * (1.0 + nn * nn);
+  return num / den;
+}
+
+__global__ __launch_bounds__(kRegionBlock) void k_region(Params p, Dev d) {
+  Ctl* c = d.ctl;
+  if (c->done) return;
+  __shared__ double s_max[kRegionBlock / 64];
+  __shared__ unsigned long long s_sum[kRegionBlock / 64];
+  const int wave = threadIdx.x >> 6;
+  // pass 1: largest score
+  double mx = 0.0;
+  for (int r = threadIdx.x; r < p.R; r += kRegionBlock)
+    if (d.avail[r]) mx = fmax(mx, region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r])));
+  mx = wave_max_f64(mx);
+  if (__lane_id() == 0) s_max[wave] = mx;
+  __syncthreads();
+  mx = 0.0;
+  for (int k = 0; k < kRegionBlock / 64; ++k) mx = fmax(mx, s_max[k]);
+  const int e = (mx > 0.0) ? ilogb(mx) : 0;
+  // pass 2: exact integer sum of the scores scaled by 2^(46 - e)
+  unsigned long long q = 0;
+  for (int r = threadIdx.x; r < p.R; r += kRegionBlock)
+    if (d.avail[r]) {
+      const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
+      q += (unsigned long long)floor(ldexp(sc, 46 - e));
+    }
+  q = wave_sum_u64(q);
+  if (__lane_id() == 0) s_sum[wave] = q;
+  __syncthreads();
+  unsigned long long Q = 0;
+  for (int k = 0; k < kRegionBlock / 64; ++k) Q += s_sum[k];
+  // pass 3: P_accept = min(1, q / Q + eps) as a 32-bit threshold
+  for (int r = threadIdx.x; r < p.R; r += kRegionBlock) {
+    if (!d.avail[r]) continue;
+    const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
+    const unsigned long long qr = (unsigned long long)floor(ldexp(sc, 46 - e));
+    const double P = (Q > 0ull) ? (double)qr / (double)Q + p.eps : p.eps;
+    d.thr[r] = (P >= 1.0) ? (1ull << 32) : (unsigned long long)floor(P * 4294967296.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_nodesets: Alg. 4 + next frontier + eq. (6)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNodeBlock) void k_nodesets(Params p, Dev d) {
+  Ctl* c = d.ctl;
+  const int done = c->done;
+  const int32_t N = c->N;
+  const int32_t nU = c->nU;
+  const int32_t Nt = N + nU;
+  const uint32_t it = (uint32_t)c->it;
+  const uint32_t epoch = c->epoch;
+  const bool goal = c->goal_id != kNoGoal;
+  const uint32_t ntiles = done ? 0u : (uint32_t)((Nt + kNodeTile - 1) / kNodeTile);
+  __shared__ uint32_t s_tile, s_pref, s_wt[4];
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const uint32_t base = tile * kNodeTile + threadIdx.x * 4u;
+    uint32_t eb = 0;
+    if (base < (uint32_t)Nt) {
+      const uint32_t fw = *reinterpret_cast<const uint32_t*>(d.flag + base);
+      const uint4 cw = *reinterpret_cast<const uint4*>(d.cell + base);
+      const uint32_t cells[4] = {cw.x, cw.y, cw.z, cw.w};
+      const U4 wa = philox(it, base >> 1, 0u, 3u, p.key0, p.key1);
+      const U4 wb = philox(it, (base >> 1) + 1u, 0u, 3u, p.key0, p.key1);
+      const uint32_t wd[4] = {wa.w[0], wa.w[2], wb.w[0], wb.w[2]};
+      const uint32_t wp[4] = {wa.w[1], wa.w[3], wb.w[1], wb.w[3]};
+      uint32_t nfw = fw;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = base + k;
+        if (i >= (uint32_t)Nt) continue;
+        const uint32_t r = cells[k] >> 6;
+        bool E;
+        if (i >= (uint32_t)N) {
+          // V_U -> T and V_E (Alg. 4 lines 4-6)
+          E = true;
+          atomicOr(&d.visited[r], 1ull << (cells[k] & 63u));
+          d.avail[r] = 1;
+        } else {
+          const unsigned long long t = d.thr[r];
+          const bool wasE = ((fw >> (8 * k)) & 0xffu) != 0u;
+          const bool stay = wasE && ((unsigned long long)wd[k] < t);        // lines 1-3
+          E = stay || (!goal && ((unsigned long long)wp[k] < t));           // lines 7-9
+          nfw = (nfw & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
+        }
+        if (E) eb |= 1u << k;
+      }
+      if (nfw != fw) *reinterpret_cast<uint32_t*>(d.flag + base) = nfw;
+    }
+    compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&c->bd_nodes, 1u);
+    if (prev == gridDim.x - 1u) {
+      __threadfence();
+      if (!done) {
+        c->N = Nt;
+        if (goal) c->done = KP_SOLVED;
+        finalize_frontier(p, c, tile_total(d.st_nodes, ntiles), Nt);
+        c->it = (int32_t)it + 1;
+        c->epoch = epoch + 1u;
+        c->iters_done += 1u;
+      }
+      c->tk_nodes = 0u;
+      c->bd_nodes = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_path: root-to-node walk along parent links
+// ---------------------------------------------------------------------------
+__global__ void k_path(Dev d, int32_t node) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int32_t len = 0;
+  for (int32_t v = node; v >= 0 && len <= kMaxPath; v = d.parent[v]) ++len;
+  d.path[0] = len;
+  if (len > kMaxPath) return;
+  int32_t k = len;
+  for (int32_t v = node; v >= 0; v = d.parent[v]) d.path[k--] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_zero(const Params& p, const Dev& d, hipStream_t s) {
+  int work = p.R;
+  if (d.tiles_node > work) work = d.tiles_node;
+  if (d.tiles_prop > work) work = d.tiles_prop;
+  int grid = (work + 255) / 256;
+  if (grid > 1024) grid = 1024;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, p, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_root(const Params& p, const Dev& d, Vec12 xi, hipStream_t s) {
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, p, d, xi);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_ctl(const Dev& d, int32_t N, int32_t it, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, d, N, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_frontier(const Params& p, const Dev& d, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kNodeBlock), 0, s, p, d);
+  return hipGetLastError();
+}
+
+template <int DYN, int INTEG>
+static hipError_t launch_prop_t(const Params& p, const Dev& d, TraceRec* trace, int grid,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((k_propagate<DYN, INTEG>), dim3(grid), dim3(kPropBlock),
+                     propagate_lds_bytes(p.n_obs), s, p, d, trace);
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate(int dyn, int integ, const Params& p, const Dev& d, TraceRec* trace,
+                            int grid, hipStream_t s) {
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
+    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER>(p, d, trace, grid, s);
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
+    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4>(p, d, trace, grid, s);
+  if (dyn == KP_DYN_QUAD12 && integ == KP_INT_EULER)
+    return launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(p, d, trace, grid, s);
+  return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(p, d, trace, grid, s);
+}
+
+hipError_t launch_region(const Params& p, const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_region, dim3(1), dim3(kRegionBlock), 0, s, p, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_nodesets(const Params& p, const Dev& d, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_nodesets, dim3(grid), dim3(kNodeBlock), 0, s, p, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_path(const Dev& d, int32_t node, hipStream_t s) {
+  hipLaunchKernelGGL(k_path, dim3(1), dim3(64), 0, s, d, node);
+  return hipGetLastError();
+}
+
+template <int DYN, int INTEG>
+static int occ_prop_t(int n_obs) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG>, kPropBlock,
+                                                    propagate_lds_bytes(n_obs)) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu) {
+  int nb;
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER) nb = occ_prop_t<KP_DYN_DI6, KP_INT_EULER>(n_obs);
+  else if (dyn == KP_DYN_DI6) nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4>(n_obs);
+  else if (integ == KP_INT_EULER) nb = occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(n_obs);
+  else nb = occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(n_obs);
+  *blocks_per_cu = nb;
+  return nb;
+}
+
+int occupancy_nodes(int* blocks_per_cu) {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nodesets, kNodeBlock, 0) != hipSuccess)
+    a = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_frontier, kNodeBlock, 0) != hipSuccess)
+    b = 1;
+  int nb = a < b ? a : b;
+  if (nb < 1) nb = 1;
+  *blocks_per_cu = nb;
+  return nb;
+}
+
+}  // namespace kp

@@ -1,0 +1,231 @@
+"""Lock-step parity between the GPU library and the FP64 oracle.
+
+For each iteration:
+  1. the oracle computes its frontier, lambda (eq. 6) and every expansion
+     record (Alg. 2, per lane) on its own state;
+  2. the GPU runs kp_expand on the same state (loaded from the oracle, or its
+     own state from the previous GPU iteration) with a trace buffer;
+  3. per lane: parent/sample order and controls must be identical; the
+     validity outcome (first failing step), the sub-region and the goal test
+     must be identical unless the oracle marked that decision ambiguous (its
+     FP64 value within the ambiguity band of a decision surface), in which
+     case the GPU's outcome must be one of the admissible ones; states must
+     agree within 1e-5 * max(1, |ref|);
+  4. the oracle's bookkeeping (counts, acceptance, V_U order, estimates, node
+     sets, next frontier) is applied to the records -- with the GPU's outcome
+     substituted only where the oracle itself found the decision ambiguous --
+     and every integer field of the GPU state (ids, parents, cells, flags,
+     counts, visited bits, R_avail, thresholds, |T|) must match bit for bit.
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+import oracle
+
+REL_TOL = 1e-5
+
+
+class Report:
+    def __init__(self):
+        self.iterations = 0
+        self.lanes = 0
+        self.ambiguous_lanes = 0
+        self.adopted = 0
+        self.max_rel_err = 0.0
+        self.failures = []
+        self.final_status = None
+
+    @property
+    def ok(self):
+        return not self.failures
+
+    def fail(self, msg):
+        if len(self.failures) < 50:
+            self.failures.append(msg)
+
+    def summary(self):
+        s = (f"iterations={self.iterations} lanes={self.lanes} ambiguous={self.ambiguous_lanes} "
+             f"adopted={self.adopted} max_rel_err={self.max_rel_err:.2e} "
+             f"status={self.final_status} failures={len(self.failures)}")
+        if self.failures:
+            s += " first: " + "; ".join(self.failures[:5])
+        return s
+
+
+def gpu_state_from_oracle(s):
+    return dict(N=s["N"], it=s["it"], x=np.asarray(s["x"], np.float64).astype(np.float32),
+                u=s["u"], parent=s["parent"], cell=s["cell"], flag=s["flag"], birth=s["birth"],
+                sample=np.maximum(s["sample"], 0), nv=s["nv"], ni=s["ni"],
+                visited=s["visited"], avail=s["avail"], thr=s["thr"])
+
+
+def rel_err(g, o):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    if g.size == 0:
+        return 0.0
+    return float(np.max(np.abs(g - o) / np.maximum(1.0, np.abs(o))))
+
+
+def admissible_cells(p, x, tol=oracle.kpo.AMB_TOL):
+    cells = set()
+    for d in itertools.product((-tol, 0.0, tol), repeat=3):
+        cells.add(oracle.cell_of(p, np.asarray(x[:3], np.float64) + np.asarray(d)))
+    return cells
+
+
+def compare_expansion(p, W, recs, tr, rep, it):
+    """Per-lane comparison; returns the records with admissible GPU outcomes
+    substituted where the oracle marked the decision ambiguous."""
+    K = int(p["steps"])
+    m = W.m
+    n = W.n
+    lanes = len(recs)
+    if not (np.array_equal(tr["parent"], recs["parent"]) and
+            np.array_equal(tr["sample"], recs["sample"])):
+        rep.fail(f"it{it}: lane order (parent, sample) differs")
+        return recs
+    gu = np.ascontiguousarray(tr["u"][:, :m]).view(np.uint32)
+    ou = np.ascontiguousarray(recs["u"][:, :m]).view(np.uint32)
+    if not np.array_equal(gu, ou):
+        k = int(np.nonzero(np.any(gu != ou, axis=1))[0][0])
+        rep.fail(f"it{it}: control bits differ at lane {k}")
+    o_fail = np.where(recs["valid"] == 1, K + 1, recs["steps"])
+    g_fail = np.where(tr["valid"] == 1, K + 1, tr["steps"])
+    amb_valid = recs["fail_strict"] != recs["fail_loose"]
+    rep.ambiguous_lanes += int(np.sum(amb_valid | (recs["amb_cell"] != 0) | (recs["amb_goal"] != 0)))
+    merged = recs.copy()
+    for k in np.nonzero(o_fail != g_fail)[0]:
+        if not (recs["fail_strict"][k] <= g_fail[k] <= recs["fail_loose"][k]):
+            rep.fail(f"it{it}: lane {k} validity differs (oracle fail step {o_fail[k]}, "
+                     f"gpu {g_fail[k]}, band [{recs['fail_strict'][k]}, {recs['fail_loose'][k]}])")
+            continue
+        # admissible: adopt the GPU's first failing step, oracle state at that step
+        rec, traj = W.expand_one(recs["parent"][k], recs["sample"][k], want_traj=True)
+        steps = min(int(g_fail[k]), K)
+        merged["valid"][k] = 1 if g_fail[k] == K + 1 else 0
+        merged["steps"][k] = steps
+        merged["x"][k][:n] = traj[steps]
+        merged["cell"][k] = tr["cell"][k]
+        if tr["cell"][k] not in admissible_cells(p, traj[steps]) and np.all(np.isfinite(traj[steps][:3])):
+            rep.fail(f"it{it}: lane {k} adopted cell not admissible")
+        gd = np.linalg.norm(traj[steps][:3] - np.asarray(p["goal_center"], np.float64))
+        merged["goal"][k] = 1 if (merged["valid"][k] and gd <= float(np.float32(p["goal_radius"]))) else 0
+        rep.adopted += 1
+    same = o_fail == g_fail
+    # states where the stop step agrees
+    idx = np.nonzero(same)[0]
+    if len(idx):
+        e = rel_err(tr["x"][idx, :n], recs["x"][idx, :n])
+        rep.max_rel_err = max(rep.max_rel_err, e)
+        if e > REL_TOL:
+            bad = np.max(np.abs(tr["x"][idx, :n] - recs["x"][idx, :n]) /
+                         np.maximum(1, np.abs(recs["x"][idx, :n])), axis=1)
+            k = int(idx[np.argmax(bad)])
+            rep.fail(f"it{it}: lane {k} state rel err {e:.2e}")
+    # cells where the stop step agrees
+    for k in idx[tr["cell"][idx] != recs["cell"][idx]]:
+        if recs["amb_cell"][k] and tr["cell"][k] in admissible_cells(p, recs["x"][k]):
+            merged["cell"][k] = tr["cell"][k]
+            rep.adopted += 1
+        else:
+            rep.fail(f"it{it}: lane {k} cell differs ({tr['cell'][k]} vs {recs['cell'][k]})")
+    # goal test on accepted lanes (GPU reports goal only for accepted samples)
+    acc = np.nonzero(same & (tr["accept"] == 1))[0]
+    for k in acc[(tr["goal"][acc] != 0) != (recs["goal"][acc] != 0)]:
+        if recs["amb_goal"][k]:
+            merged["goal"][k] = tr["goal"][k]
+            rep.adopted += 1
+        else:
+            rep.fail(f"it{it}: lane {k} goal test differs")
+    rep.lanes += lanes
+    return merged
+
+
+def compare_state(p, W, g, rep, it, where):
+    s = W.state()
+    N = s["N"]
+    if g["N"] != N:
+        rep.fail(f"it{it} {where}: |T| gpu {g['N']} oracle {N}")
+        return
+    for k in ("parent", "cell", "flag", "birth"):
+        if not np.array_equal(np.asarray(g[k][:N]).astype(np.int64), np.asarray(s[k][:N]).astype(np.int64)):
+            j = int(np.nonzero(np.asarray(g[k][:N]).astype(np.int64) != np.asarray(s[k][:N]).astype(np.int64))[0][0])
+            rep.fail(f"it{it} {where}: {k} differs first at node {j}")
+    if N > 1 and not np.array_equal(g["sample"][1:N].astype(np.int64), s["sample"][1:N].astype(np.int64)):
+        rep.fail(f"it{it} {where}: sample index differs")
+    for k in ("nv", "ni", "visited", "avail", "thr"):
+        if not np.array_equal(np.asarray(g[k]).astype(np.uint64), np.asarray(s[k]).astype(np.uint64)):
+            j = int(np.nonzero(np.asarray(g[k]).astype(np.uint64) != np.asarray(s[k]).astype(np.uint64))[0][0])
+            rep.fail(f"it{it} {where}: region array {k} differs first at region {j} "
+                     f"(gpu {g[k][j]} oracle {s[k][j]})")
+    gu = np.ascontiguousarray(g["u"][1:N], np.float32).view(np.uint32)
+    ou = np.ascontiguousarray(s["u"][1:N], np.float32).view(np.uint32)
+    if not np.array_equal(gu, ou):
+        rep.fail(f"it{it} {where}: stored controls differ")
+    e = rel_err(g["x"][:N], s["x"][:N])
+    rep.max_rel_err = max(rep.max_rel_err, e)
+    if e > REL_TOL:
+        rep.fail(f"it{it} {where}: stored states rel err {e:.2e}")
+
+
+def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=None):
+    """Run `iterations` lock-step iterations from the root.  reload=True loads
+    the oracle's state into the GPU before every iteration (identical inputs);
+    reload=False lets the GPU continue from its own state (exercises the fused
+    next-frontier pass)."""
+    from paper_2409_06807_amd import Planner
+    import torch
+
+    rep = report if report is not None else Report()
+    W = oracle.OraclePlanner(p)
+    if G is None:
+        G = Planner(p, device=device)
+    trace = G.trace_buffer()
+    for it in range(iterations):
+        if W.state(copy=False)["goal_id"] >= 0:
+            rep.final_status = oracle.SOLVED
+            break
+        if reload or it == 0:
+            G.load_tree(gpu_state_from_oracle(W.state()))
+        st = W.frontier()
+        gs = G.stats()
+        if gs["n_frontier"] != W.state(copy=False)["nF"] or gs["lam"] != W.state(copy=False)["lam"]:
+            rep.fail(f"it{it}: frontier size / lambda gpu ({gs['n_frontier']}, {gs['lam']}) "
+                     f"oracle ({W.state(copy=False)['nF']}, {W.state(copy=False)['lam']})")
+            break
+        if st != oracle.OK:
+            if gs["done_code"] != st:
+                rep.fail(f"it{it}: termination code gpu {gs['done_code']} oracle {st}")
+            rep.final_status = st
+            break
+        recs = W.expand_all()
+        G.expand(trace)
+        torch.cuda.synchronize()
+        tr = G.trace(trace, len(recs))
+        merged = compare_expansion(p, W, recs, tr, rep, it)
+        W.apply(merged)
+        g = G.copy_tree()
+        if g["N"] != W.state(copy=False)["N"] + W.view().nU:
+            rep.fail(f"it{it}: |V_U| gpu {g['N'] - W.state(copy=False)['N']} oracle {W.view().nU}")
+        for k in ("nv", "ni"):
+            if not np.array_equal(g[k], W.state(copy=False)[k]):
+                rep.fail(f"it{it}: {k} after Propagate differs")
+        W.update_estimates()
+        G.update_regions()
+        W.update_node_sets()
+        G.update_tree()
+        g = G.copy_tree()
+        compare_state(p, W, g, rep, it, "after UpdateNodeSets")
+        gs = G.stats()
+        og = W.state(copy=False)["goal_id"]
+        if gs["goal_id"] != og:
+            rep.fail(f"it{it}: goal id gpu {gs['goal_id']} oracle {og}")
+        rep.iterations += 1
+        if not rep.ok:
+            break
+    return rep

@@ -1,0 +1,60 @@
+"""GPU parity: the HIP path against the FP64 oracle, iteration by iteration,
+through the C ABI (kp_load_tree / kp_expand with a trace / kp_update_regions /
+kp_update_tree / kp_copy_tree).  See lockstep.py for the protocol."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import problem_small_di, problem_small_quad, RK4
+
+import lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(name, p):
+    print(f"[gpu-case] {name}: cap={p['node_cap']} obs={len(p['obstacles'])} "
+          f"lam={p['lambda_max']} grid={p['grid']} sub={p['sub']} seed={p['seed']}", flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "di-euler": lambda: problem_small_di(seed=1, cap=4096, n_obs=12),
+    "di-euler-ragged": lambda: problem_small_di(seed=2, cap=3001, n_obs=7, lambda_max=7,
+                                                grid=(5, 6, 7), sub=3),
+    "di-rk4": lambda: problem_small_di(seed=3, cap=4096, n_obs=12, integrator=RK4),
+    "di-sub1": lambda: problem_small_di(seed=4, cap=2500, n_obs=20, grid=(4, 4, 4), sub=1),
+    "quad-rk4": lambda: problem_small_quad(seed=1, cap=8192, n_obs=60),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("reload", [True, False])
+def test_lockstep(name, reload):
+    p = CASES[name]()
+    _announce(f"lockstep {name} reload={reload}", p)
+    iters = 8 if name.startswith("quad") else 14
+    rep = lockstep.run_lockstep(p, iterations=iters, reload=reload)
+    print(rep.summary(), flush=True)
+    assert rep.ok, rep.summary()
+    assert rep.iterations >= 3 or rep.final_status in (oracle.TREE_FULL, oracle.SOLVED)
+
+
+def test_lockstep_until_tree_full():
+    p = problem_small_di(seed=9, cap=256, n_obs=5)
+    _announce("tree-full", p)
+    rep = lockstep.run_lockstep(p, iterations=50, reload=False)
+    assert rep.ok, rep.summary()
+    assert rep.final_status == oracle.TREE_FULL
+
+
+def test_lockstep_until_goal():
+    from test_oracle_planner import near_goal_problem
+    p = near_goal_problem(1)
+    _announce("goal", p)
+    rep = lockstep.run_lockstep(p, iterations=60, reload=False)
+    assert rep.ok, rep.summary()
+    assert rep.final_status == oracle.SOLVED

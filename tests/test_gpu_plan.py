@@ -1,0 +1,219 @@
+"""GPU end-to-end: kp_plan results replayed in FP64 by the oracle, determinism,
+argument / order errors, forced terminations, and full-size property checks
+(sampled edges re-integrated by the oracle one by one)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import problem_small_di, problem_small_quad, problem_c1, problem_c2
+
+from test_oracle_planner import near_goal_problem, check_invariants, expected_controls
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def planner(p, **kw):
+    from paper_2409_06807_amd import Planner
+    return Planner(p, device="cuda:0", **kw)
+
+
+def tree_for_invariants(g):
+    s = dict(g)
+    s["sample"] = s["sample"].astype(np.int32)
+    s["sample"][0] = -1
+    s["sum_lanes"] = None
+    return s
+
+
+def check_gpu_invariants(p, g, stats):
+    s = tree_for_invariants(g)
+    s["sum_lanes"] = int(stats["lanes_total"])
+    check_invariants(p, s)
+
+
+def check_sampled_edges(p, g, n_samples=400, seed=0):
+    """Every sampled edge: the child equals the FP64 re-integration of its
+    stored parent under the stored control (within 1e-5 relative), the control
+    equals the Philox map of (birth, parent, sample), and the segment is valid
+    in FP64 unless the oracle marks it ambiguous."""
+    N = g["N"]
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(np.arange(1, N), size=min(n_samples, N - 1), replace=False)
+    K = int(p["steps"])
+    m = 3 if int(p["dynamics"]) == 0 else 4
+    worst = 0.0
+    for i in idx:
+        par = int(g["parent"][i])
+        assert 0 <= par < i
+        u = g["u"][i]
+        want_u = expected_controls(p, int(g["birth"][i]), par, int(g["sample"][i]), m)
+        assert np.array_equal(u.view(np.uint32), want_u.view(np.uint32)), f"control of node {i}"
+        x = g["x"][par].astype(np.float64)
+        traj = [x]
+        for _ in range(K):
+            x = oracle.step(p, x, u.astype(np.float64))
+            traj.append(x)
+        err = np.max(np.abs(g["x"][i] - x) / np.maximum(1.0, np.abs(x)))
+        worst = max(worst, err)
+        assert err <= 1e-5, f"node {i}: rel err {err:.2e}"
+        # validity with the ambiguity band: the strict test may fail only if
+        # the loose one passes everywhere
+        loose_ok = all(oracle.state_ok(p, traj[j], relax=1e-4) and
+                       not oracle.swept_hit(p, traj[j - 1], traj[j],
+                                            float(np.float32(p["margin"])) - 1e-4)
+                       for j in range(1, K + 1))
+        assert loose_ok, f"node {i}: segment invalid in FP64"
+    return worst
+
+
+def test_plan_replays_in_fp64():
+    for seed in range(3):
+        p = near_goal_problem(seed)
+        _say(f"plan near-goal seed={seed}")
+        G = planner(p)
+        r = G.plan()
+        assert r["status"] == oracle.SOLVED, r
+        g = G.copy_tree()
+        path = G.path(r["goal_id"])
+        assert path[0] == 0 and path[-1] == r["goal_id"] and len(path) == r["path_len"]
+        assert np.all(g["parent"][path[1:]] == path[:-1])
+        ctl = g["u"][path[1:]]
+        valid, reached, ends = oracle.replay(p, g["x"][0].astype(np.float64), ctl, margin=0.0)
+        assert valid and reached
+        np.testing.assert_allclose(ends, g["x"][path[1:]], rtol=0, atol=1e-3)
+        check_gpu_invariants(p, g, G.stats())
+        check_sampled_edges(p, g, 200, seed)
+        G.close()
+
+
+def test_plan_matches_oracle_plan():
+    # identical inputs: unless an ambiguous decision occurred, the GPU plan
+    # reaches the same goal node as the oracle's free run
+    p = near_goal_problem(2)
+    _say("plan vs oracle near-goal seed=2")
+    O = oracle.OraclePlanner(p)
+    st, goal, iters = O.plan()
+    G = planner(p)
+    r = G.plan()
+    assert r["status"] == st == oracle.SOLVED
+    assert r["iterations"] == iters
+    assert r["goal_id"] == goal
+    so = O.state()
+    g = G.copy_tree()
+    assert g["N"] == so["N"]
+    assert np.array_equal(g["parent"], so["parent"])
+
+
+def test_determinism_and_reset():
+    p = problem_small_quad(seed=3, cap=20000, n_obs=60, max_iters=6)
+    _say("determinism quad")
+    G = planner(p)
+    r1 = G.plan()
+    t1 = G.copy_tree()
+    G.reset(p["seed"])
+    r2 = G.plan()
+    t2 = G.copy_tree()
+    assert r1["iterations"] == r2["iterations"] and r1["n_nodes"] == r2["n_nodes"]
+    for k in ("x", "u", "parent", "cell", "flag", "nv", "ni", "visited", "thr"):
+        assert np.array_equal(t1[k], t2[k]), k
+    # iterations per status read do not change results
+    H = planner(p, iters_per_sync=4)
+    r3 = H.plan()
+    t3 = H.copy_tree()
+    assert r3["n_nodes"] == r1["n_nodes"]
+    for k in ("x", "parent", "flag", "thr"):
+        assert np.array_equal(t1[k], t3[k]), k
+    G.reset(p["seed"] + 1)
+    r4 = G.plan()
+    assert G.copy_tree()["N"] != t1["N"] or not np.array_equal(G.copy_tree()["x"], t1["x"])
+
+
+def test_errors_and_order():
+    from paper_2409_06807_amd import KPError, E_START_INVALID, E_GOAL_INVALID, E_ORDER
+    p = problem_small_di()
+    p["obstacles"] = np.vstack([p["obstacles"], np.array([[4, 4, 4, 6, 6, 6]], np.float32)])
+    with pytest.raises(KPError) as e:
+        planner(p)
+    assert e.value.code == E_START_INVALID
+    p = problem_small_di()
+    p["obstacles"] = np.vstack([p["obstacles"], np.array([[93, 93, 93, 97, 97, 97]], np.float32)])
+    with pytest.raises(KPError) as e:
+        planner(p)
+    assert e.value.code == E_GOAL_INVALID
+    G = planner(problem_small_di())
+    with pytest.raises(KPError) as e:
+        G.update_tree()
+    assert e.value.code == E_ORDER
+    with pytest.raises(KPError) as e:
+        G.update_regions()
+    assert e.value.code == E_ORDER
+    G.expand()
+    with pytest.raises(KPError) as e:
+        G.expand()
+    assert e.value.code == E_ORDER
+
+
+def test_forced_terminations():
+    p = problem_small_di(cap=60)
+    _say("tree full cap=60")
+    r = planner(p).plan()
+    assert r["status"] == oracle.TREE_FULL and r["n_nodes"] <= 60
+    p = problem_small_di()
+    p["goal_center"] = np.array([7, 7, 7], np.float32)
+    p["goal_radius"] = np.float32(4.0)
+    p["obstacles"] = np.zeros((0, 6), np.float32)
+    r = planner(p).plan()
+    assert r["status"] == oracle.SOLVED and r["goal_id"] == 0 and r["iterations"] == 0
+    p = problem_small_quad(cap=2000, max_iters=5)
+    prm = np.array(p["dyn_params"], np.float32)
+    prm[0] = np.nan
+    p["dyn_params"] = prm
+    G = planner(p)
+    r = G.plan()
+    s = G.stats()
+    assert r["status"] == oracle.TIMEOUT and r["n_nodes"] == 1
+    assert s["valid_total"] == 0 and s["invalid_total"] == s["lanes_total"] > 0
+    p = problem_small_di(t_max_ms=0.0)
+    r = planner(p).plan()
+    assert r["status"] == oracle.TIMEOUT and r["iterations"] == 0
+
+
+def test_c1_full_config_properties():
+    p = problem_c1(seed=0)
+    _say("c1 full config")
+    G = planner(p)
+    r = G.plan()
+    g = G.copy_tree()
+    stats = G.stats()
+    assert stats["device_error"] == 0
+    check_gpu_invariants(p, g, stats)
+    check_sampled_edges(p, g, 500)
+    # thresholds equal the oracle's estimates on the GPU's own counts
+    e = oracle.estimates(g["avail"], g["nv"], g["ni"], g["visited"], p["delta"], p["epsilon"])
+    # (the last UpdateEstimates ran before the last admission, so compare on
+    # the regions whose counts and coverage it saw: recompute is exact only
+    # when no new region appeared; check Lemma 1 everywhere instead)
+    assert np.all(g["thr"] >= np.uint64(int(np.floor(p["epsilon"] * 2**32))))
+
+
+@pytest.mark.parametrize("iters", [8])
+def test_c2_full_size_properties(iters):
+    p = problem_c2(seed=0, max_iters=iters)
+    _say(f"c2 full size, {iters} iterations")
+    G = planner(p)
+    r = G.plan()
+    g = G.copy_tree()
+    stats = G.stats()
+    assert stats["device_error"] == 0
+    assert r["iterations"] == iters or r["status"] != oracle.TIMEOUT
+    check_gpu_invariants(p, g, stats)
+    worst = check_sampled_edges(p, g, 300)
+    print(f"c2: N={g['N']} iterations={r['iterations']} worst edge rel err {worst:.2e}")
