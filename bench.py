@@ -1,0 +1,187 @@
+"""Bench: Kino-PAX planning on one MI355X.
+
+A step is one full planning query (Alg. 1 from initialisation to a goal node,
+a full tree or the time budget) on the 12D quadcopter forest workload, with a
+different planner seed per step.  The timed region covers K queries back to
+back; inputs (problem, obstacles, workspace) are resident on the GPU before it
+starts.
+
+Prints one JSON line: value = valid expansions per second over the whole
+timed region (sum of n_valid increments / wall time), plus the median
+time-to-solution over solved queries, a roofline entry for the dominant
+kernel (propagation, ALU-bound) from HIP-event kernel durations, and the CPU
+oracle's throughput on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "median time-to-solution (ms) + valid expansions/s; learned vs uniform proposal"
+
+# Algorithmic work model of the propagation kernel (counted from the
+# formulas, not from the compiled code): FP32 operations per integration step
+# (a fused multiply-add counts 2, a sin or cos 1, a compare 1), per swept-box
+# test against one obstacle, and integer operations per Philox4x32-10 block.
+STEP_OPS = {
+    # quadcopter RK4: 4 derivatives x 43 + stage/combination 156 + state box 24 + swept box 12
+    (1, 1): 4 * 43 + 156 + 24 + 12,
+    # double integrator Euler: 6 FMA (12) + state box 12 + swept box 12
+    (0, 0): 12 + 12 + 12,
+    # double integrator RK4: 3 stages x 12 + 12 x 2 accum + 12 x 3 final + 12 + 12
+    (0, 1): 36 + 24 + 36 + 12 + 12,
+    (1, 0): 43 + 24 + 24 + 12,
+}
+BOX_TEST_OPS = 6
+PHILOX_OPS = 100
+PEAK_FP32_TFLOPS = 157.3
+
+
+def gpu_workload(name: str, seed: int = 0):
+    from workloads import problem_c1, problem_c2, problem_c5
+    return {"c1": problem_c1, "c2": problem_c2, "c5": problem_c5}[name](seed=seed)
+
+
+def run_cpu_baseline(name: str, iters: int):
+    """The CPU oracle as it stands, single-threaded, on the first `iters`
+    iterations of seed 0 of the same workload."""
+    import oracle
+    p = gpu_workload(name, 0)
+    P = oracle.OraclePlanner(p)
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(iters):
+        st, g = P.iterate()
+        done += 1
+        if st != oracle.OK:
+            break
+    dt = time.perf_counter() - t0
+    s = P.state(copy=False)
+    nv = int(s["nv"].sum())
+    return {
+        "value": nv / dt, "unit": "valid expansions/s", "cores": 1, "kind": "oracle",
+        "sample": f"{p['name']} seed 0, first {done} iterations: {s['sum_lanes']} expansions, "
+                  f"{nv} valid, |T| = {s['N']}, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters-per-sync", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_06807_amd import Planner, SOLVED
+
+    p = gpu_workload(args.workload, 0)
+    G = Planner(p, device="cuda:0", iters_per_sync=args.iters_per_sync)
+    dyn, integ = int(p["dynamics"]), int(p["integrator"])
+
+    for s in range(args.warmup):
+        G.reset(10_000 + s)
+        G.plan()
+    torch.cuda.synchronize()
+
+    results = []
+    per_ms = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        a = time.perf_counter()
+        G.reset(s)
+        r = G.plan()
+        per_ms.append((time.perf_counter() - a) * 1e3)
+        results.append(r)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    valid = sum(r["valid_total"] for r in results)
+    lanes = sum(r["lanes_total"] for r in results)
+    solved = [ms for ms, r in zip(per_ms, results) if r["status"] == SOLVED]
+
+    # per-kernel HIP-event durations on the planner's stream (separate pass)
+    G.set_profiling(True)
+    steps_tot = box_tot = lanes_prof = 0
+    for s in range(args.profile_steps):
+        G.reset(s)
+        G.plan()
+        st = G.stats()
+        steps_tot += st["steps_total"]
+        box_tot += st["box_tests_total"]
+        lanes_prof += st["lanes_total"]
+    kt = G.kernel_times()
+    G.set_profiling(False)
+    n_launch, prop_ms = kt["propagate"]
+    philox_per_lane = 2 if dyn == 1 else 1
+    ops = steps_tot * STEP_OPS[(dyn, integ)] + box_tot * BOX_TEST_OPS + \
+        lanes_prof * philox_per_lane * PHILOX_OPS
+    achieved = ops / (prop_ms * 1e-3) / 1e12 if prop_ms > 0 else 0.0
+
+    line = {
+        "metric": METRIC,
+        "value": valid / elapsed,
+        "unit": "valid expansions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": p["name"],
+            "dynamics": "12D quadcopter RK4 h=0.02 x 20" if dyn == 1 else "6D double integrator",
+            "obstacles": int(len(p["obstacles"])),
+            "regions": list(p["grid"]),
+            "node_cap": int(p["node_cap"]),
+            "lambda_max": int(p["lambda_max"]),
+            "query": "one planning query per step, planner seeds 0..steps-1",
+        },
+        "median_tts_ms": statistics.median(solved) if solved else None,
+        "mean_tts_ms": statistics.mean(solved) if solved else None,
+        "success_rate": len(solved) / len(results),
+        "attempted_expansions_per_s": lanes / elapsed,
+        "statuses": [r["status"] for r in results],
+        "iterations": [r["iterations"] for r in results],
+        "roofline": {
+            "kernel": "k_propagate",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "launches": n_launch,
+            "avg_launch_ms": prop_ms / n_launch if n_launch else None,
+            "ops_per_launch": ops / n_launch if n_launch else None,
+        },
+        "kernel_ms": {k: v[1] for k, v in kt.items()},
+        "kernel_launches": {k: v[0] for k, v in kt.items()},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_iters)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

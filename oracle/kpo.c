@@ -703,6 +703,24 @@ int32_t kpo_replay(const kpo_problem* pb, const double* x0, int32_t n_edges, con
   return valid;
 }
 
+/* Integrate n_seg segments in FP64: segment i starts at x0[i] (n values),
+ * holds control u[i] (m FP32 values) and runs steps[i] integration steps;
+ * the end state goes to out[i].  A plain primitive used to re-check edges. */
+void kpo_integrate_batch(const kpo_problem* pb, int64_t n_seg, const double* x0, const float* u,
+                         const int32_t* steps, double* out) {
+  const int n = state_dim(pb->dyn), m = ctrl_dim(pb->dyn);
+  for (int64_t i = 0; i < n_seg; ++i) {
+    double x[12], xn[12], uu[4] = {0, 0, 0, 0};
+    memcpy(x, x0 + (size_t)i * n, sizeof(double) * n);
+    for (int j = 0; j < m; ++j) uu[j] = (double)u[(size_t)i * m + j];
+    for (int k = 0; k < steps[i]; ++k) {
+      kpo_step(pb, x, uu, xn);
+      memcpy(x, xn, sizeof(double) * n);
+    }
+    memcpy(out + (size_t)i * n, x, sizeof(double) * n);
+  }
+}
+
 void kpo_get_view(kpo_planner* P, kpo_view* v) {
   v->n = P->n; v->m = P->m; v->R = P->R; v->cap = P->pb.cap;
   v->N = P->N; v->it = P->it; v->nF = P->nF; v->lambda = P->lambda; v->nU = P->nU;

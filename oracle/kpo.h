@@ -108,6 +108,9 @@ int32_t kpo_path(const kpo_planner* P, int32_t node, int32_t* ids, int32_t cap);
 int32_t kpo_replay(const kpo_problem* pb, const double* x0, int32_t n_edges, const float* controls,
                    double margin, double* end_states, int32_t* reached_goal);
 
+void kpo_integrate_batch(const kpo_problem* pb, int64_t n_seg, const double* x0, const float* u,
+                         const int32_t* steps, double* out);
+
 /* --- state access (arrays owned by the planner) --- */
 typedef struct {
   int32_t n, m, R, cap;

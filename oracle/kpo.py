@@ -116,6 +116,7 @@ def lib():
         L.kpo_replay.argtypes = [C.POINTER(Problem), vp, C.c_int32, vp, C.c_double, vp,
                                  C.POINTER(C.c_int32)]
         L.kpo_replay.restype = C.c_int32
+        L.kpo_integrate_batch.argtypes = [C.POINTER(Problem), C.c_int64, vp, vp, vp, vp]
         L.kpo_get_view.argtypes = [P, C.POINTER(View)]
         L.kpo_set_counters.argtypes = [P, C.c_int32, C.c_int32]
         _lib = L
@@ -242,6 +243,17 @@ def estimates(avail, nv, ni, visited, delta, eps):
     lib().kpo_estimates(R, _ptr(avail), _ptr(nv), _ptr(ni), _ptr(visited), float(delta),
                         float(eps), _ptr(score), _ptr(q), _ptr(P), _ptr(thr))
     return dict(score=score, q=q, P=P, thr=thr)
+
+
+def integrate_batch(p, x0, u, steps):
+    """FP64 end states of segments (x0[i], u[i], steps[i])."""
+    pb = _PB(p)
+    x0 = np.ascontiguousarray(np.asarray(x0, np.float64).reshape(-1, pb.n))
+    u = np.ascontiguousarray(np.asarray(u, np.float32).reshape(-1, pb.m))
+    steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, np.int32), (len(x0),)))
+    out = np.zeros_like(x0)
+    lib().kpo_integrate_batch(C.byref(pb.s), len(x0), _ptr(x0), _ptr(u), _ptr(steps), _ptr(out))
+    return out
 
 
 def replay(p, x0, controls, margin=0.0):

@@ -78,9 +78,12 @@ def admissible_cells(p, x, tol=oracle.kpo.AMB_TOL):
     return cells
 
 
-def compare_expansion(p, W, recs, tr, rep, it):
+def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
     """Per-lane comparison; returns the records with admissible GPU outcomes
-    substituted where the oracle marked the decision ambiguous."""
+    substituted where the oracle marked the decision ambiguous.  gpu_prev: the
+    GPU's own tree before this expansion, when it continues from its own FP32
+    states; child states are then checked edge by edge against the FP64
+    re-integration of the GPU's stored parent."""
     K = int(p["steps"])
     m = W.m
     n = W.n
@@ -117,9 +120,16 @@ def compare_expansion(p, W, recs, tr, rep, it):
         merged["goal"][k] = 1 if (merged["valid"][k] and gd <= float(np.float32(p["goal_radius"]))) else 0
         rep.adopted += 1
     same = o_fail == g_fail
-    # states where the stop step agrees
     idx = np.nonzero(same)[0]
-    if len(idx):
+    if gpu_prev is not None:
+        ref = oracle.integrate_batch(p, gpu_prev["x"][tr["parent"]].astype(np.float64),
+                                     tr["u"][:, :m], tr["steps"])
+        e = rel_err(tr["x"][:, :n], ref)
+        rep.max_rel_err = max(rep.max_rel_err, e)
+        if e > REL_TOL:
+            rep.fail(f"it{it}: edge re-integration rel err {e:.2e}")
+    elif len(idx):
+        # states where the stop step agrees
         e = rel_err(tr["x"][idx, :n], recs["x"][idx, :n])
         rep.max_rel_err = max(rep.max_rel_err, e)
         if e > REL_TOL:
@@ -146,7 +156,7 @@ def compare_expansion(p, W, recs, tr, rep, it):
     return merged
 
 
-def compare_state(p, W, g, rep, it, where):
+def compare_state(p, W, g, rep, it, where, gpu_prev=None):
     s = W.state()
     N = s["N"]
     if g["N"] != N:
@@ -167,6 +177,12 @@ def compare_state(p, W, g, rep, it, where):
     ou = np.ascontiguousarray(s["u"][1:N], np.float32).view(np.uint32)
     if not np.array_equal(gu, ou):
         rep.fail(f"it{it} {where}: stored controls differ")
+    if gpu_prev is not None:
+        # old nodes keep their states; new ones were checked edge by edge
+        N0 = gpu_prev["N"]
+        if not np.array_equal(g["x"][:N0], gpu_prev["x"][:N0]):
+            rep.fail(f"it{it} {where}: stored states of old nodes changed")
+        return
     e = rel_err(g["x"][:N], s["x"][:N])
     rep.max_rel_err = max(rep.max_rel_err, e)
     if e > REL_TOL:
@@ -186,12 +202,14 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
     if G is None:
         G = Planner(p, device=device)
     trace = G.trace_buffer()
+    gpu_prev = None
     for it in range(iterations):
         if W.state(copy=False)["goal_id"] >= 0:
             rep.final_status = oracle.SOLVED
             break
         if reload or it == 0:
             G.load_tree(gpu_state_from_oracle(W.state()))
+            gpu_prev = None
         st = W.frontier()
         gs = G.stats()
         if gs["n_frontier"] != W.state(copy=False)["nF"] or gs["lam"] != W.state(copy=False)["lam"]:
@@ -207,7 +225,7 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
         G.expand(trace)
         torch.cuda.synchronize()
         tr = G.trace(trace, len(recs))
-        merged = compare_expansion(p, W, recs, tr, rep, it)
+        merged = compare_expansion(p, W, recs, tr, rep, it, gpu_prev)
         W.apply(merged)
         g = G.copy_tree()
         if g["N"] != W.state(copy=False)["N"] + W.view().nU:
@@ -220,7 +238,9 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
         W.update_node_sets()
         G.update_tree()
         g = G.copy_tree()
-        compare_state(p, W, g, rep, it, "after UpdateNodeSets")
+        compare_state(p, W, g, rep, it, "after UpdateNodeSets", gpu_prev)
+        if not reload:
+            gpu_prev = g
         gs = G.stats()
         og = W.state(copy=False)["goal_id"]
         if gs["goal_id"] != og:
