@@ -50,15 +50,25 @@ def gpu_workload(name: str, seed: int = 0):
     return {"c1": problem_c1, "c2": problem_c2, "c5": problem_c5}[name](seed=seed)
 
 
-def run_cpu_baseline(name: str, iters: int):
-    """The CPU oracle as it stands, single-threaded, on the first `iters`
-    iterations of seed 0 of the same workload."""
+def run_cpu_baseline(name: str, budget_s: float):
+    """The CPU oracle as it stands, single-threaded, on the leading iterations
+    of seed 0 of the same workload: it stops before the first iteration whose
+    predicted time (its expansion count times the time per expansion so far)
+    would overrun the budget."""
     import oracle
     p = gpu_workload(name, 0)
     P = oracle.OraclePlanner(p)
     t0 = time.perf_counter()
     done = 0
-    for _ in range(iters):
+    while True:
+        if P.frontier() != oracle.OK:
+            break
+        lanes_next = P.num_lanes()
+        spent = time.perf_counter() - t0
+        lanes_so_far = P.state(copy=False)["sum_lanes"]
+        per_lane = spent / lanes_so_far if lanes_so_far else 0.0
+        if done > 0 and spent + lanes_next * per_lane > budget_s:
+            break
         st, g = P.iterate()
         done += 1
         if st != oracle.OK:
@@ -80,9 +90,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--profile-steps", type=int, default=2)
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters-per-sync", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy (a kernel of known "
+                         "traffic, used to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
@@ -91,6 +104,13 @@ def main():
 
     import torch
     from paper_2409_06807_amd import Planner, SOLVED
+
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     p = gpu_workload(args.workload, 0)
     G = Planner(p, device="cuda:0", iters_per_sync=args.iters_per_sync)
@@ -179,7 +199,7 @@ def main():
         "kernel_launches": {k: v[0] for k, v in kt.items()},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_iters)
+        line["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_budget_s)
     print(json.dumps(line))
 
 

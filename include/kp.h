@@ -254,7 +254,7 @@ kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, in
 /* Per-kernel timing with HIP events on the handle's stream (0 = off).  While
  * on, every kernel launch is bracketed by two events; totals accumulate until
  * the next call with on = 1.  kp_kernel_times fills, for kernel index k
- * (0 propagate, 1 region estimates, 2 node sets, 3 frontier), the launch
+ * (0 propagate, 1 region estimates, 2 node sets, 3 frontier, 4 V_U commit), the launch
  * count and the summed duration in milliseconds.  Synchronises. */
 kp_status kp_set_profiling(kp_problem* h, int32_t on);
 kp_status kp_kernel_times(kp_problem* h, int32_t kernel, int64_t* launches, double* total_ms);

@@ -18,14 +18,15 @@ using namespace kp;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kProfKernels = 4;  // propagate, region, node sets, frontier
+constexpr int kProfKernels = 5;  // propagate, region, node sets, frontier, commit
 constexpr int kEventPool = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-  size_t ctl, x, u, parent, cell, flag, birth, sample, F;
+  size_t ctl, env, x, u, parent, cell, flag, birth, sample, F;
   size_t nv, ni, visited, thr, avail, obs, st_front, st_nodes, st_prop, path;
+  size_t sx, su, scell, slane, scount;
   size_t total;
   int capP, tiles_node, tiles_prop;
 };
@@ -83,6 +84,7 @@ Layout make_layout(const kp_problem_desc* d) {
     return o;
   };
   L.ctl = take(sizeof(Ctl));
+  L.env = take(sizeof(Env));
   L.x = take(capP * n * 4);
   L.u = take(capP * m * 4);
   L.parent = take(capP * 4);
@@ -101,6 +103,11 @@ Layout make_layout(const kp_problem_desc* d) {
   L.st_nodes = take((size_t)L.tiles_node * 8);
   L.st_prop = take((size_t)L.tiles_prop * 8);
   L.path = take((size_t)(kMaxPath + 1) * 4);
+  L.sx = take(capP * n * 4);
+  L.su = take(capP * m * 4);
+  L.scell = take(capP * 4);
+  L.slane = take(capP * 4);
+  L.scount = take((size_t)L.tiles_prop * 4);
   L.total = off;
   return L;
 }
@@ -124,6 +131,8 @@ struct kp_problem {
   std::vector<float> obs;  // row-major copy
   Params prm;
   Dev dev;
+  Env* env_dev;  // device copy of {prm, dev} read by the kernels
+  Env env_host;
   Layout L;
   hipStream_t stream;
   int n, m, R;
@@ -230,6 +239,7 @@ void carve(kp_problem* h, void* ws) {
   const Layout& L = h->L;
   Dev& v = h->dev;
   v.ctl = reinterpret_cast<Ctl*>(b + L.ctl);
+  h->env_dev = reinterpret_cast<Env*>(b + L.env);
   v.x = reinterpret_cast<float*>(b + L.x);
   v.u = reinterpret_cast<float*>(b + L.u);
   v.parent = reinterpret_cast<int32_t*>(b + L.parent);
@@ -248,6 +258,11 @@ void carve(kp_problem* h, void* ws) {
   v.st_nodes = reinterpret_cast<unsigned long long*>(b + L.st_nodes);
   v.st_prop = reinterpret_cast<unsigned long long*>(b + L.st_prop);
   v.path = reinterpret_cast<int32_t*>(b + L.path);
+  v.sx = reinterpret_cast<float*>(b + L.sx);
+  v.su = reinterpret_cast<float*>(b + L.su);
+  v.scell = reinterpret_cast<uint32_t*>(b + L.scell);
+  v.slane = reinterpret_cast<uint32_t*>(b + L.slane);
+  v.scount = reinterpret_cast<uint32_t*>(b + L.scount);
   v.capP = L.capP;
   v.tiles_node = L.tiles_node;
   v.tiles_prop = L.tiles_prop;
@@ -291,7 +306,7 @@ kp_status do_frontier(kp_problem* h) {
   int grid = tiles < h->grid_node_max ? tiles : h->grid_node_max;
   if (grid < 1) grid = 1;
   const int pk = prof_begin(h, 3);
-  hipError_t e = launch_frontier(h->prm, h->dev, grid, h->stream);
+  hipError_t e = launch_frontier(h->env_dev, grid, h->stream);
   prof_end(h, pk);
   if (e != hipSuccess) return hip_fail(h, e, "frontier launch");
   return KP_OK;
@@ -304,16 +319,23 @@ kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub) {
   int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
   if (grid < 1) grid = 1;
   const int pk = prof_begin(h, 0);
-  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm, h->dev, trace,
+  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->env_dev,
+                                  h->desc.n_obstacles, trace,
                                   grid, h->stream);
   prof_end(h, pk);
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
+  int cgrid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
+  if (cgrid < 1) cgrid = 1;
+  const int ck = prof_begin(h, 4);
+  e = launch_commit(h->env_dev, trace, cgrid, h->stream);
+  prof_end(h, ck);
+  if (e != hipSuccess) return hip_fail(h, e, "commit launch");
   return KP_OK;
 }
 
 kp_status do_region(kp_problem* h) {
   const int pk = prof_begin(h, 1);
-  hipError_t e = launch_region(h->prm, h->dev, h->stream);
+  hipError_t e = launch_region(h->env_dev, h->stream);
   prof_end(h, pk);
   if (e != hipSuccess) return hip_fail(h, e, "region launch");
   return KP_OK;
@@ -324,18 +346,28 @@ kp_status do_nodesets(kp_problem* h, long long nodes_ub) {
   int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
   if (grid < 1) grid = 1;
   const int pk = prof_begin(h, 2);
-  hipError_t e = launch_nodesets(h->prm, h->dev, grid, h->stream);
+  hipError_t e = launch_nodesets(h->env_dev, grid, h->stream);
   prof_end(h, pk);
   if (e != hipSuccess) return hip_fail(h, e, "node sets launch");
   return KP_OK;
 }
 
+// copy {prm, dev} to the device (stream-ordered; the host copy lives in the
+// handle, and callers synchronise before returning)
+hipError_t upload_env(kp_problem* h) {
+  h->env_host.p = h->prm;
+  h->env_host.d = h->dev;
+  return hipMemcpyAsync(h->env_dev, &h->env_host, sizeof(Env), hipMemcpyHostToDevice, h->stream);
+}
+
 kp_status init_state(kp_problem* h) {
-  hipError_t e = launch_zero(h->prm, h->dev, h->stream);
+  hipError_t e = upload_env(h);
+  if (e != hipSuccess) return hip_fail(h, e, "environment upload");
+  e = launch_zero(h->prm, h->dev, h->env_dev, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "zero launch");
   Vec12 xi;
   for (int k = 0; k < 12; ++k) xi.v[k] = h->desc.x_init[k];
-  e = launch_root(h->prm, h->dev, xi, h->stream);
+  e = launch_root(h->env_dev, xi, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "root launch");
   kp_status st = do_frontier(h);
   if (st != KP_OK) return st;
@@ -664,7 +696,7 @@ kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in) {
   if (e == hipSuccess) e = hipMemcpyAsync(h->dev.thr, in->thr, R * 8, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "tree load");
-  e = launch_set_ctl(h->dev, N, in->iteration, h->stream);
+  e = launch_set_ctl(h->env_dev, N, in->iteration, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "control load");
   kp_status st = do_frontier(h);
   if (st != KP_OK) return st;
@@ -677,7 +709,7 @@ kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, in
   kp_status st = sync_ctl(h);
   if (st != KP_OK) return st;
   if (node < 0 || node >= h->hctl->N) return fail(h, KP_E_ARG, "kp_get_path: node out of range");
-  hipError_t e = launch_path(h->dev, node, h->stream);
+  hipError_t e = launch_path(h->env_dev, node, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "path launch");
   int32_t n = 0;
   e = hipMemcpyAsync(&n, h->dev.path, 4, hipMemcpyDeviceToHost, h->stream);

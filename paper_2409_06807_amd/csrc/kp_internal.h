@@ -9,7 +9,8 @@ namespace kp {
 
 constexpr int kPropBlock = 256;      // lanes per propagate tile (4 waves)
 constexpr int kNodeBlock = 256;      // threads per node-pass block
-constexpr int kNodeTile = 1024;      // nodes per node-pass tile (4 per thread)
+constexpr int kNodesPerThread = 16;  // nodes per thread in the node passes
+constexpr int kNodeTile = 4096;      // nodes per node-pass tile
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
 constexpr int kMaxPath = 65536;      // longest path kp_get_path can return
 constexpr int kDoneNone = 0;
@@ -31,7 +32,7 @@ struct alignas(256) Ctl {
   uint32_t bd_front, bd_prop, bd_nodes;   // blocks finished (last-block finalisation)
   uint32_t err;       // nonzero: a look-back wait hit its spin limit
   uint32_t iters_done;
-  uint32_t pad0;
+  uint32_t tk_commit, bd_commit;
   unsigned long long lanes_total, valid_total, invalid_total, steps_total, box_total;
 };
 
@@ -74,6 +75,12 @@ struct Dev {
   unsigned long long* st_front;  // look-back status, one word per tile
   unsigned long long* st_prop;
   unsigned long long* st_nodes;
+  // accepted samples staged per propagate tile: slot = tile * kPropBlock + rank
+  float* sx;           // [n][capP]
+  float* su;           // [m][capP]
+  uint32_t* scell;     // [capP]
+  uint32_t* slane;     // [capP] lane index << 1 | goal bit
+  uint32_t* scount;    // [tiles_prop] accepted samples per tile
   int32_t* path;       // [kMaxPath + 1]
   int32_t capP;        // padded node capacity (multiple of kNodeTile)
   int32_t tiles_node;  // entries of st_front / st_nodes
@@ -91,17 +98,26 @@ struct TraceRec {
 };
 static_assert(sizeof(TraceRec) == 96, "trace record layout");
 
+// Everything a kernel needs besides per-launch arguments; lives in device
+// memory (start of the workspace) so kernels read it through one pointer
+// with scalar loads instead of holding a large by-value argument in registers.
+struct Env {
+  Params p;
+  Dev d;
+};
+
 // Launchers (kp_kernels.hip).  Each returns the hipError_t of the launch.
-hipError_t launch_zero(const Params& p, const Dev& d, hipStream_t s);
 struct Vec12 { float v[12]; };
-hipError_t launch_root(const Params& p, const Dev& d, Vec12 x_init, hipStream_t s);
-hipError_t launch_frontier(const Params& p, const Dev& d, int grid, hipStream_t s);
-hipError_t launch_propagate(int dyn, int integ, const Params& p, const Dev& d, TraceRec* trace,
+hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s);
+hipError_t launch_root(const Env* env, Vec12 x_init, hipStream_t s);
+hipError_t launch_frontier(const Env* env, int grid, hipStream_t s);
+hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
                             int grid, hipStream_t s);
-hipError_t launch_region(const Params& p, const Dev& d, hipStream_t s);
-hipError_t launch_nodesets(const Params& p, const Dev& d, int grid, hipStream_t s);
-hipError_t launch_path(const Dev& d, int32_t node, hipStream_t s);
-hipError_t launch_set_ctl(const Dev& d, int32_t N, int32_t it, hipStream_t s);
+hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s);
+hipError_t launch_region(const Env* env, hipStream_t s);
+hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s);
+hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
+hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
 int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
 size_t propagate_lds_bytes(int n_obs);

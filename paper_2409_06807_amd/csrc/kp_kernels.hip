@@ -52,50 +52,68 @@ __device__ __forceinline__ double wave_max_f64(double v) {
   return v;
 }
 
-// Exclusive prefix of small per-lane counts (0..7) across the wave from three
+// Exclusive prefix of small per-lane counts (0..31) across the wave from five
 // ballots of the count's bit planes.
 __device__ __forceinline__ uint32_t wave_excl_small(uint32_t c, uint32_t* total) {
-  const unsigned long long b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
   const unsigned long long lo = lanes_below();
-  *total = __popcll(b0) + 2u * __popcll(b1) + 4u * __popcll(b2);
-  return __popcll(b0 & lo) + 2u * __popcll(b1 & lo) + 4u * __popcll(b2 & lo);
+  uint32_t ex = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const unsigned long long m = __ballot((c >> b) & 1u);
+    ex += (uint32_t)__popcll(m & lo) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  *total = tot;
+  return ex;
 }
 
 // Decoupled look-back over per-tile status words: (30-bit epoch tag | 2-bit
-// flag | 32-bit value); flag 1 = tile aggregate, 2 = inclusive prefix.  A tile
-// only waits for tiles with smaller tickets, all held by running blocks, so
-// the wait always ends; the spin bound only guards against a broken invariant.
-__device__ uint32_t lookback_prefix(unsigned long long* st, uint32_t tile, uint32_t agg,
-                                    uint32_t epoch, uint32_t* err) {
+// flag | 32-bit value); flag 1 = tile aggregate, 2 = inclusive prefix.  Run by
+// one whole wave: lane l inspects tile (t - 1 - l), so one probe covers 64
+// predecessors; the nearest inclusive prefix ends the walk.  A tile only waits
+// for tiles with smaller tickets, all held by running blocks, so the wait
+// always ends; the spin bound only guards against a broken invariant.
+__device__ uint32_t lookback_prefix_wave(unsigned long long* st, uint32_t tile, uint32_t agg,
+                                         uint32_t epoch, uint32_t* err) {
   const unsigned long long tag = (unsigned long long)(epoch & 0x3fffffffu) << 34;
+  const int lane = (int)__lane_id();
   if (tile == 0) {
-    __hip_atomic_store(&st[0], tag | (2ull << 32) | agg, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+      __hip_atomic_store(&st[0], tag | (2ull << 32) | agg, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     return 0u;
   }
-  __hip_atomic_store(&st[tile], tag | (1ull << 32) | agg, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(&st[tile], tag | (1ull << 32) | agg, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   uint32_t excl = 0;
-  int32_t j = (int32_t)tile - 1;
+  int32_t base = (int32_t)tile - 1;
   uint32_t spins = 0;
-  while (j >= 0) {
-    const unsigned long long w =
-        __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const int32_t j = base - lane;
+    unsigned long long w = tag | (2ull << 32);  // before tile 0: an empty prefix
+    if (j >= 0) w = __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t fl = (uint32_t)(w >> 32) & 3u;
-    if ((uint32_t)(w >> 34) != (epoch & 0x3fffffffu) || fl == 0u) {
+    const bool ready = ((uint32_t)(w >> 34) == (epoch & 0x3fffffffu)) && fl != 0u;
+    const unsigned long long pm = __ballot(ready && fl == 2u);
+    const unsigned long long rm = __ballot(ready);
+    const int limit = pm ? (__ffsll((long long)pm) - 1) : 63;
+    const unsigned long long need = (limit == 63) ? ~0ull : ((1ull << (limit + 1)) - 1ull);
+    if ((rm & need) != need) {
       if (++spins > (1u << 22)) {
-        atomicOr(err, 1u);
+        if (lane == 0) atomicOr(err, 1u);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    excl += (uint32_t)w;
-    if (fl == 2u) break;
-    --j;
+    excl += (uint32_t)wave_sum_u64(lane <= limit ? (unsigned long long)(uint32_t)w : 0ull);
+    if (pm) break;
+    base -= 64;
   }
-  __hip_atomic_store(&st[tile], tag | (2ull << 32) | (unsigned long long)(excl + agg),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(&st[tile], tag | (2ull << 32) | (unsigned long long)(excl + agg),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
 
@@ -123,7 +141,10 @@ __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t*
     off += (k < w) ? t : 0u;
     agg += t;
   }
-  if (threadIdx.x == 0) *s_pref = lookback_prefix(st, tile, agg, epoch, err);
+  if (w == 0) {
+    const uint32_t pre = lookback_prefix_wave(st, tile, agg, epoch, err);
+    if (__lane_id() == 0) *s_pref = pre;
+  }
   __syncthreads();
   *prefix = *s_pref;
   return off;
@@ -193,15 +214,45 @@ __device__ __forceinline__ void deriv<KP_DYN_DI6>(const Params& p, const float* 
   dx[5] = u[2];
 }
 
+// sin and cos without branches for |x| up to ~1e4 (the state box bounds the
+// angles far below that): x = k * pi/2 + r, |r| <= pi/4, with pi/2 split into
+// three FP32 parts (Cody-Waite reduction, each product folded into one fused
+// multiply-add); then the Taylor polynomials of sin (to degree 9) and cos (to
+// degree 10) on [-pi/4, pi/4], whose truncation errors are below 2e-9 and
+// 1.2e-10; the quadrant k mod 4 swaps and negates.  Coefficients are 1/n!
+// rounded to FP32.  Measured against FP64 sin/cos on [-1000, 1000]: at most
+// 1.5 ulp, absolute error below 8e-8.
+__device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
+  const float k = rintf(x * 0x1.45f306p-1f);  // 2/pi
+  float r = __builtin_fmaf(-k, 0x1.921fb6p+0f, x);
+  r = __builtin_fmaf(-k, -0x1.777a5cp-25f, r);
+  r = __builtin_fmaf(-k, -0x1.ee59dap-50f, r);
+  const float r2 = r * r;
+  float ps = __builtin_fmaf(r2, 0x1.71de3ap-19f, -0x1.a01a02p-13f);
+  ps = __builtin_fmaf(r2, ps, 0x1.111112p-7f);
+  ps = __builtin_fmaf(r2, ps, -0x1.555556p-3f);
+  const float sr = __builtin_fmaf(r * r2, ps, r);
+  float pc = __builtin_fmaf(r2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f);
+  pc = __builtin_fmaf(r2, pc, -0x1.6c16c2p-10f);
+  pc = __builtin_fmaf(r2, pc, 0x1.555556p-5f);
+  pc = __builtin_fmaf(r2, pc, -0.5f);
+  const float cr = __builtin_fmaf(r2, pc, 1.0f);
+  const int q = (int)k;
+  const float sv = (q & 1) ? cr : sr;
+  const float cv = (q & 1) ? sr : cr;
+  *s = __uint_as_float(__float_as_uint(sv) ^ (((uint32_t)q & 2u) << 30));
+  *c = __uint_as_float(__float_as_uint(cv) ^ (((uint32_t)(q + 1) & 2u) << 30));
+}
+
 // rigid-body quadcopter, ZYX Euler angles, inertial velocity, body rates
 template <>
 __device__ __forceinline__ void deriv<KP_DYN_QUAD12>(const Params& p, const float* x,
                                                     const float* u, float* dx) {
   float sf, cf, st, ct, sp, cp;
-  sincosf(x[3], &sf, &cf);
-  sincosf(x[4], &st, &ct);
-  sincosf(x[5], &sp, &cp);
-  const float ict = 1.0f / ct;
+  sincos_rr(x[3], &sf, &cf);
+  sincos_rr(x[4], &st, &ct);
+  sincos_rr(x[5], &sp, &cp);
+  const float ict = __builtin_amdgcn_rcpf(ct);  // 1 ulp; |theta| stays far from pi/2
   const float P = x[9], Q = x[10], R = x[11];
   const float a = __builtin_fmaf(Q, sf, R * cf);
   dx[0] = x[6];
@@ -284,7 +335,9 @@ __device__ __forceinline__ uint32_t cell_of(const Params& p, float px, float py,
 // ---------------------------------------------------------------------------
 // k_zero / k_root / k_set_ctl: (re)initialisation, Alg. 1 lines 1-3
 // ---------------------------------------------------------------------------
-__global__ void k_zero(Params p, Dev d) {
+__global__ void k_zero(const Env* __restrict__ env) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
   const int stride = gridDim.x * blockDim.x;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < p.R; r += stride) {
     d.nv[r] = 0ull;
@@ -301,7 +354,9 @@ __global__ void k_zero(Params p, Dev d) {
     d.st_prop[t] = 0ull;
 }
 
-__global__ void k_root(Params p, Dev d, Vec12 xi) {
+__global__ void k_root(const Env* __restrict__ env, Vec12 xi) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctl* c = d.ctl;
   for (int k = 0; k < p.n; ++k) d.x[(size_t)k * d.capP] = xi.v[k];
@@ -325,15 +380,16 @@ __global__ void k_root(Params p, Dev d, Vec12 xi) {
   c->goal_id = in_goal ? 0 : kNoGoal;
   c->done = in_goal ? KP_SOLVED : 0;
   c->epoch = c->epoch + 1u;
-  c->tk_front = c->tk_prop = c->tk_nodes = 0u;
-  c->bd_front = c->bd_prop = c->bd_nodes = 0u;
+  c->tk_front = c->tk_prop = c->tk_nodes = c->tk_commit = 0u;
+  c->bd_front = c->bd_prop = c->bd_nodes = c->bd_commit = 0u;
   c->err = 0u;
   c->iters_done = 0u;
   c->lanes_total = c->valid_total = c->invalid_total = c->steps_total = c->box_total = 0ull;
 }
 
 // state loaded from the host: counters for |T| = N at iteration `it`
-__global__ void k_set_ctl(Dev d, int32_t N, int32_t it) {
+__global__ void k_set_ctl(const Env* __restrict__ env, int32_t N, int32_t it) {
+  const Dev& d = env->d;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctl* c = d.ctl;
   c->N = N;
@@ -345,8 +401,8 @@ __global__ void k_set_ctl(Dev d, int32_t N, int32_t it) {
   c->goal_id = kNoGoal;
   c->done = 0;
   c->epoch = c->epoch + 1u;
-  c->tk_front = c->tk_prop = c->tk_nodes = 0u;
-  c->bd_front = c->bd_prop = c->bd_nodes = 0u;
+  c->tk_front = c->tk_prop = c->tk_nodes = c->tk_commit = 0u;
+  c->bd_front = c->bd_prop = c->bd_nodes = c->bd_commit = 0u;
   c->err = 0u;
   c->lanes_total = c->valid_total = c->invalid_total = c->steps_total = c->box_total = 0ull;
 }
@@ -365,9 +421,11 @@ __device__ __forceinline__ void compact_frontier(const Dev& d, unsigned long lon
   const uint32_t woff =
       block_offsets(wt, s_wt, s_pref, st, tile, epoch, &d.ctl->err, &prefix);
   uint32_t pos = prefix + woff + ex;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (ebits & (1u << k)) d.F[pos++] = (int32_t)(base + k);
+  while (ebits) {
+    const int k = __ffs(ebits) - 1;
+    d.F[pos++] = (int32_t)(base + k);
+    ebits &= ebits - 1u;
+  }
 }
 
 // last-block finalisation of the frontier: |V_E|, eq. (6), termination codes
@@ -387,7 +445,9 @@ __device__ __forceinline__ void finalize_frontier(const Params& p, Ctl* c, uint3
   }
 }
 
-__global__ __launch_bounds__(kNodeBlock) void k_frontier(Params p, Dev d) {
+__global__ __launch_bounds__(kNodeBlock) void k_frontier(const Env* __restrict__ env) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
   Ctl* c = d.ctl;
   const int32_t N = c->N;
   const int done = c->done;
@@ -399,12 +459,13 @@ __global__ __launch_bounds__(kNodeBlock) void k_frontier(Params p, Dev d) {
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) break;
-    const uint32_t base = tile * kNodeTile + threadIdx.x * 4u;
-    const uint32_t fw = *reinterpret_cast<const uint32_t*>(d.flag + base);
+    const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
+    const uint4 fv = *reinterpret_cast<const uint4*>(d.flag + base);
+    const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
     uint32_t eb = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (base + k < (uint32_t)N && ((fw >> (8 * k)) & 0xffu)) eb |= 1u << k;
+    for (int k = 0; k < kNodesPerThread; ++k)
+      if (base + k < (uint32_t)N && ((fw[k >> 2] >> (8 * (k & 3))) & 0xffu)) eb |= 1u << k;
     compact_frontier(d, d.st_front, eb, base, tile, epoch, s_wt, &s_pref);
     __syncthreads();
   }
@@ -430,7 +491,10 @@ size_t propagate_lds_bytes(int n_obs) {
 }
 
 template <int DYN, int INTEG>
-__global__ __launch_bounds__(kPropBlock) void k_propagate(Params p, Dev d, TraceRec* trace) {
+__global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict__ env,
+                                                           TraceRec* trace) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
   constexpr int n = Dim<DYN>::n;
   constexpr int m = Dim<DYN>::m;
   extern __shared__ float lds[];
@@ -438,9 +502,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(Params p, Dev d, Trace
   const int done = c->done;
   const int32_t lanes = c->lanes;
   const int32_t lam = c->lambda;
-  const int32_t N = c->N;
   const uint32_t it = (uint32_t)c->it;
-  const uint32_t epoch = c->epoch;
   const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + kPropBlock - 1) / kPropBlock);
   const int n_obs = p.n_obs;
   const int wave = threadIdx.x >> 6;
@@ -451,7 +513,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(Params p, Dev d, Trace
   float* o_hy = lds + 4 * n_obs;
   float* o_hz = lds + 5 * n_obs;
   uint16_t* cand = reinterpret_cast<uint16_t*>(lds + 6 * n_obs) + wave * n_obs;
-  __shared__ uint32_t s_tile, s_pref, s_wt[4];
+  __shared__ uint32_t s_tile, s_wt[kPropBlock / 64];
 
   if (ntiles > 0)
     for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) lds[k] = d.obs[k];
@@ -583,34 +645,30 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(Params p, Dev d, Trace
       }
     }
 
-    // stable compaction of accepted samples: id = |T| + rank in lane order
+    // Accepted samples are compacted inside the tile (lane order) into the
+    // staging area; k_commit later gives them their tree ids.  The tile never
+    // waits for other tiles, so slow tiles do not hold up fast ones.
     const unsigned long long ab = __ballot(accept);
     const uint32_t rank = (uint32_t)__popcll(ab & lanes_below());
-    uint32_t prefix;
-    const uint32_t woff = block_offsets((uint32_t)__popcll(ab), s_wt, &s_pref, d.st_prop, tile,
-                                        epoch, &c->err, &prefix);
-    int32_t id = -1;
-    if (accept) {
-      id = N + (int32_t)(prefix + woff + rank);
-      if (id >= N + lanes) {  // cannot happen with a consistent look-back; never write past it
-        atomicOr(&c->err, 2u);
-        accept = false;
-        goal = false;
-        id = -1;
-      }
+    if (__lane_id() == 0) s_wt[wave] = (uint32_t)__popcll(ab);
+    __syncthreads();
+    uint32_t woff = 0, tcount = 0;
+#pragma unroll
+    for (int k = 0; k < kPropBlock / 64; ++k) {
+      woff += (k < wave) ? s_wt[k] : 0u;
+      tcount += s_wt[k];
     }
     if (accept) {
+      const size_t slot = (size_t)tile * kPropBlock + woff + rank;
 #pragma unroll
-      for (int k = 0; k < n; ++k) d.x[(size_t)k * d.capP + id] = x[k];
+      for (int k = 0; k < n; ++k) d.sx[(size_t)k * d.capP + slot] = x[k];
 #pragma unroll
-      for (int j = 0; j < m; ++j) d.u[(size_t)j * d.capP + id] = u[j];
-      d.parent[id] = f;
-      d.cell[id] = cl;
-      d.flag[id] = 1;
-      d.birth[id] = (int32_t)it;
-      d.sample[id] = (uint8_t)s;
-      if (goal) atomicMin(&c->goal_id, id);
+      for (int j = 0; j < m; ++j) d.su[(size_t)j * d.capP + slot] = u[j];
+      d.scell[slot] = cl;
+      d.slane[slot] = ((uint32_t)g << 1) | (goal ? 1u : 0u);
     }
+    if (threadIdx.x == 0) d.scount[tile] = tcount;
+    const int32_t id = -1;  // assigned by k_commit
     if (trace != nullptr && active) {
       TraceRec* t = trace + g;
       t->parent = f;
@@ -649,9 +707,75 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(Params p, Dev d, Trace
     const uint32_t prev = atomicAdd(&c->bd_prop, 1u);
     if (prev == gridDim.x - 1u) {
       __threadfence();
-      if (!done) c->nU = (int32_t)tile_total(d.st_prop, ntiles);
       c->tk_prop = 0u;
       c->bd_prop = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_commit: V_U ids (Alg. 2 line 9, "add x' to V_U"), stable in lane order
+// ---------------------------------------------------------------------------
+// One tile per propagate tile: the tile's staged samples take ids
+// |T| + (accepted samples of all earlier tiles) + (rank inside the tile).
+// Tiles are uniform and short, so the decoupled look-back rarely waits.
+__global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ env,
+                                                       TraceRec* trace) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  Ctl* c = d.ctl;
+  const int done = c->done;
+  const int32_t lanes = c->lanes;
+  const int32_t lam = c->lambda;
+  const int32_t N = c->N;
+  const uint32_t it = (uint32_t)c->it;
+  const uint32_t epoch = c->epoch;
+  const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + kPropBlock - 1) / kPropBlock);
+  __shared__ uint32_t s_tile, s_pref;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_commit, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const uint32_t cnt = d.scount[tile];
+    if (threadIdx.x < 64) {
+      const uint32_t pre = lookback_prefix_wave(d.st_prop, tile, cnt, epoch, &c->err);
+      if (threadIdx.x == 0) s_pref = pre;
+    }
+    __syncthreads();
+    const uint32_t k = threadIdx.x;
+    if (k < cnt) {
+      const size_t slot = (size_t)tile * kPropBlock + k;
+      int32_t id = N + (int32_t)(s_pref + k);
+      if (id >= N + lanes) {  // cannot happen with a consistent look-back; never write past it
+        atomicOr(&c->err, 2u);
+      } else {
+        const uint32_t sl = d.slane[slot];
+        const int32_t g = (int32_t)(sl >> 1);
+        const int32_t e = g / lam;
+        const int32_t s = g - e * lam;
+        for (int q = 0; q < p.n; ++q) d.x[(size_t)q * d.capP + id] = d.sx[(size_t)q * d.capP + slot];
+        for (int q = 0; q < p.m; ++q) d.u[(size_t)q * d.capP + id] = d.su[(size_t)q * d.capP + slot];
+        d.parent[id] = d.F[e];
+        d.cell[id] = d.scell[slot];
+        d.flag[id] = 1;
+        d.birth[id] = (int32_t)it;
+        d.sample[id] = (uint8_t)s;
+        if (sl & 1u) atomicMin(&c->goal_id, id);
+        if (trace != nullptr) trace[g].new_id = id;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&c->bd_commit, 1u);
+    if (prev == gridDim.x - 1u) {
+      __threadfence();
+      if (!done) c->nU = (int32_t)tile_total(d.st_prop, ntiles);
+      c->tk_commit = 0u;
+      c->bd_commit = 0u;
     }
   }
 }
@@ -672,7 +796,9 @@ __device__ __forceinline__ double region_score(double delta, unsigned long long 
   return num / den;
 }
 
-__global__ __launch_bounds__(kRegionBlock) void k_region(Params p, Dev d) {
+__global__ __launch_bounds__(kRegionBlock) void k_region(const Env* __restrict__ env) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
   Ctl* c = d.ctl;
   if (c->done) return;
   __shared__ double s_max[kRegionBlock / 64];
@@ -713,7 +839,9 @@ __global__ __launch_bounds__(kRegionBlock) void k_region(Params p, Dev d) {
 // ---------------------------------------------------------------------------
 // k_nodesets: Alg. 4 + next frontier + eq. (6)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kNodeBlock) void k_nodesets(Params p, Dev d) {
+__global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__ env) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
   Ctl* c = d.ctl;
   const int done = c->done;
   const int32_t N = c->N;
@@ -729,38 +857,46 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(Params p, Dev d) {
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) break;
-    const uint32_t base = tile * kNodeTile + threadIdx.x * 4u;
+    const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
     uint32_t eb = 0;
     if (base < (uint32_t)Nt) {
-      const uint32_t fw = *reinterpret_cast<const uint32_t*>(d.flag + base);
-      const uint4 cw = *reinterpret_cast<const uint4*>(d.cell + base);
-      const uint32_t cells[4] = {cw.x, cw.y, cw.z, cw.w};
-      const U4 wa = philox(it, base >> 1, 0u, 3u, p.key0, p.key1);
-      const U4 wb = philox(it, (base >> 1) + 1u, 0u, 3u, p.key0, p.key1);
-      const uint32_t wd[4] = {wa.w[0], wa.w[2], wb.w[0], wb.w[2]};
-      const uint32_t wp[4] = {wa.w[1], wa.w[3], wb.w[1], wb.w[3]};
-      uint32_t nfw = fw;
+      const uint4 fv = *reinterpret_cast<const uint4*>(d.flag + base);
+      const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
+      uint32_t nfw[4] = {fv.x, fv.y, fv.z, fv.w};
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t i = base + k;
-        if (i >= (uint32_t)Nt) continue;
-        const uint32_t r = cells[k] >> 6;
-        bool E;
-        if (i >= (uint32_t)N) {
-          // V_U -> T and V_E (Alg. 4 lines 4-6)
-          E = true;
-          atomicOr(&d.visited[r], 1ull << (cells[k] & 63u));
-          d.avail[r] = 1;
-        } else {
-          const unsigned long long t = d.thr[r];
-          const bool wasE = ((fw >> (8 * k)) & 0xffu) != 0u;
-          const bool stay = wasE && ((unsigned long long)wd[k] < t);        // lines 1-3
-          E = stay || (!goal && ((unsigned long long)wp[k] < t));           // lines 7-9
-          nfw = (nfw & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
+      for (int q = 0; q < kNodesPerThread / 4; ++q) {
+        const uint32_t b4 = base + 4u * q;
+        if (b4 >= (uint32_t)Nt) break;
+        const uint4 cw = *reinterpret_cast<const uint4*>(d.cell + b4);
+        const uint32_t cells[4] = {cw.x, cw.y, cw.z, cw.w};
+        // node pair (2k, 2k+1) shares Philox block (it, k, 0, 3)
+        const U4 wa = philox(it, b4 >> 1, 0u, 3u, p.key0, p.key1);
+        const U4 wb = philox(it, (b4 >> 1) + 1u, 0u, 3u, p.key0, p.key1);
+        const uint32_t wd[4] = {wa.w[0], wa.w[2], wb.w[0], wb.w[2]};
+        const uint32_t wp[4] = {wa.w[1], wa.w[3], wb.w[1], wb.w[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t i = b4 + k;
+          if (i >= (uint32_t)Nt) continue;
+          const uint32_t r = cells[k] >> 6;
+          bool E;
+          if (i >= (uint32_t)N) {
+            // V_U -> T and V_E (Alg. 4 lines 4-6)
+            E = true;
+            atomicOr(&d.visited[r], 1ull << (cells[k] & 63u));
+            d.avail[r] = 1;
+          } else {
+            const unsigned long long t = d.thr[r];
+            const bool wasE = ((fw[q] >> (8 * k)) & 0xffu) != 0u;
+            const bool stay = wasE && ((unsigned long long)wd[k] < t);   // lines 1-3
+            E = stay || (!goal && ((unsigned long long)wp[k] < t));      // lines 7-9
+            nfw[q] = (nfw[q] & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
+          }
+          if (E) eb |= 1u << (4 * q + k);
         }
-        if (E) eb |= 1u << k;
       }
-      if (nfw != fw) *reinterpret_cast<uint32_t*>(d.flag + base) = nfw;
+      if (nfw[0] != fw[0] || nfw[1] != fw[1] || nfw[2] != fw[2] || nfw[3] != fw[3])
+        *reinterpret_cast<uint4*>(d.flag + base) = make_uint4(nfw[0], nfw[1], nfw[2], nfw[3]);
     }
     compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
     __syncthreads();
@@ -788,7 +924,8 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(Params p, Dev d) {
 // ---------------------------------------------------------------------------
 // k_path: root-to-node walk along parent links
 // ---------------------------------------------------------------------------
-__global__ void k_path(Dev d, int32_t node) {
+__global__ void k_path(const Env* __restrict__ env, int32_t node) {
+  const Dev& d = env->d;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   int32_t len = 0;
   for (int32_t v = node; v >= 0 && len <= kMaxPath; v = d.parent[v]) ++len;
@@ -801,63 +938,68 @@ __global__ void k_path(Dev d, int32_t node) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_zero(const Params& p, const Dev& d, hipStream_t s) {
+hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s) {
   int work = p.R;
   if (d.tiles_node > work) work = d.tiles_node;
   if (d.tiles_prop > work) work = d.tiles_prop;
   int grid = (work + 255) / 256;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, p, d);
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, env);
   return hipGetLastError();
 }
 
-hipError_t launch_root(const Params& p, const Dev& d, Vec12 xi, hipStream_t s) {
-  hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, p, d, xi);
+hipError_t launch_root(const Env* env, Vec12 xi, hipStream_t s) {
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, env, xi);
   return hipGetLastError();
 }
 
-hipError_t launch_set_ctl(const Dev& d, int32_t N, int32_t it, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, d, N, it);
+hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, env, N, it);
   return hipGetLastError();
 }
 
-hipError_t launch_frontier(const Params& p, const Dev& d, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kNodeBlock), 0, s, p, d);
+hipError_t launch_frontier(const Env* env, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kNodeBlock), 0, s, env);
   return hipGetLastError();
 }
 
 template <int DYN, int INTEG>
-static hipError_t launch_prop_t(const Params& p, const Dev& d, TraceRec* trace, int grid,
+static hipError_t launch_prop_t(const Env* env, int n_obs, TraceRec* trace, int grid,
                                 hipStream_t s) {
   hipLaunchKernelGGL((k_propagate<DYN, INTEG>), dim3(grid), dim3(kPropBlock),
-                     propagate_lds_bytes(p.n_obs), s, p, d, trace);
+                     propagate_lds_bytes(n_obs), s, env, trace);
   return hipGetLastError();
 }
 
-hipError_t launch_propagate(int dyn, int integ, const Params& p, const Dev& d, TraceRec* trace,
+hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
                             int grid, hipStream_t s) {
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER>(p, d, trace, grid, s);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER>(env, n_obs, trace, grid, s);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4>(p, d, trace, grid, s);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4>(env, n_obs, trace, grid, s);
   if (dyn == KP_DYN_QUAD12 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(p, d, trace, grid, s);
-  return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(p, d, trace, grid, s);
+    return launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(env, n_obs, trace, grid, s);
+  return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(env, n_obs, trace, grid, s);
 }
 
-hipError_t launch_region(const Params& p, const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_region, dim3(1), dim3(kRegionBlock), 0, s, p, d);
+hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit, dim3(grid), dim3(kPropBlock), 0, s, env, trace);
   return hipGetLastError();
 }
 
-hipError_t launch_nodesets(const Params& p, const Dev& d, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_nodesets, dim3(grid), dim3(kNodeBlock), 0, s, p, d);
+hipError_t launch_region(const Env* env, hipStream_t s) {
+  hipLaunchKernelGGL(k_region, dim3(1), dim3(kRegionBlock), 0, s, env);
   return hipGetLastError();
 }
 
-hipError_t launch_path(const Dev& d, int32_t node, hipStream_t s) {
-  hipLaunchKernelGGL(k_path, dim3(1), dim3(64), 0, s, d, node);
+hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_nodesets, dim3(grid), dim3(kNodeBlock), 0, s, env);
+  return hipGetLastError();
+}
+
+hipError_t launch_path(const Env* env, int32_t node, hipStream_t s) {
+  hipLaunchKernelGGL(k_path, dim3(1), dim3(64), 0, s, env, node);
   return hipGetLastError();
 }
 

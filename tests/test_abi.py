@@ -45,9 +45,10 @@ def test_workspace_bytes(lib):
     c2 = kp.workspace_bytes(problem_c2())
     c5 = kp.workspace_bytes(problem_c5())
     assert 0 < small < c1 < c2
-    # node arrays dominate: 12 + 4 floats + 14 bytes of ids / flags per node (c2)
+    # node arrays dominate: 12 + 4 floats + 14 bytes of ids / flags per node, plus
+    # the staging area for accepted samples (c2)
     assert c2 > 4194304 * (16 * 4 + 14)
-    assert c2 < 4194304 * 100
+    assert c2 < 4194304 * 200
     assert c5 > 8388608 * (9 * 4 + 14)
     assert c2 % 256 == 0
 
