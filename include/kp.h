@@ -37,8 +37,8 @@ extern "C" {
 
 typedef enum {
   KP_OK = 0,
-  KP_SOLVED = 1,          /* a new tree node reached X_goal (Alg. 4, lines 4-6) */
-  KP_TIMEOUT = 2,         /* t_max or max_iters reached (Alg. 1, line 4) */
+  KP_SOLVED = 1,          /* a new tree node reached X_goal (goal test of Alg. 4) */
+  KP_TIMEOUT = 2,         /* t_max or max_iters reached (loop bound of Alg. 1) */
   KP_TREE_FULL = 3,       /* eq. (6) gave lambda = 0: |T| + |V_E| > t_e */
   KP_FRONTIER_EMPTY = 4,  /* V_E became empty */
   KP_E_ARG = -1,          /* invalid argument (null pointer, bad size, bad field) */
@@ -189,7 +189,7 @@ size_t kp_workspace_bytes(const kp_problem_desc* desc);
 size_t kp_trace_bytes(const kp_problem* h);
 
 /*
- * Alg. 1, lines 1-3: checks the description, copies it and the obstacles,
+ * Alg. 1 set-up: checks the description, copies it and the obstacles,
  * carves the workspace and initialises the tree with the root x_init in V_E
  * and every P_accept = 1.  dev_workspace: device pointer, >= the size from
  * kp_workspace_bytes, borrowed for the handle's lifetime.  hip_stream: a
@@ -203,7 +203,7 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
 /* Frees the handle (not the workspace).  Synchronises the stream. */
 kp_status kp_destroy_problem(kp_problem* h);
 
-/* Back to Alg. 1 line 3 with a new seed; the workspace is re-initialised. */
+/* Back to Alg. 1 set-up with a new seed; the workspace is re-initialised. */
 kp_status kp_reset(kp_problem* h, uint64_t seed);
 
 /*
@@ -247,7 +247,7 @@ kp_status kp_copy_tree(kp_problem* h, kp_tree_host* out);
 kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in);
 
 /* Node ids from the root to `node` ("return trajectory x_init to x",
- * Alg. 4 line 5).  ids: host array of cap entries; *len receives the path
+ * the goal test of Alg. 4).  ids: host array of cap entries; *len receives the path
  * length.  KP_E_ARG if node is out of range or the path exceeds cap. */
 kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, int32_t* len);
 

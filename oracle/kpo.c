@@ -378,7 +378,7 @@ static int ball_box_dist_le(const double* c, double r, const double* o) {
   return d2 <= r * r;
 }
 
-/* Alg. 1, lines 1-3: root = x_init in V_E, every P_accept = 1. */
+/* Alg. 1 set-up: root = x_init in V_E, every P_accept = 1. */
 kpo_planner* kpo_create(const kpo_problem* pb, int32_t* status) {
   *status = KPO_E_ARG;
   if (!pb || (pb->dyn != KPO_DI6 && pb->dyn != KPO_QUAD12)) return NULL;
@@ -590,12 +590,11 @@ static void node_words(const kpo_planner* P, int32_t i, uint32_t* w_dem, uint32_
   *w_pro = w[2 * (i & 1) + 1];
 }
 
-/* Alg. 4.  Lines 1-3: each x in V_E moves to V_O with probability
- * 1 - P_accept (w_dem >= thr).  Lines 4-6: V_U joins V_E and the tree in
- * lane order; the first new node in X_goal ends the run (its id is returned)
- * and lines 7-9 are not reached.  Lines 7-9: each x in V_O, including the
- * ones just moved there, returns to V_E with probability P_accept
- * (w_pro < thr). */
+/* Alg. 4, in its order.  First, each x in V_E moves to V_O with probability
+ * 1 - P_accept (w_dem >= thr).  Then V_U joins V_E and the tree in lane
+ * order; the first new node in X_goal ends the run (its id is returned) and
+ * the last step is not reached.  Last, each x in V_O, including the ones
+ * just moved there, returns to V_E with probability P_accept (w_pro < thr). */
 int32_t kpo_update_node_sets(kpo_planner* P) {
   const int n = P->n, m = P->m;
   const int32_t N0 = P->N;
@@ -656,7 +655,7 @@ static double now_ms(void) {
   return ts.tv_sec * 1e3 + ts.tv_nsec * 1e-6;
 }
 
-/* Alg. 1, lines 4-9: loop until a goal node appears, the frontier empties,
+/* Alg. 1's loop: until a goal node appears, the frontier empties,
  * the tree is full, or the iteration / wall-clock budget runs out. */
 int32_t kpo_plan(kpo_planner* P, int32_t max_iters, double t_max_ms, int32_t* goal_id,
                  int32_t* iters) {

@@ -333,7 +333,8 @@ __device__ __forceinline__ uint32_t cell_of(const Params& p, float px, float py,
 }
 
 // ---------------------------------------------------------------------------
-// k_zero / k_root / k_set_ctl: (re)initialisation, Alg. 1 lines 1-3
+// k_zero / k_root / k_set_ctl: (re)initialisation, Alg. 1's set-up of the
+// tree, V_E and P_accept
 // ---------------------------------------------------------------------------
 __global__ void k_zero(const Env* __restrict__ env) {
   const Params& p = env->p;
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       }
     }
 
-    // sub-region, counts, acceptance (Alg. 2 lines 5-11)
+    // sub-region, n_valid / n_invalid and acceptance (Alg. 2)
     uint32_t cl = 0;
     bool accept = false, goal = false;
     if (active) {
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// k_commit: V_U ids (Alg. 2 line 9, "add x' to V_U"), stable in lane order
+// k_commit: ids of the accepted samples (V_U of Alg. 2), stable in lane order
 // ---------------------------------------------------------------------------
 // One tile per propagate tile: the tile's staged samples take ids
 // |T| + (accepted samples of all earlier tiles) + (rank inside the tile).
@@ -881,15 +882,15 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
           const uint32_t r = cells[k] >> 6;
           bool E;
           if (i >= (uint32_t)N) {
-            // V_U -> T and V_E (Alg. 4 lines 4-6)
+            // V_U joins T and V_E (Alg. 4)
             E = true;
             atomicOr(&d.visited[r], 1ull << (cells[k] & 63u));
             d.avail[r] = 1;
           } else {
             const unsigned long long t = d.thr[r];
             const bool wasE = ((fw[q] >> (8 * k)) & 0xffu) != 0u;
-            const bool stay = wasE && ((unsigned long long)wd[k] < t);   // lines 1-3
-            E = stay || (!goal && ((unsigned long long)wp[k] < t));      // lines 7-9
+            const bool stay = wasE && ((unsigned long long)wd[k] < t);   // V_E -> V_O w.p. 1-P
+            E = stay || (!goal && ((unsigned long long)wp[k] < t));      // V_O -> V_E w.p. P
             nfw[q] = (nfw[q] & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
           }
           if (E) eb |= 1u << (4 * q + k);

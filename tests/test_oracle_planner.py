@@ -105,7 +105,7 @@ def test_di_edges_closed_form():
 
 
 def test_acceptance_statistics():
-    # Alg. 2 lines 8-9: a valid sample in a visited sub-region is accepted
+    # Alg. 2 acceptance: a valid sample in a visited sub-region is accepted
     # with probability P_accept; in an unvisited one always.
     p = problem_small_di(cap=200000)
     P = oracle.OraclePlanner(p)
