@@ -491,6 +491,19 @@ size_t propagate_lds_bytes(int n_obs) {
   return b < 16 ? 16 : b;
 }
 
+// Separation of two closed boxes: the largest gap along any axis between a
+// face of one and the facing face of the other.  The boxes intersect
+// (touching included) iff the separation is <= 0; for finite operands
+// a - b <= 0 holds exactly when a <= b, so this is the same test as six
+// comparisons, computed without lane masks.
+__device__ __forceinline__ float box_separation(float lx, float ly, float lz, float hx, float hy,
+                                                float hz, const float2* ob) {
+  const float2 a = ob[0], b = ob[1], c = ob[2];  // (lo x, lo y), (lo z, hi x), (hi y, hi z)
+  const float s0 = fmaxf(fmaxf(lx - b.y, a.x - hx), ly - c.x);
+  const float s1 = fmaxf(fmaxf(a.y - hy, lz - c.y), b.x - hz);
+  return fmaxf(s0, s1);
+}
+
 template <int DYN, int INTEG>
 __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict__ env,
                                                            TraceRec* trace) {
@@ -507,17 +520,16 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + kPropBlock - 1) / kPropBlock);
   const int n_obs = p.n_obs;
   const int wave = threadIdx.x >> 6;
-  float* o_lx = lds;
-  float* o_ly = lds + n_obs;
-  float* o_lz = lds + 2 * n_obs;
-  float* o_hx = lds + 3 * n_obs;
-  float* o_hy = lds + 4 * n_obs;
-  float* o_hz = lds + 5 * n_obs;
+  // obstacle k in LDS: lo x, lo y, lo z, hi x, hi y, hi z (6 floats, read as 3 float2)
+  const float2* obox = reinterpret_cast<const float2*>(lds);
   uint16_t* cand = reinterpret_cast<uint16_t*>(lds + 6 * n_obs) + wave * n_obs;
   __shared__ uint32_t s_tile, s_wt[kPropBlock / 64];
 
   if (ntiles > 0)
-    for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) lds[k] = d.obs[k];
+    for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
+      const int ob = k / 6, comp = k - 6 * ob;
+      lds[k] = d.obs[(size_t)comp * n_obs + ob];
+    }
   __syncthreads();
 
   for (;;) {
@@ -572,9 +584,8 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       const int k = k0 + (int)__lane_id();
       bool ov = false;
       if (k < n_obs) {
-        ov = (o_lx[k] <= bx1 + p.margin) && (bx0 - p.margin <= o_hx[k]) &&
-             (o_ly[k] <= by1 + p.margin) && (by0 - p.margin <= o_hy[k]) &&
-             (o_lz[k] <= bz1 + p.margin) && (bz0 - p.margin <= o_hz[k]);
+        ov = box_separation(bx0 - p.margin, by0 - p.margin, bz0 - p.margin, bx1 + p.margin,
+                            by1 + p.margin, bz1 + p.margin, obox + 3 * k) <= 0.0f;
       }
       const unsigned long long b = __ballot(ov);
       if (ov) cand[ncand + __popcll(b & lanes_below())] = (uint16_t)k;
@@ -599,11 +610,13 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
           const float lx = fminf(px, x[0]) - p.margin, hx = fmaxf(px, x[0]) + p.margin;
           const float ly = fminf(py, x[1]) - p.margin, hy = fmaxf(py, x[1]) + p.margin;
           const float lz = fminf(pz, x[2]) - p.margin, hz = fmaxf(pz, x[2]) + p.margin;
+          // six comparisons per candidate (closed boxes: touching is a hit);
+          // measured faster here than the separation form used for culling
           bool hit = false;
           for (uint32_t q = 0; q < ncand; ++q) {
-            const int k = cand[q];
-            hit |= (lx <= o_hx[k]) & (o_lx[k] <= hx) & (ly <= o_hy[k]) & (o_ly[k] <= hy) &
-                   (lz <= o_hz[k]) & (o_lz[k] <= hz);
+            const float* o = reinterpret_cast<const float*>(obox + 3 * cand[q]);
+            hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
+                   (o[2] <= hz);
           }
           box_tests += ncand;
           ok = !hit;
