@@ -195,6 +195,7 @@ def main():
             "avg_launch_ms": prop_ms / n_launch if n_launch else None,
             "ops_per_launch": ops / n_launch if n_launch else None,
         },
+        "grid": {"propagate": G.stats()["grid_propagate"], "nodes": G.stats()["grid_nodes"]},
         "kernel_ms": {k: v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},
     }

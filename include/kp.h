@@ -134,6 +134,8 @@ typedef struct {
   uint64_t lanes_total, valid_total, invalid_total;
   uint64_t steps_total;    /* integration steps executed */
   uint64_t box_tests_total;/* swept-box vs obstacle tests executed */
+  int32_t grid_propagate;  /* workgroups of a full-size propagate launch */
+  int32_t grid_nodes;      /* workgroups of a full-size node-pass launch */
 } kp_iter_stats;
 
 /*

@@ -107,7 +107,7 @@ Layout make_layout(const kp_problem_desc* d) {
   L.su = take(capP * m * 4);
   L.scell = take(capP * 4);
   L.slane = take(capP * 4);
-  L.scount = take((size_t)L.tiles_prop * 4);
+  L.scount = take(((size_t)d->node_cap / 64 + 2) * 4);  // one count per 64-lane wave tile
   L.total = off;
   return L;
 }
@@ -612,6 +612,8 @@ kp_status kp_get_stats(kp_problem* h, kp_iter_stats* out) {
   out->invalid_total = c.invalid_total;
   out->steps_total = c.steps_total;
   out->box_tests_total = c.box_total;
+  out->grid_propagate = h->grid_prop_max;
+  out->grid_nodes = h->grid_node_max;
   return KP_OK;
 }
 

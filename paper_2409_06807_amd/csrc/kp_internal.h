@@ -75,12 +75,12 @@ struct Dev {
   unsigned long long* st_front;  // look-back status, one word per tile
   unsigned long long* st_prop;
   unsigned long long* st_nodes;
-  // accepted samples staged per propagate tile: slot = tile * kPropBlock + rank
+  // accepted samples staged per 64-lane wave tile: slot = tile * 64 + rank
   float* sx;           // [n][capP]
   float* su;           // [m][capP]
   uint32_t* scell;     // [capP]
   uint32_t* slane;     // [capP] lane index << 1 | goal bit
-  uint32_t* scount;    // [tiles_prop] accepted samples per tile
+  uint32_t* scount;    // [node_cap / 64 + 2] accepted samples per 64-lane wave tile
   int32_t* path;       // [kMaxPath + 1]
   int32_t capP;        // padded node capacity (multiple of kNodeTile)
   int32_t tiles_node;  // entries of st_front / st_nodes

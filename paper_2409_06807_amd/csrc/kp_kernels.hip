@@ -200,12 +200,36 @@ struct Dim<KP_DYN_QUAD12> {
   static constexpr int n = 12, m = 4;
 };
 
+// Per-step constants, copied out of Params once per kernel so that the step
+// loop keeps them in registers instead of re-loading them from memory.
 template <int DYN>
-__device__ __forceinline__ void deriv(const Params& p, const float* x, const float* u, float* dx);
+struct StepC {
+  float h, inv_m, grav, inv_Ixx, inv_Iyy, inv_Izz, dIyz, dIzx, dIxy;
+  float x_lo[Dim<DYN>::n], x_hi[Dim<DYN>::n];
+};
 
-template <>
-__device__ __forceinline__ void deriv<KP_DYN_DI6>(const Params& p, const float* x, const float* u,
-                                                 float* dx) {
+template <int DYN>
+__device__ __forceinline__ StepC<DYN> load_step_consts(const Params& p) {
+  StepC<DYN> s;
+  s.h = p.h;
+  s.inv_m = p.inv_m;
+  s.grav = p.grav;
+  s.inv_Ixx = p.inv_Ixx;
+  s.inv_Iyy = p.inv_Iyy;
+  s.inv_Izz = p.inv_Izz;
+  s.dIyz = p.dIyz;
+  s.dIzx = p.dIzx;
+  s.dIxy = p.dIxy;
+#pragma unroll
+  for (int i = 0; i < Dim<DYN>::n; ++i) {
+    s.x_lo[i] = p.x_lo[i];
+    s.x_hi[i] = p.x_hi[i];
+  }
+  return s;
+}
+
+template <class PP>
+__device__ __forceinline__ void deriv_di(const PP&, const float* x, const float* u, float* dx) {
   dx[0] = x[3];
   dx[1] = x[4];
   dx[2] = x[5];
@@ -245,9 +269,9 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
 }
 
 // rigid-body quadcopter, ZYX Euler angles, inertial velocity, body rates
-template <>
-__device__ __forceinline__ void deriv<KP_DYN_QUAD12>(const Params& p, const float* x,
-                                                    const float* u, float* dx) {
+template <class PP>
+__device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const float* u,
+                                           float* dx) {
   float sf, cf, st, ct, sp, cp;
   sincos_rr(x[3], &sf, &cf);
   sincos_rr(x[4], &st, &ct);
@@ -271,8 +295,14 @@ __device__ __forceinline__ void deriv<KP_DYN_QUAD12>(const Params& p, const floa
   dx[11] = __builtin_fmaf(p.dIxy * P, Q, u[3]) * p.inv_Izz;
 }
 
-template <int DYN, int INTEG>
-__device__ __forceinline__ void integ_step(const Params& p, float* x, const float* u) {
+template <int DYN, class PP>
+__device__ __forceinline__ void deriv(const PP& p, const float* x, const float* u, float* dx) {
+  if constexpr (DYN == KP_DYN_DI6) deriv_di(p, x, u, dx);
+  else deriv_quad(p, x, u, dx);
+}
+
+template <int DYN, int INTEG, class PP>
+__device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u) {
   constexpr int n = Dim<DYN>::n;
   const float h = p.h;
   float k1[n];
@@ -307,8 +337,8 @@ __device__ __forceinline__ void integ_step(const Params& p, float* x, const floa
   }
 }
 
-template <int DYN>
-__device__ __forceinline__ bool state_ok(const Params& p, const float* x) {
+template <int DYN, class PP>
+__device__ __forceinline__ bool state_ok(const PP& p, const float* x) {
   constexpr int n = Dim<DYN>::n;
   bool ok = true;
 #pragma unroll
@@ -517,13 +547,16 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   const int32_t lanes = c->lanes;
   const int32_t lam = c->lambda;
   const uint32_t it = (uint32_t)c->it;
-  const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + kPropBlock - 1) / kPropBlock);
+  // tiles are single waves: each wave takes 64 lanes at a time from the ticket
+  const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + 63) / 64);
+  const StepC<DYN> sc = load_step_consts<DYN>(p);
+  const int K = p.K;
+  const float margin = p.margin;
   const int n_obs = p.n_obs;
   const int wave = threadIdx.x >> 6;
   // obstacle k in LDS: lo x, lo y, lo z, hi x, hi y, hi z (6 floats, read as 3 float2)
   const float2* obox = reinterpret_cast<const float2*>(lds);
   uint16_t* cand = reinterpret_cast<uint16_t*>(lds + 6 * n_obs) + wave * n_obs;
-  __shared__ uint32_t s_tile, s_wt[kPropBlock / 64];
 
   if (ntiles > 0)
     for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
@@ -533,12 +566,12 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   __syncthreads();
 
   for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_prop, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    uint32_t tk = 0;
+    if (__lane_id() == 0) tk = atomicAdd(&c->tk_prop, 1u);
+    const uint32_t tile = __builtin_amdgcn_readfirstlane(tk);
     if (tile >= ntiles) break;
 
-    const int32_t g = (int32_t)(tile * kPropBlock + threadIdx.x);
+    const int32_t g = (int32_t)(tile * 64u + __lane_id());
     const bool active = g < lanes;
     int32_t e = 0, s = 0, f = 0;
     float x[n];
@@ -591,7 +624,10 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       if (ov) cand[ncand + __popcll(b & lanes_below())] = (uint16_t)k;
       ncand += (uint32_t)__popcll(b);
     }
-    __syncthreads();  // candidate lists written by lanes are read wave-wide below
+    // the candidate list is private to this wave: order its LDS writes before
+    // the wave-wide reads below
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 
     // Segment integration with per-step validity; x' is the segment end or
     // the first failing state.
@@ -599,21 +635,31 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
     bool valid = active;
     int32_t steps = 0;
     uint32_t box_tests = 0;
-    for (int j = 0; j < p.K; ++j) {
+    for (int j = 0; j < K; ++j) {
       if (__ballot(alive) == 0ull) break;
       if (alive) {
         const float px = x[0], py = x[1], pz = x[2];
-        integ_step<DYN, INTEG>(p, x, u);
+        integ_step<DYN, INTEG>(sc, x, u);
         steps = j + 1;
-        bool ok = state_ok<DYN>(p, x);
+        bool ok = state_ok<DYN>(sc, x);
         if (ok) {
-          const float lx = fminf(px, x[0]) - p.margin, hx = fmaxf(px, x[0]) + p.margin;
-          const float ly = fminf(py, x[1]) - p.margin, hy = fmaxf(py, x[1]) + p.margin;
-          const float lz = fminf(pz, x[2]) - p.margin, hz = fmaxf(pz, x[2]) + p.margin;
+          const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
+          const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;
+          const float lz = fminf(pz, x[2]) - margin, hz = fmaxf(pz, x[2]) + margin;
           // six comparisons per candidate (closed boxes: touching is a hit);
-          // measured faster here than the separation form used for culling
+          // measured faster here than the separation form used for culling.
+          // Two candidates per trip so that their LDS reads overlap.
           bool hit = false;
-          for (uint32_t q = 0; q < ncand; ++q) {
+          uint32_t q = 0;
+          for (; q + 1 < ncand; q += 2) {
+            const float* o = reinterpret_cast<const float*>(obox + 3 * cand[q]);
+            const float* r = reinterpret_cast<const float*>(obox + 3 * cand[q + 1]);
+            hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
+                   (o[2] <= hz);
+            hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
+                   (r[2] <= hz);
+          }
+          if (q < ncand) {
             const float* o = reinterpret_cast<const float*>(obox + 3 * cand[q]);
             hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
                    (o[2] <= hz);
@@ -659,21 +705,13 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       }
     }
 
-    // Accepted samples are compacted inside the tile (lane order) into the
-    // staging area; k_commit later gives them their tree ids.  The tile never
-    // waits for other tiles, so slow tiles do not hold up fast ones.
+    // Accepted samples are compacted inside the wave's tile (lane order) into
+    // the staging area; k_commit later gives them their tree ids.  No wave
+    // ever waits for another, so slow tiles do not hold up fast ones.
     const unsigned long long ab = __ballot(accept);
     const uint32_t rank = (uint32_t)__popcll(ab & lanes_below());
-    if (__lane_id() == 0) s_wt[wave] = (uint32_t)__popcll(ab);
-    __syncthreads();
-    uint32_t woff = 0, tcount = 0;
-#pragma unroll
-    for (int k = 0; k < kPropBlock / 64; ++k) {
-      woff += (k < wave) ? s_wt[k] : 0u;
-      tcount += s_wt[k];
-    }
     if (accept) {
-      const size_t slot = (size_t)tile * kPropBlock + woff + rank;
+      const size_t slot = (size_t)tile * 64u + rank;
 #pragma unroll
       for (int k = 0; k < n; ++k) d.sx[(size_t)k * d.capP + slot] = x[k];
 #pragma unroll
@@ -681,7 +719,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       d.scell[slot] = cl;
       d.slane[slot] = ((uint32_t)g << 1) | (goal ? 1u : 0u);
     }
-    if (threadIdx.x == 0) d.scount[tile] = tcount;
+    if (__lane_id() == 0) d.scount[tile] = (uint32_t)__popcll(ab);
     const int32_t id = -1;  // assigned by k_commit
     if (trace != nullptr && active) {
       TraceRec* t = trace + g;
@@ -712,7 +750,6 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
         atomicAdd(&c->box_total, bt);
       }
     }
-    __syncthreads();
   }
 
   __syncthreads();
@@ -730,9 +767,10 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
 // ---------------------------------------------------------------------------
 // k_commit: ids of the accepted samples (V_U of Alg. 2), stable in lane order
 // ---------------------------------------------------------------------------
-// One tile per propagate tile: the tile's staged samples take ids
-// |T| + (accepted samples of all earlier tiles) + (rank inside the tile).
-// Tiles are uniform and short, so the decoupled look-back rarely waits.
+// One tile = four consecutive 64-lane propagate tiles, one per wave.  The
+// staged samples take ids |T| + (accepted samples of all earlier lanes) +
+// (rank inside the wave's tile); the tile prefix comes from a decoupled
+// look-back.  Tiles are uniform and short, so the look-back rarely waits.
 __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ env,
                                                        TraceRec* trace) {
   const Params& p = env->p;
@@ -744,23 +782,33 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
   const int32_t N = c->N;
   const uint32_t it = (uint32_t)c->it;
   const uint32_t epoch = c->epoch;
-  const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + kPropBlock - 1) / kPropBlock);
+  const uint32_t nwt = done ? 0u : (uint32_t)((lanes + 63) / 64);  // wave tiles
+  const uint32_t ntiles = (nwt + 3u) / 4u;
+  const int wave = threadIdx.x >> 6;
   __shared__ uint32_t s_tile, s_pref;
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_commit, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) break;
-    const uint32_t cnt = d.scount[tile];
-    if (threadIdx.x < 64) {
-      const uint32_t pre = lookback_prefix_wave(d.st_prop, tile, cnt, epoch, &c->err);
-      if (threadIdx.x == 0) s_pref = pre;
+    uint32_t cnt[4];
+    uint32_t tot = 0, woff = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t wt = tile * 4u + (uint32_t)w;
+      cnt[w] = (wt < nwt) ? d.scount[wt] : 0u;
+      woff += (w < wave) ? cnt[w] : 0u;
+      tot += cnt[w];
+    }
+    if (wave == 0) {
+      const uint32_t pre = lookback_prefix_wave(d.st_prop, tile, tot, epoch, &c->err);
+      if (__lane_id() == 0) s_pref = pre;
     }
     __syncthreads();
-    const uint32_t k = threadIdx.x;
-    if (k < cnt) {
-      const size_t slot = (size_t)tile * kPropBlock + k;
-      int32_t id = N + (int32_t)(s_pref + k);
+    const uint32_t k = __lane_id();
+    if (k < cnt[wave]) {
+      const size_t slot = (size_t)(tile * 4u + (uint32_t)wave) * 64u + k;
+      const int32_t id = N + (int32_t)(s_pref + woff + k);
       if (id >= N + lanes) {  // cannot happen with a consistent look-back; never write past it
         atomicOr(&c->err, 2u);
       } else {

@@ -59,6 +59,7 @@ class IterStats(C.Structure):
         ("n_new", C.c_int32), ("device_error", C.c_int32),
         ("lanes_total", C.c_uint64), ("valid_total", C.c_uint64), ("invalid_total", C.c_uint64),
         ("steps_total", C.c_uint64), ("box_tests_total", C.c_uint64),
+        ("grid_propagate", C.c_int32), ("grid_nodes", C.c_int32),
     ]
 
 
