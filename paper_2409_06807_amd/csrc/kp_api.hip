@@ -25,10 +25,10 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t ctl, env, x, u, parent, cell, flag, birth, sample, F;
-  size_t nv, ni, visited, thr, avail, obs, st_front, st_nodes, st_prop, path;
-  size_t sx, su, scell, slane, scount;
+  size_t nv, ni, visited, thr, avail, obs, st_front, st_nodes, path;
+  size_t sx, su, scell, slane, scount, ssum;
   size_t total;
-  int capP, tiles_node, tiles_prop;
+  int capP, tiles_node, nchunk;
 };
 
 int state_dim(int dyn) { return dyn == KP_DYN_DI6 ? 6 : 12; }
@@ -76,7 +76,7 @@ Layout make_layout(const kp_problem_desc* d) {
   const size_t capP = align_up((size_t)d->node_cap + 1, kNodeTile);
   L.capP = (int)capP;
   L.tiles_node = (int)(capP / kNodeTile + 2);
-  L.tiles_prop = (int)((size_t)d->node_cap / kPropBlock + 2);
+  L.nchunk = (int)(((size_t)d->node_cap / 64 + 2 + kChunkTiles - 1) / kChunkTiles);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -101,13 +101,13 @@ Layout make_layout(const kp_problem_desc* d) {
   L.obs = take((size_t)(d->n_obstacles > 0 ? d->n_obstacles : 1) * 6 * 4);
   L.st_front = take((size_t)L.tiles_node * 8);
   L.st_nodes = take((size_t)L.tiles_node * 8);
-  L.st_prop = take((size_t)L.tiles_prop * 8);
   L.path = take((size_t)(kMaxPath + 1) * 4);
   L.sx = take(capP * n * 4);
   L.su = take(capP * m * 4);
   L.scell = take(capP * 4);
   L.slane = take(capP * 4);
   L.scount = take(((size_t)d->node_cap / 64 + 2) * 4);  // one count per 64-lane wave tile
+  L.ssum = take((size_t)L.nchunk * 4);
   L.total = off;
   return L;
 }
@@ -256,16 +256,16 @@ void carve(kp_problem* h, void* ws) {
   v.obs = reinterpret_cast<float*>(b + L.obs);
   v.st_front = reinterpret_cast<unsigned long long*>(b + L.st_front);
   v.st_nodes = reinterpret_cast<unsigned long long*>(b + L.st_nodes);
-  v.st_prop = reinterpret_cast<unsigned long long*>(b + L.st_prop);
   v.path = reinterpret_cast<int32_t*>(b + L.path);
   v.sx = reinterpret_cast<float*>(b + L.sx);
   v.su = reinterpret_cast<float*>(b + L.su);
   v.scell = reinterpret_cast<uint32_t*>(b + L.scell);
   v.slane = reinterpret_cast<uint32_t*>(b + L.slane);
   v.scount = reinterpret_cast<uint32_t*>(b + L.scount);
+  v.ssum = reinterpret_cast<uint32_t*>(b + L.ssum);
   v.capP = L.capP;
   v.tiles_node = L.tiles_node;
-  v.tiles_prop = L.tiles_prop;
+  v.nchunk = L.nchunk;
 }
 
 kp_status sync_ctl(kp_problem* h) {
@@ -277,16 +277,16 @@ kp_status sync_ctl(kp_problem* h) {
   return KP_OK;
 }
 
-// profiling: bracket a launch with a pair of events
-int prof_begin(kp_problem* h, int kernel) {
-  if (!h->prof || h->ev_used >= kEventPool) return -1;
+// profiling: hand a launch a pair of events that the runtime stamps with the
+// dispatch's begin and end
+Timing prof_slot(kp_problem* h, int kernel) {
+  Timing t;
+  if (!h->prof || h->ev_used >= kEventPool) return t;
   const int k = h->ev_used++;
   h->ev_kernel[k] = kernel;
-  (void)hipEventRecord(h->ev[k][0], h->stream);
-  return k;
-}
-void prof_end(kp_problem* h, int k) {
-  if (k >= 0) (void)hipEventRecord(h->ev[k][1], h->stream);
+  t.start = h->ev[k][0];
+  t.stop = h->ev[k][1];
+  return t;
 }
 void prof_collect(kp_problem* h) {
   if (!h->prof || h->ev_used == 0) return;
@@ -305,9 +305,7 @@ kp_status do_frontier(kp_problem* h) {
   const int tiles = (h->L.capP + kNodeTile - 1) / kNodeTile;
   int grid = tiles < h->grid_node_max ? tiles : h->grid_node_max;
   if (grid < 1) grid = 1;
-  const int pk = prof_begin(h, 3);
-  hipError_t e = launch_frontier(h->env_dev, grid, h->stream);
-  prof_end(h, pk);
+  hipError_t e = launch_frontier(h->env_dev, grid, h->stream, prof_slot(h, 3));
   if (e != hipSuccess) return hip_fail(h, e, "frontier launch");
   return KP_OK;
 }
@@ -318,25 +316,19 @@ kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub) {
   long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
   int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
   if (grid < 1) grid = 1;
-  const int pk = prof_begin(h, 0);
   hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->env_dev,
-                                  h->desc.n_obstacles, trace,
-                                  grid, h->stream);
-  prof_end(h, pk);
+                                  h->desc.n_obstacles, trace, grid, h->stream,
+                                  prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
   int cgrid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
   if (cgrid < 1) cgrid = 1;
-  const int ck = prof_begin(h, 4);
-  e = launch_commit(h->env_dev, trace, cgrid, h->stream);
-  prof_end(h, ck);
+  e = launch_commit(h->env_dev, trace, cgrid, h->stream, prof_slot(h, 4));
   if (e != hipSuccess) return hip_fail(h, e, "commit launch");
   return KP_OK;
 }
 
 kp_status do_region(kp_problem* h) {
-  const int pk = prof_begin(h, 1);
-  hipError_t e = launch_region(h->env_dev, h->stream);
-  prof_end(h, pk);
+  hipError_t e = launch_region(h->env_dev, h->stream, prof_slot(h, 1));
   if (e != hipSuccess) return hip_fail(h, e, "region launch");
   return KP_OK;
 }
@@ -345,9 +337,7 @@ kp_status do_nodesets(kp_problem* h, long long nodes_ub) {
   long long tiles = (nodes_ub + kNodeTile - 1) / kNodeTile;
   int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
   if (grid < 1) grid = 1;
-  const int pk = prof_begin(h, 2);
-  hipError_t e = launch_nodesets(h->env_dev, grid, h->stream);
-  prof_end(h, pk);
+  hipError_t e = launch_nodesets(h->env_dev, grid, h->stream, prof_slot(h, 2));
   if (e != hipSuccess) return hip_fail(h, e, "node sets launch");
   return KP_OK;
 }

@@ -11,6 +11,7 @@ constexpr int kPropBlock = 256;      // lanes per propagate tile (4 waves)
 constexpr int kNodeBlock = 256;      // threads per node-pass block
 constexpr int kNodesPerThread = 16;  // nodes per thread in the node passes
 constexpr int kNodeTile = 4096;      // nodes per node-pass tile
+constexpr int kChunkTiles = 256;     // 64-lane wave tiles per accepted-sample chunk sum
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
 constexpr int kMaxPath = 65536;      // longest path kp_get_path can return
 constexpr int kDoneNone = 0;
@@ -33,8 +34,11 @@ struct alignas(256) Ctl {
   uint32_t err;       // nonzero: a look-back wait hit its spin limit
   uint32_t iters_done;
   uint32_t tk_commit, bd_commit;
+  // the running totals sit on their own 128-byte line, away from the tickets
+  uint32_t pad_[13];
   unsigned long long lanes_total, valid_total, invalid_total, steps_total, box_total;
 };
+static_assert(__builtin_offsetof(Ctl, lanes_total) == 128, "Ctl totals on their own line");
 
 // Problem constants, passed by value to every kernel.
 struct Params {
@@ -73,7 +77,6 @@ struct Dev {
   uint8_t* avail;      // [R]
   float* obs;          // [6][n_obs] SoA
   unsigned long long* st_front;  // look-back status, one word per tile
-  unsigned long long* st_prop;
   unsigned long long* st_nodes;
   // accepted samples staged per 64-lane wave tile: slot = tile * 64 + rank
   float* sx;           // [n][capP]
@@ -81,10 +84,11 @@ struct Dev {
   uint32_t* scell;     // [capP]
   uint32_t* slane;     // [capP] lane index << 1 | goal bit
   uint32_t* scount;    // [node_cap / 64 + 2] accepted samples per 64-lane wave tile
+  uint32_t* ssum;      // [nchunk] accepted samples per kChunkTiles consecutive wave tiles
   int32_t* path;       // [kMaxPath + 1]
   int32_t capP;        // padded node capacity (multiple of kNodeTile)
   int32_t tiles_node;  // entries of st_front / st_nodes
-  int32_t tiles_prop;  // entries of st_prop
+  int32_t nchunk;      // entries of ssum
   int32_t pad;
 };
 
@@ -107,15 +111,22 @@ struct Env {
 };
 
 // Launchers (kp_kernels.hip).  Each returns the hipError_t of the launch.
+// A non-null Timing pair is filled with the dispatch's own begin and end
+// timestamps (hipExtLaunchKernel), so that the measured span is the kernel
+// alone, without the command-processor work between two event markers.
 struct Vec12 { float v[12]; };
+struct Timing {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
 hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s);
 hipError_t launch_root(const Env* env, Vec12 x_init, hipStream_t s);
-hipError_t launch_frontier(const Env* env, int grid, hipStream_t s);
+hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
-                            int grid, hipStream_t s);
-hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s);
-hipError_t launch_region(const Env* env, hipStream_t s);
-hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s);
+                            int grid, hipStream_t s, Timing t);
+hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s, Timing t);
+hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
+hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
 int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu);

@@ -20,6 +20,8 @@
 // memory, and the host never needs these sizes to launch.
 #include "kp_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include "kp.h"
 
 namespace kp {
@@ -381,8 +383,7 @@ __global__ void k_zero(const Env* __restrict__ env) {
     d.st_front[t] = 0ull;
     d.st_nodes[t] = 0ull;
   }
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.tiles_prop; t += stride)
-    d.st_prop[t] = 0ull;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.nchunk; t += stride) d.ssum[t] = 0u;
 }
 
 __global__ void k_root(const Env* __restrict__ env, Vec12 xi) {
@@ -557,6 +558,8 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   // obstacle k in LDS: lo x, lo y, lo z, hi x, hi y, hi z (6 floats, read as 3 float2)
   const float2* obox = reinterpret_cast<const float2*>(lds);
   uint16_t* cand = reinterpret_cast<uint16_t*>(lds + 6 * n_obs) + wave * n_obs;
+  // per-wave running totals (wave-uniform), flushed once per block
+  unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0;
 
   if (ntiles > 0)
     for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
@@ -719,7 +722,11 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       d.scell[slot] = cl;
       d.slane[slot] = ((uint32_t)g << 1) | (goal ? 1u : 0u);
     }
-    if (__lane_id() == 0) d.scount[tile] = (uint32_t)__popcll(ab);
+    if (__lane_id() == 0) {
+      const uint32_t na = (uint32_t)__popcll(ab);
+      d.scount[tile] = na;
+      if (na) atomicAdd(&d.ssum[tile / kChunkTiles], na);
+    }
     const int32_t id = -1;  // assigned by k_commit
     if (trace != nullptr && active) {
       TraceRec* t = trace + g;
@@ -736,24 +743,31 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       t->accept = accept ? 1 : 0;
       t->new_id = id;
     }
-    // counters
-    {
-      const unsigned long long nl = __popcll(__ballot(active));
-      const unsigned long long nvv = __popcll(__ballot(active && valid));
-      const unsigned long long st = wave_sum_u64((unsigned long long)steps);
-      const unsigned long long bt = wave_sum_u64((unsigned long long)box_tests);
-      if (__lane_id() == 0 && nl) {
-        atomicAdd(&c->lanes_total, nl);
-        atomicAdd(&c->valid_total, nvv);
-        atomicAdd(&c->invalid_total, nl - nvv);
-        atomicAdd(&c->steps_total, st);
-        atomicAdd(&c->box_total, bt);
-      }
-    }
+    t_lanes += (unsigned long long)__popcll(__ballot(active));
+    t_valid += (unsigned long long)__popcll(__ballot(active && valid));
+    t_steps += wave_sum_u64((unsigned long long)steps);
+    t_box += wave_sum_u64((unsigned long long)box_tests);
   }
 
+  __shared__ unsigned long long s_tot[kPropBlock / 64][4];
+  if (__lane_id() == 0) {
+    s_tot[wave][0] = t_lanes;
+    s_tot[wave][1] = t_valid;
+    s_tot[wave][2] = t_steps;
+    s_tot[wave][3] = t_box;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
+    unsigned long long a[4] = {0, 0, 0, 0};
+    for (int w = 0; w < kPropBlock / 64; ++w)
+      for (int q = 0; q < 4; ++q) a[q] += s_tot[w][q];
+    if (a[0]) {
+      atomicAdd(&c->lanes_total, a[0]);
+      atomicAdd(&c->valid_total, a[1]);
+      atomicAdd(&c->invalid_total, a[0] - a[1]);
+      atomicAdd(&c->steps_total, a[2]);
+      atomicAdd(&c->box_total, a[3]);
+    }
     __threadfence();
     const uint32_t prev = atomicAdd(&c->bd_prop, 1u);
     if (prev == gridDim.x - 1u) {
@@ -767,10 +781,12 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
 // ---------------------------------------------------------------------------
 // k_commit: ids of the accepted samples (V_U of Alg. 2), stable in lane order
 // ---------------------------------------------------------------------------
-// One tile = four consecutive 64-lane propagate tiles, one per wave.  The
-// staged samples take ids |T| + (accepted samples of all earlier lanes) +
-// (rank inside the wave's tile); the tile prefix comes from a decoupled
-// look-back.  Tiles are uniform and short, so the look-back rarely waits.
+// Each wave takes one 64-lane propagate tile (grid-stride over blocks, four
+// tiles per block).  Its staged samples take ids |T| + (accepted samples of
+// all earlier tiles) + (rank inside the tile).  The earlier-tile count is the
+// sum of the chunk totals before the tile's chunk plus the per-tile counts
+// inside it: at most a few loads per lane, with no wait on any other block.
+// The last block to finish publishes |V_U| and clears the chunk totals.
 __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ env,
                                                        TraceRec* trace) {
   const Params& p = env->p;
@@ -781,35 +797,24 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
   const int32_t lam = c->lambda;
   const int32_t N = c->N;
   const uint32_t it = (uint32_t)c->it;
-  const uint32_t epoch = c->epoch;
   const uint32_t nwt = done ? 0u : (uint32_t)((lanes + 63) / 64);  // wave tiles
   const uint32_t ntiles = (nwt + 3u) / 4u;
-  const int wave = threadIdx.x >> 6;
-  __shared__ uint32_t s_tile, s_pref;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_commit, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= ntiles) break;
-    uint32_t cnt[4];
-    uint32_t tot = 0, woff = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t wt = tile * 4u + (uint32_t)w;
-      cnt[w] = (wt < nwt) ? d.scount[wt] : 0u;
-      woff += (w < wave) ? cnt[w] : 0u;
-      tot += cnt[w];
-    }
-    if (wave == 0) {
-      const uint32_t pre = lookback_prefix_wave(d.st_prop, tile, tot, epoch, &c->err);
-      if (__lane_id() == 0) s_pref = pre;
-    }
-    __syncthreads();
-    const uint32_t k = __lane_id();
-    if (k < cnt[wave]) {
-      const size_t slot = (size_t)(tile * 4u + (uint32_t)wave) * 64u + k;
-      const int32_t id = N + (int32_t)(s_pref + woff + k);
-      if (id >= N + lanes) {  // cannot happen with a consistent look-back; never write past it
+  const uint32_t lane = __lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t wt = tile * 4u + wave;
+    if (wt >= nwt) continue;
+    const uint32_t cnt = d.scount[wt];
+    if (cnt == 0u) continue;
+    const uint32_t ch = wt / kChunkTiles;
+    unsigned long long part = 0;
+    for (uint32_t j = lane; j < ch; j += 64u) part += d.ssum[j];
+    for (uint32_t j = ch * kChunkTiles + lane; j < wt; j += 64u) part += d.scount[j];
+    const uint32_t pre = (uint32_t)wave_sum_u64(part);
+    if (lane < cnt) {
+      const size_t slot = (size_t)wt * 64u + lane;
+      const int32_t id = N + (int32_t)(pre + lane);
+      if (id >= N + lanes) {  // cannot happen with consistent counts; never write past it
         atomicOr(&c->err, 2u);
       } else {
         const uint32_t sl = d.slane[slot];
@@ -827,15 +832,30 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
         if (trace != nullptr) trace[g].new_id = id;
       }
     }
-    __syncthreads();
   }
+  __shared__ uint32_t s_last;
+  __shared__ unsigned long long s_sum[kPropBlock / 64];
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    const uint32_t prev = atomicAdd(&c->bd_commit, 1u);
-    if (prev == gridDim.x - 1u) {
-      __threadfence();
-      if (!done) c->nU = (int32_t)tile_total(d.st_prop, ntiles);
+    s_last = (atomicAdd(&c->bd_commit, 1u) == gridDim.x - 1u) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
+    unsigned long long part = 0;
+    for (uint32_t j = threadIdx.x; j < nch; j += kPropBlock) {
+      part += d.ssum[j];
+      d.ssum[j] = 0u;
+    }
+    part = wave_sum_u64(part);
+    if (lane == 0) s_sum[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long tot = 0;
+      for (int w = 0; w < kPropBlock / 64; ++w) tot += s_sum[w];
+      if (!done) c->nU = (int32_t)tot;
       c->tk_commit = 0u;
       c->bd_commit = 0u;
     }
@@ -921,6 +941,9 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
     if (tile >= ntiles) break;
     const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
     uint32_t eb = 0;
+    // visited bits of new nodes, merged over runs of nodes in one region
+    uint32_t run_r = 0xffffffffu;
+    unsigned long long run_m = 0ull;
     if (base < (uint32_t)Nt) {
       const uint4 fv = *reinterpret_cast<const uint4*>(d.flag + base);
       const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
@@ -945,8 +968,15 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
           if (i >= (uint32_t)N) {
             // V_U joins T and V_E (Alg. 4)
             E = true;
-            atomicOr(&d.visited[r], 1ull << (cells[k] & 63u));
-            d.avail[r] = 1;
+            if (r != run_r) {
+              if (run_m) {
+                atomicOr(&d.visited[run_r], run_m);
+                d.avail[run_r] = 1;
+              }
+              run_r = r;
+              run_m = 0ull;
+            }
+            run_m |= 1ull << (cells[k] & 63u);
           } else {
             const unsigned long long t = d.thr[r];
             const bool wasE = ((fw[q] >> (8 * k)) & 0xffu) != 0u;
@@ -959,6 +989,10 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
       }
       if (nfw[0] != fw[0] || nfw[1] != fw[1] || nfw[2] != fw[2] || nfw[3] != fw[3])
         *reinterpret_cast<uint4*>(d.flag + base) = make_uint4(nfw[0], nfw[1], nfw[2], nfw[3]);
+      if (run_m) {
+        atomicOr(&d.visited[run_r], run_m);
+        d.avail[run_r] = 1;
+      }
     }
     compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
     __syncthreads();
@@ -1003,7 +1037,7 @@ __global__ void k_path(const Env* __restrict__ env, int32_t node) {
 hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s) {
   int work = p.R;
   if (d.tiles_node > work) work = d.tiles_node;
-  if (d.tiles_prop > work) work = d.tiles_prop;
+  if (d.nchunk > work) work = d.nchunk;
   int grid = (work + 255) / 256;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
@@ -1021,42 +1055,43 @@ hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_frontier(const Env* env, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kNodeBlock), 0, s, env);
+hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t) {
+  hipExtLaunchKernelGGL(k_frontier, dim3(grid), dim3(kNodeBlock), 0, s, t.start, t.stop, 0, env);
   return hipGetLastError();
 }
 
 template <int DYN, int INTEG>
 static hipError_t launch_prop_t(const Env* env, int n_obs, TraceRec* trace, int grid,
-                                hipStream_t s) {
-  hipLaunchKernelGGL((k_propagate<DYN, INTEG>), dim3(grid), dim3(kPropBlock),
-                     propagate_lds_bytes(n_obs), s, env, trace);
+                                hipStream_t s, Timing t) {
+  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG>), dim3(grid), dim3(kPropBlock),
+                        (uint32_t)propagate_lds_bytes(n_obs), s, t.start, t.stop, 0, env, trace);
   return hipGetLastError();
 }
 
 hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
-                            int grid, hipStream_t s) {
+                            int grid, hipStream_t s, Timing t) {
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER>(env, n_obs, trace, grid, s);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER>(env, n_obs, trace, grid, s, t);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4>(env, n_obs, trace, grid, s);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4>(env, n_obs, trace, grid, s, t);
   if (dyn == KP_DYN_QUAD12 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(env, n_obs, trace, grid, s);
-  return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(env, n_obs, trace, grid, s);
+    return launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(env, n_obs, trace, grid, s, t);
+  return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(env, n_obs, trace, grid, s, t);
 }
 
-hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_commit, dim3(grid), dim3(kPropBlock), 0, s, env, trace);
+hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s, Timing t) {
+  hipExtLaunchKernelGGL(k_commit, dim3(grid), dim3(kPropBlock), 0, s, t.start, t.stop, 0, env,
+                        trace);
   return hipGetLastError();
 }
 
-hipError_t launch_region(const Env* env, hipStream_t s) {
-  hipLaunchKernelGGL(k_region, dim3(1), dim3(kRegionBlock), 0, s, env);
+hipError_t launch_region(const Env* env, hipStream_t s, Timing t) {
+  hipExtLaunchKernelGGL(k_region, dim3(1), dim3(kRegionBlock), 0, s, t.start, t.stop, 0, env);
   return hipGetLastError();
 }
 
-hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_nodesets, dim3(grid), dim3(kNodeBlock), 0, s, env);
+hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t) {
+  hipExtLaunchKernelGGL(k_nodesets, dim3(grid), dim3(kNodeBlock), 0, s, t.start, t.stop, 0, env);
   return hipGetLastError();
 }
 
