@@ -226,6 +226,8 @@ def main():
             "launches": n_launch,
             "avg_launch_ms": prop_ms / n_launch if n_launch else None,
             "ops_per_launch": ops / n_launch if n_launch else None,
+            "steps_per_lane": steps_tot / lanes_prof if lanes_prof else None,
+            "box_tests_per_step": box_tot / steps_tot if steps_tot else None,
         },
         "grid": {"propagate": G.stats()["grid_propagate"], "nodes": G.stats()["grid_nodes"]},
         "kernel_ms": {k: v[1] for k, v in kt.items()},

@@ -277,6 +277,21 @@ kp_status sync_ctl(kp_problem* h) {
   return KP_OK;
 }
 
+// propagate totals, kept per counter group on the device
+struct Totals {
+  unsigned long long lanes = 0, valid = 0, steps = 0, box = 0;
+};
+Totals totals(const Ctl& c) {
+  Totals t;
+  for (int g = 0; g < kGroups; ++g) {
+    t.lanes += c.tot[g].lanes;
+    t.valid += c.tot[g].valid;
+    t.steps += c.tot[g].steps;
+    t.box += c.tot[g].box;
+  }
+  return t;
+}
+
 // profiling: hand a launch a pair of events that the runtime stamps with the
 // dispatch's begin and end
 Timing prof_slot(kp_problem* h, int kernel) {
@@ -540,7 +555,11 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
   kp_status st = sync_ctl(h);
   if (st != KP_OK) return st;
   const uint32_t it0 = h->hctl->iters_done;
-  const int per_sync = h->desc.iters_per_sync > 0 ? h->desc.iters_per_sync : 1;
+  // Default: 8 iterations between status reads.  Every kernel reads its
+  // sizes from the device and an oversized grid costs no atomics, so the
+  // host round trip (about 25 us) is paid once per 8 iterations instead of
+  // once per iteration; after a stop the rest of a batch is empty launches.
+  const int per_sync = h->desc.iters_per_sync > 0 ? h->desc.iters_per_sync : 8;
   const long long cap = h->desc.node_cap;
   int status = KP_TIMEOUT;
   for (;;) {
@@ -573,8 +592,9 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
   out->goal_id = (c.goal_id == kNoGoal) ? -1 : c.goal_id;
   out->iterations = (int32_t)(c.iters_done - it0);
   out->n_nodes = c.N;
-  out->lanes_total = c.lanes_total;
-  out->valid_total = c.valid_total;
+  const Totals t = totals(c);
+  out->lanes_total = t.lanes;
+  out->valid_total = t.valid;
   out->path_len = 0;
   if (out->goal_id >= 0) {
     int32_t len = 0;
@@ -597,11 +617,12 @@ kp_status kp_get_stats(kp_problem* h, kp_iter_stats* out) {
   out->done_code = c.done;
   out->n_new = c.nU;
   out->device_error = (int32_t)c.err;
-  out->lanes_total = c.lanes_total;
-  out->valid_total = c.valid_total;
-  out->invalid_total = c.invalid_total;
-  out->steps_total = c.steps_total;
-  out->box_tests_total = c.box_total;
+  const Totals t = totals(c);
+  out->lanes_total = t.lanes;
+  out->valid_total = t.valid;
+  out->invalid_total = t.lanes - t.valid;
+  out->steps_total = t.steps;
+  out->box_tests_total = t.box;
   out->grid_propagate = h->grid_prop_max;
   out->grid_nodes = h->grid_node_max;
   return KP_OK;

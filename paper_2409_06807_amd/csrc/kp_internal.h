@@ -19,6 +19,16 @@ constexpr int32_t kNoGoal = 0x7fffffff;
 
 // Device control block: sizes and counters of the running iteration.  Written
 // only by single threads (finalisers) or by atomics, read at block start.
+// Counters that many blocks update sit in kGroups separate 128-byte lines
+// (group = block index mod kGroups): same-address atomics from the whole
+// chip serialise, about 11 ns each, so one shared line would throttle them.
+constexpr int kGroups = 8;
+struct alignas(128) TotLine {
+  unsigned long long lanes, valid, steps, box;
+};
+struct alignas(128) TkLine {
+  uint32_t v;
+};
 struct alignas(256) Ctl {
   int32_t N;          // |T|
   int32_t nF;         // |V_E| for the next expansion
@@ -29,16 +39,18 @@ struct alignas(256) Ctl {
   int32_t goal_id;    // smallest new node id in X_goal, kNoGoal if none
   int32_t done;       // 0 running, else KP_SOLVED / KP_TREE_FULL / KP_FRONTIER_EMPTY
   uint32_t epoch;     // tags look-back status words; bumped once per iteration
-  uint32_t tk_front, tk_prop, tk_nodes;   // tile tickets
-  uint32_t bd_front, bd_prop, bd_nodes;   // blocks finished (last-block finalisation)
+  uint32_t tk_front, tk_nodes;   // tile tickets of the node passes
+  uint32_t bd_front, bd_nodes;   // blocks finished (last-block finalisation)
   uint32_t err;       // nonzero: a look-back wait hit its spin limit
   uint32_t iters_done;
-  uint32_t tk_commit, bd_commit;
-  // the running totals sit on their own 128-byte line, away from the tickets
-  uint32_t pad_[13];
-  unsigned long long lanes_total, valid_total, invalid_total, steps_total, box_total;
+  // the iteration as k_commit saw it, read by k_nodesets (whose finaliser
+  // rewrites N, it, epoch and done while other blocks may still start)
+  int32_t sN, snU, sit, sdone;
+  uint32_t sepoch;
+  TotLine tot[kGroups];  // propagate totals per group; the host adds the groups
+  TkLine tkp[kGroups];   // propagate tile tickets per group; cleared by k_commit
 };
-static_assert(__builtin_offsetof(Ctl, lanes_total) == 128, "Ctl totals on their own line");
+static_assert(sizeof(Ctl) <= 4096, "control block size");
 
 // Problem constants, passed by value to every kernel.
 struct Params {

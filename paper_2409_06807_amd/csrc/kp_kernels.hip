@@ -132,7 +132,7 @@ __device__ __forceinline__ uint32_t tile_total(unsigned long long* st, uint32_t 
 __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t* s_wt,
                                                   uint32_t* s_pref, unsigned long long* st,
                                                   uint32_t tile, uint32_t epoch, uint32_t* err,
-                                                  uint32_t* prefix) {
+                                                  uint32_t* prefix, uint32_t* tile_total = nullptr) {
   const int w = threadIdx.x >> 6;
   if (__lane_id() == 0) s_wt[w] = wave_total;
   __syncthreads();
@@ -149,6 +149,7 @@ __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t*
   }
   __syncthreads();
   *prefix = *s_pref;
+  if (tile_total) *tile_total = agg;
   return off;
 }
 
@@ -386,6 +387,16 @@ __global__ void k_zero(const Env* __restrict__ env) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.nchunk; t += stride) d.ssum[t] = 0u;
 }
 
+__device__ void clear_counters(Ctl* c) {
+  c->tk_front = c->tk_nodes = 0u;
+  c->bd_front = c->bd_nodes = 0u;
+  c->err = 0u;
+  for (int g = 0; g < kGroups; ++g) {
+    c->tot[g].lanes = c->tot[g].valid = c->tot[g].steps = c->tot[g].box = 0ull;
+    c->tkp[g].v = 0u;
+  }
+}
+
 __global__ void k_root(const Env* __restrict__ env, Vec12 xi) {
   const Params& p = env->p;
   const Dev& d = env->d;
@@ -412,11 +423,8 @@ __global__ void k_root(const Env* __restrict__ env, Vec12 xi) {
   c->goal_id = in_goal ? 0 : kNoGoal;
   c->done = in_goal ? KP_SOLVED : 0;
   c->epoch = c->epoch + 1u;
-  c->tk_front = c->tk_prop = c->tk_nodes = c->tk_commit = 0u;
-  c->bd_front = c->bd_prop = c->bd_nodes = c->bd_commit = 0u;
-  c->err = 0u;
   c->iters_done = 0u;
-  c->lanes_total = c->valid_total = c->invalid_total = c->steps_total = c->box_total = 0ull;
+  clear_counters(c);
 }
 
 // state loaded from the host: counters for |T| = N at iteration `it`
@@ -433,31 +441,32 @@ __global__ void k_set_ctl(const Env* __restrict__ env, int32_t N, int32_t it) {
   c->goal_id = kNoGoal;
   c->done = 0;
   c->epoch = c->epoch + 1u;
-  c->tk_front = c->tk_prop = c->tk_nodes = c->tk_commit = 0u;
-  c->bd_front = c->bd_prop = c->bd_nodes = c->bd_commit = 0u;
-  c->err = 0u;
-  c->lanes_total = c->valid_total = c->invalid_total = c->steps_total = c->box_total = 0ull;
+  clear_counters(c);
+  for (int j = 0; j < d.nchunk; ++j) d.ssum[j] = 0u;
 }
 
 // ---------------------------------------------------------------------------
 // frontier compaction shared by k_frontier and k_nodesets
 // ---------------------------------------------------------------------------
 // E-bits of the four nodes held by this thread -> F, in ascending id order.
-__device__ __forceinline__ void compact_frontier(const Dev& d, unsigned long long* st,
-                                                 uint32_t ebits, uint32_t base, uint32_t tile,
-                                                 uint32_t epoch, uint32_t* s_wt, uint32_t* s_pref) {
-  uint32_t wt;
+// Returns the number of E nodes up to and including this tile.
+__device__ __forceinline__ uint32_t compact_frontier(const Dev& d, unsigned long long* st,
+                                                     uint32_t ebits, uint32_t base, uint32_t tile,
+                                                     uint32_t epoch, uint32_t* s_wt,
+                                                     uint32_t* s_pref) {
+  uint32_t wt, agg;
   const uint32_t c = __popc(ebits);
   const uint32_t ex = wave_excl_small(c, &wt);
   uint32_t prefix;
   const uint32_t woff =
-      block_offsets(wt, s_wt, s_pref, st, tile, epoch, &d.ctl->err, &prefix);
+      block_offsets(wt, s_wt, s_pref, st, tile, epoch, &d.ctl->err, &prefix, &agg);
   uint32_t pos = prefix + woff + ex;
   while (ebits) {
     const int k = __ffs(ebits) - 1;
     d.F[pos++] = (int32_t)(base + k);
     ebits &= ebits - 1u;
   }
+  return prefix + agg;
 }
 
 // last-block finalisation of the frontier: |V_E|, eq. (6), termination codes
@@ -561,17 +570,24 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   // per-wave running totals (wave-uniform), flushed once per block
   unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0;
 
-  if (ntiles > 0)
-    for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
-      const int ob = k / 6, comp = k - 6 * ob;
-      lds[k] = d.obs[(size_t)comp * n_obs + ob];
-    }
+  // A wave's first tile is its index in the grid.  Later tiles come from
+  // per-group ticket counters: group q (block index mod ng) hands out tiles
+  // nwaves + ng * k + q.  No burst of tickets at launch, and each counter
+  // sees about 1/ng of the requests.  A block whose first tiles are all past
+  // the end has nothing to do (an oversized grid costs no atomics).
+  const uint32_t nwaves = gridDim.x * (kPropBlock / 64);
+  const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
+  const uint32_t grp = blockIdx.x % ng;
+  if (blockIdx.x * (kPropBlock / 64) >= ntiles) return;
+  for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
+    const int ob = k / 6, comp = k - 6 * ob;
+    lds[k] = d.obs[(size_t)comp * n_obs + ob];
+  }
   __syncthreads();
 
+  uint32_t next = blockIdx.x * (kPropBlock / 64) + (uint32_t)wave;
   for (;;) {
-    uint32_t tk = 0;
-    if (__lane_id() == 0) tk = atomicAdd(&c->tk_prop, 1u);
-    const uint32_t tile = __builtin_amdgcn_readfirstlane(tk);
+    const uint32_t tile = next;
     if (tile >= ntiles) break;
 
     const int32_t g = (int32_t)(tile * 64u + __lane_id());
@@ -743,6 +759,11 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       t->accept = accept ? 1 : 0;
       t->new_id = id;
     }
+    {
+      uint32_t tk = 0;
+      if (__lane_id() == 0) tk = atomicAdd(&c->tkp[grp].v, 1u);
+      next = nwaves + ng * __builtin_amdgcn_readfirstlane(tk) + grp;
+    }
     t_lanes += (unsigned long long)__popcll(__ballot(active));
     t_valid += (unsigned long long)__popcll(__ballot(active && valid));
     t_steps += wave_sum_u64((unsigned long long)steps);
@@ -762,18 +783,11 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
     for (int w = 0; w < kPropBlock / 64; ++w)
       for (int q = 0; q < 4; ++q) a[q] += s_tot[w][q];
     if (a[0]) {
-      atomicAdd(&c->lanes_total, a[0]);
-      atomicAdd(&c->valid_total, a[1]);
-      atomicAdd(&c->invalid_total, a[0] - a[1]);
-      atomicAdd(&c->steps_total, a[2]);
-      atomicAdd(&c->box_total, a[3]);
-    }
-    __threadfence();
-    const uint32_t prev = atomicAdd(&c->bd_prop, 1u);
-    if (prev == gridDim.x - 1u) {
-      __threadfence();
-      c->tk_prop = 0u;
-      c->bd_prop = 0u;
+      TotLine* t = &c->tot[blockIdx.x % kGroups];
+      atomicAdd(&t->lanes, a[0]);
+      atomicAdd(&t->valid, a[1]);
+      atomicAdd(&t->steps, a[2]);
+      atomicAdd(&t->box, a[3]);
     }
   }
 }
@@ -786,7 +800,8 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
 // all earlier tiles) + (rank inside the tile).  The earlier-tile count is the
 // sum of the chunk totals before the tile's chunk plus the per-tile counts
 // inside it: at most a few loads per lane, with no wait on any other block.
-// The last block to finish publishes |V_U| and clears the chunk totals.
+// The first wave of block 0 publishes |V_U| (the sum of all chunk totals)
+// and clears the propagate tickets; k_nodesets clears the chunk totals.
 __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ env,
                                                        TraceRec* trace) {
   const Params& p = env->p;
@@ -801,6 +816,22 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
   const uint32_t ntiles = (nwt + 3u) / 4u;
   const uint32_t lane = __lane_id();
   const uint32_t wave = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && wave == 0) {
+    const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
+    unsigned long long part = 0;
+    for (uint32_t j = lane; j < nch; j += 64u) part += d.ssum[j];
+    part = wave_sum_u64(part);
+    if (lane == 0) {
+      if (!done) c->nU = (int32_t)part;
+      c->sN = N;
+      c->snU = done ? 0 : (int32_t)part;
+      c->sit = (int32_t)it;
+      c->sdone = done;
+      c->sepoch = c->epoch;
+      c->tk_nodes = 0u;
+    }
+    if (lane < (uint32_t)kGroups) c->tkp[lane].v = 0u;
+  }
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint32_t wt = tile * 4u + wave;
     if (wt >= nwt) continue;
@@ -831,33 +862,6 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
         if (sl & 1u) atomicMin(&c->goal_id, id);
         if (trace != nullptr) trace[g].new_id = id;
       }
-    }
-  }
-  __shared__ uint32_t s_last;
-  __shared__ unsigned long long s_sum[kPropBlock / 64];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = (atomicAdd(&c->bd_commit, 1u) == gridDim.x - 1u) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
-    unsigned long long part = 0;
-    for (uint32_t j = threadIdx.x; j < nch; j += kPropBlock) {
-      part += d.ssum[j];
-      d.ssum[j] = 0u;
-    }
-    part = wave_sum_u64(part);
-    if (lane == 0) s_sum[wave] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long tot = 0;
-      for (int w = 0; w < kPropBlock / 64; ++w) tot += s_sum[w];
-      if (!done) c->nU = (int32_t)tot;
-      c->tk_commit = 0u;
-      c->bd_commit = 0u;
     }
   }
 }
@@ -925,19 +929,24 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
   const Params& p = env->p;
   const Dev& d = env->d;
   Ctl* c = d.ctl;
-  const int done = c->done;
-  const int32_t N = c->N;
-  const int32_t nU = c->nU;
+  const int done = c->sdone;
+  const int32_t N = c->sN;
+  const int32_t nU = c->snU;
   const int32_t Nt = N + nU;
-  const uint32_t it = (uint32_t)c->it;
-  const uint32_t epoch = c->epoch;
+  const uint32_t it = (uint32_t)c->sit;
+  const uint32_t epoch = c->sepoch;
   const bool goal = c->goal_id != kNoGoal;
   const uint32_t ntiles = done ? 0u : (uint32_t)((Nt + kNodeTile - 1) / kNodeTile);
+  // accepted-sample chunk totals of this iteration's expansion: used up
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < d.nchunk; j += kNodeBlock) d.ssum[j] = 0u;
+  // First tile = block index (blocks start in index order, so a tile's
+  // look-back only waits on tiles of blocks already running); later tiles
+  // from the ticket counter, in order.  The block that holds the last tile
+  // finalises the iteration once its look-back has given the total.
   __shared__ uint32_t s_tile, s_pref, s_wt[4];
+  uint32_t tile = blockIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
     if (tile >= ntiles) break;
     const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
     uint32_t eb = 0;
@@ -994,26 +1003,19 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
         d.avail[run_r] = 1;
       }
     }
-    compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
-    __syncthreads();
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(&c->bd_nodes, 1u);
-    if (prev == gridDim.x - 1u) {
-      __threadfence();
-      if (!done) {
-        c->N = Nt;
-        if (goal) c->done = KP_SOLVED;
-        finalize_frontier(p, c, tile_total(d.st_nodes, ntiles), Nt);
-        c->it = (int32_t)it + 1;
-        c->epoch = epoch + 1u;
-        c->iters_done += 1u;
-      }
-      c->tk_nodes = 0u;
-      c->bd_nodes = 0u;
+    const uint32_t upto = compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
+    if (tile == ntiles - 1u && threadIdx.x == 0) {
+      c->N = Nt;
+      if (goal) c->done = KP_SOLVED;
+      finalize_frontier(p, c, upto, Nt);
+      c->it = (int32_t)it + 1;
+      c->epoch = epoch + 1u;
+      c->iters_done += 1u;
     }
+    if (threadIdx.x == 0) s_tile = gridDim.x + atomicAdd(&c->tk_nodes, 1u);
+    __syncthreads();
+    tile = s_tile;
+    __syncthreads();
   }
 }
 
