@@ -33,7 +33,7 @@ extern "C" {
 #define KP_ABI_VERSION 1u
 #define KP_MAX_STATE 12
 #define KP_MAX_CONTROL 4
-#define KP_MAX_OBSTACLES 2040
+#define KP_MAX_OBSTACLES 1536  /* per-block LDS (obstacle table + candidate lists) stays under 64 KiB */
 
 typedef enum {
   KP_OK = 0,

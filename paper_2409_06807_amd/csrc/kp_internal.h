@@ -62,7 +62,8 @@ struct Params {
   float goal_c[3];
   float w_lo[3];        // workspace lower corner
   float inv_w[3];       // fine cells per unit length
-  float x_lo[12], x_hi[12];
+  alignas(64) float x_lo[12];   // 64-byte aligned: one wide scalar load each
+  alignas(64) float x_hi[12];
   float u_lo[4], u_hi[4];
   float mass, grav, Ixx, Iyy, Izz;
   float inv_m, inv_Ixx, inv_Iyy, inv_Izz;

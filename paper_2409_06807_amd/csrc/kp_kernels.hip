@@ -208,7 +208,6 @@ struct Dim<KP_DYN_QUAD12> {
 template <int DYN>
 struct StepC {
   float h, inv_m, grav, inv_Ixx, inv_Iyy, inv_Izz, dIyz, dIzx, dIxy;
-  float x_lo[Dim<DYN>::n], x_hi[Dim<DYN>::n];
 };
 
 template <int DYN>
@@ -223,11 +222,6 @@ __device__ __forceinline__ StepC<DYN> load_step_consts(const Params& p) {
   s.dIyz = p.dIyz;
   s.dIzx = p.dIzx;
   s.dIxy = p.dIxy;
-#pragma unroll
-  for (int i = 0; i < Dim<DYN>::n; ++i) {
-    s.x_lo[i] = p.x_lo[i];
-    s.x_hi[i] = p.x_hi[i];
-  }
   return s;
 }
 
@@ -343,9 +337,15 @@ __device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u
 template <int DYN, class PP>
 __device__ __forceinline__ bool state_ok(const PP& p, const float* x) {
   constexpr int n = Dim<DYN>::n;
+  float lo[n], hi[n];
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    lo[i] = p.x_lo[i];
+    hi[i] = p.x_hi[i];
+  }
   bool ok = true;
 #pragma unroll
-  for (int i = 0; i < n; ++i) ok = ok && (x[i] >= p.x_lo[i]) && (x[i] <= p.x_hi[i]);
+  for (int i = 0; i < n; ++i) ok = ok && (x[i] >= lo[i]) && (x[i] <= hi[i]);
   return ok;  // NaN fails both comparisons
 }
 
@@ -526,9 +526,29 @@ __global__ __launch_bounds__(kNodeBlock) void k_frontier(const Env* __restrict__
 // ---------------------------------------------------------------------------
 // k_propagate: Alg. 2
 // ---------------------------------------------------------------------------
-size_t propagate_lds_bytes(int n_obs) {
-  const size_t b = (size_t)n_obs * (6 * sizeof(float) + 4 * sizeof(uint16_t));
-  return b < 16 ? 16 : b;
+// LDS of a propagate block: the obstacle table ((n_obs + 1) boxes of six
+// floats; box n_obs is a sentinel that no segment touches), then per wave a
+// union candidate list, kGroupsPerWave group lists and their counts.
+constexpr int kLaneGroup = 4;                       // lanes per culling group
+constexpr int kGroupsPerWave = 64 / kLaneGroup;
+constexpr int kGroupCap = 30;                       // candidates a group list holds
+constexpr int kGroupStride = kGroupCap + 2;         // + room to pad to an even length
+constexpr uint32_t kGroupCull = 8;                  // longer union lists are split per group
+__host__ __device__ constexpr int union_stride(int n_obs) { return (n_obs + 2 + 3) & ~3; }
+__host__ __device__ constexpr size_t wave_lds_bytes(int n_obs) {
+  return (size_t)union_stride(n_obs) * 2 + (size_t)kGroupsPerWave * kGroupStride * 2 +
+         (size_t)kGroupsPerWave * 4;
+}
+constexpr size_t prop_lds_bytes(int n_obs) {
+  return (size_t)(n_obs + 1) * 6 * sizeof(float) + (size_t)(kPropBlock / 64) * wave_lds_bytes(n_obs);
+}
+static_assert(prop_lds_bytes(KP_MAX_OBSTACLES) <= 65536, "propagate LDS above 64 KiB");
+size_t propagate_lds_bytes(int n_obs) { return prop_lds_bytes(n_obs); }
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+  return v;
 }
 
 // Separation of two closed boxes: the largest gap along any axis between a
@@ -566,7 +586,11 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   const int wave = threadIdx.x >> 6;
   // obstacle k in LDS: lo x, lo y, lo z, hi x, hi y, hi z (6 floats, read as 3 float2)
   const float2* obox = reinterpret_cast<const float2*>(lds);
-  uint16_t* cand = reinterpret_cast<uint16_t*>(lds + 6 * n_obs) + wave * n_obs;
+  char* wlds = reinterpret_cast<char*>(lds) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
+               (size_t)wave * wave_lds_bytes(n_obs);
+  uint16_t* cand = reinterpret_cast<uint16_t*>(wlds);
+  uint16_t* glist = cand + union_stride(n_obs);
+  uint32_t* gcnt = reinterpret_cast<uint32_t*>(glist + kGroupsPerWave * kGroupStride);
   // per-wave running totals (wave-uniform), flushed once per block
   unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0;
 
@@ -583,6 +607,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
     const int ob = k / 6, comp = k - 6 * ob;
     lds[k] = d.obs[(size_t)comp * n_obs + ob];
   }
+  if (threadIdx.x < 6) lds[6 * n_obs + threadIdx.x] = (threadIdx.x < 3) ? 3.0e38f : -3.0e38f;
   __syncthreads();
 
   uint32_t next = blockIdx.x * (kPropBlock / 64) + (uint32_t)wave;
@@ -618,12 +643,15 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       for (int j = 0; j < m; ++j) u[j] = 0.0f;
     }
 
-    // Per-wave obstacle culling.  Until its first failing step, a segment
-    // stays within rc (per axis) of its parent: every checked step starts
-    // from a state inside the velocity bounds.  Obstacles that overlap the
-    // union of the wave's parent boxes grown by rc + margin are copied to a
-    // wave-private candidate list; the step loop then reads only those, with
-    // wave-uniform indices (LDS broadcast).
+    // Obstacle culling.  Until its first failing step, a segment stays
+    // within rc (per axis) of its parent: every checked step starts from a
+    // state inside the velocity bounds.  Obstacles that overlap the union of
+    // the wave's parent boxes grown by rc + margin form the wave's union
+    // list.  The parents of one tile can lie far apart, and then the union
+    // box covers much of the scene; one such tile ran several times longer
+    // than the rest and set the launch time.  So a long union list is culled
+    // again per group of four lanes (one parent when lambda = 4) into short
+    // group lists; a lane tests only its group's list.
     const float big = 3.0e38f;
     const float bx0 = wave_min(active ? x[0] - p.rc : big);
     const float by0 = wave_min(active ? x[1] - p.rc : big);
@@ -643,8 +671,63 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
       if (ov) cand[ncand + __popcll(b & lanes_below())] = (uint16_t)k;
       ncand += (uint32_t)__popcll(b);
     }
-    // the candidate list is private to this wave: order its LDS writes before
-    // the wave-wide reads below
+    // the candidate lists are private to this wave: order their LDS writes
+    // before the reads of other lanes below
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t lane = __lane_id();
+    const uint16_t* my = cand;  // this lane's candidate list and its length
+    uint32_t mycnt = ncand;
+    if (ncand > kGroupCull) {
+      // group box: the reach boxes of lanes 4q .. 4q+3
+      float q0 = active ? x[0] - p.rc : big, q1 = active ? x[1] - p.rc : big;
+      float q2 = active ? x[2] - p.rc : big, q3 = active ? x[0] + p.rc : -big;
+      float q4 = active ? x[1] + p.rc : -big, q5 = active ? x[2] + p.rc : -big;
+#pragma unroll
+      for (int o = 1; o < kLaneGroup; o <<= 1) {
+        q0 = fminf(q0, __shfl_xor(q0, o));
+        q1 = fminf(q1, __shfl_xor(q1, o));
+        q2 = fminf(q2, __shfl_xor(q2, o));
+        q3 = fmaxf(q3, __shfl_xor(q3, o));
+        q4 = fmaxf(q4, __shfl_xor(q4, o));
+        q5 = fmaxf(q5, __shfl_xor(q5, o));
+      }
+      // in the passes below lane l serves group l % 16 and union entries
+      // c0 + l / 16, so one pass tests four entries against all 16 groups
+      const uint32_t gq = lane & (kGroupsPerWave - 1);
+      const int src = (int)gq * kLaneGroup;
+      const float m = p.margin;
+      const float b0 = __shfl(q0, src) - m, b1 = __shfl(q1, src) - m, b2 = __shfl(q2, src) - m;
+      const float b3 = __shfl(q3, src) + m, b4 = __shfl(q4, src) + m, b5 = __shfl(q5, src) + m;
+      const unsigned long long gm = 0x0001000100010001ull << gq;
+      uint32_t qn = 0;
+      for (uint32_t c0 = 0; c0 < ncand; c0 += 4) {
+        const uint32_t ci = c0 + (lane >> 4);
+        bool ov = false;
+        uint32_t ob = 0;
+        if (ci < ncand) {
+          ob = cand[ci];
+          ov = box_separation(b0, b1, b2, b3, b4, b5, obox + 3 * ob) <= 0.0f;
+        }
+        const unsigned long long hb = __ballot(ov) & gm;
+        const uint32_t pos = qn + (uint32_t)__popcll(hb & lanes_below());
+        if (ov && pos < (uint32_t)kGroupCap) glist[gq * kGroupStride + pos] = (uint16_t)ob;
+        qn += (uint32_t)__popcll(hb);
+      }
+      if (lane < (uint32_t)kGroupsPerWave) gcnt[lane] = qn;
+      // every group fits: each lane takes its group's list; else the union
+      if (__ballot(qn > (uint32_t)kGroupCap) == 0ull) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t g4 = lane / kLaneGroup;
+        my = glist + g4 * kGroupStride;
+        mycnt = gcnt[g4];
+      }
+    }
+    // every list is read to the same even length; pad with the sentinel
+    const uint32_t kmax = (__builtin_amdgcn_readfirstlane(wave_max_u32(mycnt)) + 1u) & ~1u;
+    for (uint32_t k = mycnt + (lane & (kLaneGroup - 1)); k < kmax; k += kLaneGroup)
+      const_cast<uint16_t*>(my)[k] = (uint16_t)n_obs;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 
@@ -660,30 +743,26 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
         const float px = x[0], py = x[1], pz = x[2];
         integ_step<DYN, INTEG>(sc, x, u);
         steps = j + 1;
-        bool ok = state_ok<DYN>(sc, x);
+        bool ok = state_ok<DYN>(p, x);
         if (ok) {
           const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
           const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;
           const float lz = fminf(pz, x[2]) - margin, hz = fmaxf(pz, x[2]) + margin;
           // six comparisons per candidate (closed boxes: touching is a hit);
           // measured faster here than the separation form used for culling.
-          // Two candidates per trip so that their LDS reads overlap.
+          // Two candidates per trip (one 32-bit read of their indices) so
+          // that their LDS reads overlap.
           bool hit = false;
-          uint32_t q = 0;
-          for (; q + 1 < ncand; q += 2) {
-            const float* o = reinterpret_cast<const float*>(obox + 3 * cand[q]);
-            const float* r = reinterpret_cast<const float*>(obox + 3 * cand[q + 1]);
+          for (uint32_t q = 0; q < kmax; q += 2) {
+            const uint32_t ij = *reinterpret_cast<const uint32_t*>(my + q);
+            const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
+            const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
             hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
                    (o[2] <= hz);
             hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
                    (r[2] <= hz);
           }
-          if (q < ncand) {
-            const float* o = reinterpret_cast<const float*>(obox + 3 * cand[q]);
-            hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
-                   (o[2] <= hz);
-          }
-          box_tests += ncand;
+          box_tests += mycnt;
           ok = !hit;
         }
         if (!ok) {
