@@ -139,6 +139,7 @@ struct kp_problem {
   int cu_count;
   int grid_prop_max;
   int grid_node_max;
+  int grid_commit_max;
   int stage;  // 0: next is kp_expand; 1: next is kp_update_regions; 2: next is kp_update_tree
   Ctl* hctl;  // pinned host mirror of the control block
   std::string err;
@@ -327,7 +328,8 @@ kp_status do_frontier(kp_problem* h) {
 
 // grids from the last host-known sizes (exact after a status read; upper
 // bounds otherwise -- the kernels read the true sizes from device memory)
-kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub) {
+// with_region: the commit launch also runs Alg. 3 in one extra block (kp_plan)
+kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_region) {
   long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
   int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
   if (grid < 1) grid = 1;
@@ -335,9 +337,10 @@ kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub) {
                                   h->desc.n_obstacles, trace, grid, h->stream,
                                   prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
-  int cgrid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
+  const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
+  int cgrid = (int)(ctiles < h->grid_commit_max ? ctiles : h->grid_commit_max);
   if (cgrid < 1) cgrid = 1;
-  e = launch_commit(h->env_dev, trace, cgrid, h->stream, prof_slot(h, 4));
+  e = launch_commit(h->env_dev, trace, cgrid, with_region ? 1 : 0, h->stream, prof_slot(h, 4));
   if (e != hipSuccess) return hip_fail(h, e, "commit launch");
   return KP_OK;
 }
@@ -458,11 +461,13 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
     delete h;
     return KP_E_DEVICE;
   }
-  int bp = 1, bn = 1;
+  int bp = 1, bn = 1, bc = 1;
   occupancy_propagate(desc->dynamics, desc->integrator, desc->n_obstacles, &bp);
   occupancy_nodes(&bn);
+  occupancy_commit(&bc);
   h->grid_prop_max = bp * h->cu_count;
   h->grid_node_max = bn * h->cu_count;
+  h->grid_commit_max = bc * h->cu_count;
   if (hipHostMalloc(reinterpret_cast<void**>(&h->hctl), sizeof(Ctl), hipHostMallocDefault) !=
       hipSuccess) {
     delete h;
@@ -518,7 +523,7 @@ kp_status kp_expand(kp_problem* h, void* dev_trace) {
   if (!h) return KP_E_ARG;
   if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_expand must follow kp_update_tree");
   const long long ub = (long long)h->desc.node_cap - h->hctl->N;
-  kp_status st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1);
+  kp_status st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1, false);
   if (st != KP_OK) return st;
   h->stage = 1;
   return KP_OK;
@@ -578,8 +583,7 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
       // exact sizes for the first iteration of a batch, bounds after it
       const long long lanes_ub = (b == 0) ? c.lanes : cap - c.N;
       const long long nodes_ub = (b == 0) ? (long long)c.N + c.lanes : cap;
-      if ((st = do_propagate(h, nullptr, lanes_ub)) != KP_OK) return st;
-      if ((st = do_region(h)) != KP_OK) return st;
+      if ((st = do_propagate(h, nullptr, lanes_ub, true)) != KP_OK) return st;
       if ((st = do_nodesets(h, nodes_ub)) != KP_OK) return st;
     }
     if ((st = sync_ctl(h)) != KP_OK) return st;

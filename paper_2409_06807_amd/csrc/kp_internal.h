@@ -13,6 +13,7 @@ constexpr int kNodesPerThread = 16;  // nodes per thread in the node passes
 constexpr int kNodeTile = 4096;      // nodes per node-pass tile
 constexpr int kChunkTiles = 256;     // 64-lane wave tiles per accepted-sample chunk sum
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
+constexpr int kCommitBlock = 1024;   // threads per commit block (16 waves)
 constexpr int kMaxPath = 65536;      // longest path kp_get_path can return
 constexpr int kDoneNone = 0;
 constexpr int32_t kNoGoal = 0x7fffffff;
@@ -137,13 +138,15 @@ hipError_t launch_root(const Env* env, Vec12 x_init, hipStream_t s);
 hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
                             int grid, hipStream_t s, Timing t);
-hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s, Timing t);
+hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
+                         hipStream_t s, Timing t);
 hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
 int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
+int occupancy_commit(int* blocks_per_cu);
 size_t propagate_lds_bytes(int n_obs);
 
 }  // namespace kp

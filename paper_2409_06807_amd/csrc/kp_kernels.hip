@@ -874,15 +874,26 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
 // ---------------------------------------------------------------------------
 // k_commit: ids of the accepted samples (V_U of Alg. 2), stable in lane order
 // ---------------------------------------------------------------------------
-// Each wave takes one 64-lane propagate tile (grid-stride over blocks, four
-// tiles per block).  Its staged samples take ids |T| + (accepted samples of
-// all earlier tiles) + (rank inside the tile).  The earlier-tile count is the
+// Each wave takes 64-lane propagate tiles, grid-stride over the waves of the
+// commit blocks.  Its staged samples take ids |T| + (accepted samples of all
+// earlier tiles) + (rank inside the tile).  The earlier-tile count is the
 // sum of the chunk totals before the tile's chunk plus the per-tile counts
 // inside it: at most a few loads per lane, with no wait on any other block.
 // The first wave of block 0 publishes |V_U| (the sum of all chunk totals)
 // and clears the propagate tickets; k_nodesets clears the chunk totals.
-__global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ env,
-                                                       TraceRec* trace) {
+// With with_region set, the last block instead runs UpdateEstimates (Alg. 3):
+// it reads only what k_propagate wrote and the tree's visited bits, none of
+// which the commit blocks touch, so the two run side by side.
+template <int NT>
+__device__ void region_body(const Env* __restrict__ env);
+
+__global__ __launch_bounds__(kCommitBlock) void k_commit(const Env* __restrict__ env,
+                                                         TraceRec* trace, int with_region) {
+  if (with_region && blockIdx.x == gridDim.x - 1u) {
+    region_body<kCommitBlock>(env);
+    return;
+  }
+  const uint32_t nblk = with_region ? gridDim.x - 1u : gridDim.x;  // >= 1 (launcher)
   const Params& p = env->p;
   const Dev& d = env->d;
   Ctl* c = d.ctl;
@@ -892,7 +903,6 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
   const int32_t N = c->N;
   const uint32_t it = (uint32_t)c->it;
   const uint32_t nwt = done ? 0u : (uint32_t)((lanes + 63) / 64);  // wave tiles
-  const uint32_t ntiles = (nwt + 3u) / 4u;
   const uint32_t lane = __lane_id();
   const uint32_t wave = threadIdx.x >> 6;
   if (blockIdx.x == 0 && wave == 0) {
@@ -911,9 +921,8 @@ __global__ __launch_bounds__(kPropBlock) void k_commit(const Env* __restrict__ e
     }
     if (lane < (uint32_t)kGroups) c->tkp[lane].v = 0u;
   }
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint32_t wt = tile * 4u + wave;
-    if (wt >= nwt) continue;
+  constexpr uint32_t wpb = kCommitBlock / 64;
+  for (uint32_t wt = blockIdx.x * wpb + wave; wt < nwt; wt += nblk * wpb) {
     const uint32_t cnt = d.scount[wt];
     if (cnt == 0u) continue;
     const uint32_t ch = wt / kChunkTiles;
@@ -961,27 +970,29 @@ __device__ __forceinline__ double region_score(double delta, unsigned long long 
   return num / den;
 }
 
-__global__ __launch_bounds__(kRegionBlock) void k_region(const Env* __restrict__ env) {
+// One workgroup of NT threads: three passes over the regions.
+template <int NT>
+__device__ void region_body(const Env* __restrict__ env) {
   const Params& p = env->p;
   const Dev& d = env->d;
   Ctl* c = d.ctl;
   if (c->done) return;
-  __shared__ double s_max[kRegionBlock / 64];
-  __shared__ unsigned long long s_sum[kRegionBlock / 64];
+  __shared__ double s_max[NT / 64];
+  __shared__ unsigned long long s_sum[NT / 64];
   const int wave = threadIdx.x >> 6;
   // pass 1: largest score
   double mx = 0.0;
-  for (int r = threadIdx.x; r < p.R; r += kRegionBlock)
+  for (int r = threadIdx.x; r < p.R; r += NT)
     if (d.avail[r]) mx = fmax(mx, region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r])));
   mx = wave_max_f64(mx);
   if (__lane_id() == 0) s_max[wave] = mx;
   __syncthreads();
   mx = 0.0;
-  for (int k = 0; k < kRegionBlock / 64; ++k) mx = fmax(mx, s_max[k]);
+  for (int k = 0; k < NT / 64; ++k) mx = fmax(mx, s_max[k]);
   const int e = (mx > 0.0) ? ilogb(mx) : 0;
   // pass 2: exact integer sum of the scores scaled by 2^(46 - e)
   unsigned long long q = 0;
-  for (int r = threadIdx.x; r < p.R; r += kRegionBlock)
+  for (int r = threadIdx.x; r < p.R; r += NT)
     if (d.avail[r]) {
       const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
       q += (unsigned long long)floor(ldexp(sc, 46 - e));
@@ -990,15 +1001,19 @@ __global__ __launch_bounds__(kRegionBlock) void k_region(const Env* __restrict__
   if (__lane_id() == 0) s_sum[wave] = q;
   __syncthreads();
   unsigned long long Q = 0;
-  for (int k = 0; k < kRegionBlock / 64; ++k) Q += s_sum[k];
+  for (int k = 0; k < NT / 64; ++k) Q += s_sum[k];
   // pass 3: P_accept = min(1, q / Q + eps) as a 32-bit threshold
-  for (int r = threadIdx.x; r < p.R; r += kRegionBlock) {
+  for (int r = threadIdx.x; r < p.R; r += NT) {
     if (!d.avail[r]) continue;
     const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
     const unsigned long long qr = (unsigned long long)floor(ldexp(sc, 46 - e));
     const double P = (Q > 0ull) ? (double)qr / (double)Q + p.eps : p.eps;
     d.thr[r] = (P >= 1.0) ? (1ull << 32) : (unsigned long long)floor(P * 4294967296.0);
   }
+}
+
+__global__ __launch_bounds__(kRegionBlock) void k_region(const Env* __restrict__ env) {
+  region_body<kRegionBlock>(env);
 }
 
 // ---------------------------------------------------------------------------
@@ -1160,9 +1175,12 @@ hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, Trace
   return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(env, n_obs, trace, grid, s, t);
 }
 
-hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, hipStream_t s, Timing t) {
-  hipExtLaunchKernelGGL(k_commit, dim3(grid), dim3(kPropBlock), 0, s, t.start, t.stop, 0, env,
-                        trace);
+hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
+                         hipStream_t s, Timing t) {
+  if (grid < 1) grid = 1;
+  if (with_region) grid += 1;  // the extra, last block runs the region pass
+  hipExtLaunchKernelGGL(k_commit, dim3(grid), dim3(kCommitBlock), 0, s, t.start, t.stop, 0, env,
+                        trace, with_region);
   return hipGetLastError();
 }
 
@@ -1196,6 +1214,15 @@ int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu) {
   else if (dyn == KP_DYN_DI6) nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4>(n_obs);
   else if (integ == KP_INT_EULER) nb = occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(n_obs);
   else nb = occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(n_obs);
+  *blocks_per_cu = nb;
+  return nb;
+}
+
+int occupancy_commit(int* blocks_per_cu) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_commit, kCommitBlock, 0) != hipSuccess)
+    nb = 1;
+  if (nb < 1) nb = 1;
   *blocks_per_cu = nb;
   return nb;
 }
