@@ -141,6 +141,7 @@ struct kp_problem {
   int grid_node_max;
   int grid_commit_max;
   int stage;  // 0: next is kp_expand; 1: next is kp_update_regions; 2: next is kp_update_tree
+  bool ctl_fresh = false;  // hctl holds the device control block (no launch since the last read)
   Ctl* hctl;  // pinned host mirror of the control block
   std::string err;
   // profiling
@@ -275,6 +276,7 @@ kp_status sync_ctl(kp_problem* h) {
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
   if (h->hctl->err) return fail(h, KP_E_DEVICE, "a kernel hit an internal wait limit");
+  h->ctl_fresh = true;
   return KP_OK;
 }
 
@@ -317,9 +319,11 @@ void prof_collect(kp_problem* h) {
   h->ev_used = 0;
 }
 
-kp_status do_frontier(kp_problem* h) {
-  const int tiles = (h->L.capP + kNodeTile - 1) / kNodeTile;
-  int grid = tiles < h->grid_node_max ? tiles : h->grid_node_max;
+// n_nodes: |T| as the host knows it (exact: reset or a loaded tree)
+kp_status do_frontier(kp_problem* h, long long n_nodes) {
+  h->ctl_fresh = false;
+  const long long tiles = (n_nodes + kNodeTile - 1) / kNodeTile;
+  int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
   if (grid < 1) grid = 1;
   hipError_t e = launch_frontier(h->env_dev, grid, h->stream, prof_slot(h, 3));
   if (e != hipSuccess) return hip_fail(h, e, "frontier launch");
@@ -330,6 +334,7 @@ kp_status do_frontier(kp_problem* h) {
 // bounds otherwise -- the kernels read the true sizes from device memory)
 // with_region: the commit launch also runs Alg. 3 in one extra block (kp_plan)
 kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_region) {
+  h->ctl_fresh = false;
   long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
   int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
   if (grid < 1) grid = 1;
@@ -346,12 +351,14 @@ kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool 
 }
 
 kp_status do_region(kp_problem* h) {
+  h->ctl_fresh = false;
   hipError_t e = launch_region(h->env_dev, h->stream, prof_slot(h, 1));
   if (e != hipSuccess) return hip_fail(h, e, "region launch");
   return KP_OK;
 }
 
 kp_status do_nodesets(kp_problem* h, long long nodes_ub) {
+  h->ctl_fresh = false;
   long long tiles = (nodes_ub + kNodeTile - 1) / kNodeTile;
   int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
   if (grid < 1) grid = 1;
@@ -369,6 +376,7 @@ hipError_t upload_env(kp_problem* h) {
 }
 
 kp_status init_state(kp_problem* h) {
+  h->ctl_fresh = false;
   hipError_t e = upload_env(h);
   if (e != hipSuccess) return hip_fail(h, e, "environment upload");
   e = launch_zero(h->prm, h->dev, h->env_dev, h->stream);
@@ -377,7 +385,7 @@ kp_status init_state(kp_problem* h) {
   for (int k = 0; k < 12; ++k) xi.v[k] = h->desc.x_init[k];
   e = launch_root(h->env_dev, xi, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "root launch");
-  kp_status st = do_frontier(h);
+  kp_status st = do_frontier(h, 1);
   if (st != KP_OK) return st;
   h->stage = 0;
   return sync_ctl(h);
@@ -557,7 +565,7 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
   if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_plan must start after a complete iteration");
   std::memset(out, 0, sizeof(*out));
   const auto t0 = std::chrono::steady_clock::now();
-  kp_status st = sync_ctl(h);
+  kp_status st = h->ctl_fresh ? KP_OK : sync_ctl(h);  // the mirror is current after a reset
   if (st != KP_OK) return st;
   const uint32_t it0 = h->hctl->iters_done;
   // Default: 8 iterations between status reads.  Every kernel reads its
@@ -713,9 +721,10 @@ kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in) {
   if (e == hipSuccess) e = hipMemcpyAsync(h->dev.thr, in->thr, R * 8, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "tree load");
+  h->ctl_fresh = false;
   e = launch_set_ctl(h->env_dev, N, in->iteration, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "control load");
-  kp_status st = do_frontier(h);
+  kp_status st = do_frontier(h, N);
   if (st != KP_OK) return st;
   h->stage = 0;
   return sync_ctl(h);

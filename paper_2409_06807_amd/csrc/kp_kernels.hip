@@ -265,13 +265,41 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
   *c = __uint_as_float(__float_as_uint(cv) ^ (((uint32_t)(q + 1) & 2u) << 30));
 }
 
+// sin and cos of a tilt angle (roll, pitch).  For |x| <= 1.6 (the tilts a
+// state box admits, with room for the RK4 stage states) near-minimax
+// polynomials on [-1.6, 1.6] of degree 9 (sin, odd) and 10 (cos, even)
+// apply with no reduction: measured against FP64 sin/cos in FP32 Horner
+// form, sin is within 2.2 ulp and cos within 8.6e-8 absolute.  A wave with
+// any larger angle also runs the full reduction for those lanes.
+__device__ __forceinline__ void sincos_tilt(float x, float* s, float* c) {
+  const float t = x * x;
+  float ps = __builtin_fmaf(t, 0x1.61f3d4p-19f, -0x1.9fccc6p-13f);
+  ps = __builtin_fmaf(t, ps, 0x1.111106p-7f);
+  ps = __builtin_fmaf(t, ps, -0x1.555556p-3f);
+  float sv = __builtin_fmaf(x * t, ps, x);
+  float pc = __builtin_fmaf(t, -0x1.1ae382p-22f, 0x1.9fb708p-16f);
+  pc = __builtin_fmaf(t, pc, -0x1.6c15cap-10f);
+  pc = __builtin_fmaf(t, pc, 0x1.555554p-5f);
+  pc = __builtin_fmaf(t, pc, -0.5f);
+  float cv = __builtin_fmaf(t, pc, 1.0f);
+  const bool big = !(__builtin_fabsf(x) <= 1.6f);  // NaN too
+  if (__builtin_expect(__ballot(big) != 0ull, 0)) {
+    float s2, c2;
+    sincos_rr(x, &s2, &c2);
+    sv = big ? s2 : sv;
+    cv = big ? c2 : cv;
+  }
+  *s = sv;
+  *c = cv;
+}
+
 // rigid-body quadcopter, ZYX Euler angles, inertial velocity, body rates
 template <class PP>
 __device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const float* u,
                                            float* dx) {
   float sf, cf, st, ct, sp, cp;
-  sincos_rr(x[3], &sf, &cf);
-  sincos_rr(x[4], &st, &ct);
+  sincos_tilt(x[3], &sf, &cf);
+  sincos_tilt(x[4], &st, &ct);
   sincos_rr(x[5], &sp, &cp);
   const float ict = __builtin_amdgcn_rcpf(ct);  // 1 ulp; |theta| stays far from pi/2
   const float P = x[9], Q = x[10], R = x[11];
@@ -347,6 +375,27 @@ __device__ __forceinline__ bool state_ok(const PP& p, const float* x) {
 #pragma unroll
   for (int i = 0; i < n; ++i) ok = ok && (x[i] >= lo[i]) && (x[i] <= hi[i]);
   return ok;  // NaN fails both comparisons
+}
+
+// the same test with the box read from LDS (lo at b[0..11], hi at b[12..23]):
+// six 16-byte broadcast reads issued together instead of dependent scalar loads
+template <int DYN>
+__device__ __forceinline__ bool state_ok_lds(const float* __restrict__ b, const float* x) {
+  constexpr int n = Dim<DYN>::n;
+  float bb[24];
+  const float4* b4 = reinterpret_cast<const float4*>(b);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float4 v = b4[i];
+    bb[4 * i] = v.x;
+    bb[4 * i + 1] = v.y;
+    bb[4 * i + 2] = v.z;
+    bb[4 * i + 3] = v.w;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < n; ++i) ok &= (x[i] >= bb[i]) & (x[i] <= bb[12 + i]);
+  return ok;
 }
 
 // fine cell (region * 64 + sub-cell) of a finite position, clamped to W
@@ -539,8 +588,10 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int n_obs) {
   return (size_t)union_stride(n_obs) * 2 + (size_t)kGroupsPerWave * kGroupStride * 2 +
          (size_t)kGroupsPerWave * 4;
 }
+constexpr int kBoundsFloats = 2 * 12;   // state box (lo[12], hi[12]) at the start of the block LDS
 constexpr size_t prop_lds_bytes(int n_obs) {
-  return (size_t)(n_obs + 1) * 6 * sizeof(float) + (size_t)(kPropBlock / 64) * wave_lds_bytes(n_obs);
+  return kBoundsFloats * sizeof(float) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
+         (size_t)(kPropBlock / 64) * wave_lds_bytes(n_obs);
 }
 static_assert(prop_lds_bytes(KP_MAX_OBSTACLES) <= 65536, "propagate LDS above 64 KiB");
 size_t propagate_lds_bytes(int n_obs) { return prop_lds_bytes(n_obs); }
@@ -585,8 +636,10 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   const int n_obs = p.n_obs;
   const int wave = threadIdx.x >> 6;
   // obstacle k in LDS: lo x, lo y, lo z, hi x, hi y, hi z (6 floats, read as 3 float2)
-  const float2* obox = reinterpret_cast<const float2*>(lds);
-  char* wlds = reinterpret_cast<char*>(lds) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
+  float* bnd = lds;  // state box
+  float* otab = lds + kBoundsFloats;
+  const float2* obox = reinterpret_cast<const float2*>(otab);
+  char* wlds = reinterpret_cast<char*>(otab) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
                (size_t)wave * wave_lds_bytes(n_obs);
   uint16_t* cand = reinterpret_cast<uint16_t*>(wlds);
   uint16_t* glist = cand + union_stride(n_obs);
@@ -605,9 +658,13 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   if (blockIdx.x * (kPropBlock / 64) >= ntiles) return;
   for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
     const int ob = k / 6, comp = k - 6 * ob;
-    lds[k] = d.obs[(size_t)comp * n_obs + ob];
+    otab[k] = d.obs[(size_t)comp * n_obs + ob];
   }
-  if (threadIdx.x < 6) lds[6 * n_obs + threadIdx.x] = (threadIdx.x < 3) ? 3.0e38f : -3.0e38f;
+  if (threadIdx.x < 6) otab[6 * n_obs + threadIdx.x] = (threadIdx.x < 3) ? 3.0e38f : -3.0e38f;
+  if (threadIdx.x < (unsigned)n) {
+    bnd[threadIdx.x] = p.x_lo[threadIdx.x];
+    bnd[12 + threadIdx.x] = p.x_hi[threadIdx.x];
+  }
   __syncthreads();
 
   uint32_t next = blockIdx.x * (kPropBlock / 64) + (uint32_t)wave;
@@ -743,7 +800,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
         const float px = x[0], py = x[1], pz = x[2];
         integ_step<DYN, INTEG>(sc, x, u);
         steps = j + 1;
-        bool ok = state_ok<DYN>(p, x);
+        bool ok = state_ok_lds<DYN>(bnd, x);
         if (ok) {
           const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
           const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;
