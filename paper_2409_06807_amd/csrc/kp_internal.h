@@ -8,9 +8,9 @@
 namespace kp {
 
 constexpr int kPropBlock = 256;      // lanes per propagate tile (4 waves)
-constexpr int kNodeBlock = 256;      // threads per node-pass block
-constexpr int kNodesPerThread = 16;  // nodes per thread in the node passes
-constexpr int kNodeTile = 4096;      // nodes per node-pass tile
+constexpr int kNodeBlock = 1024;     // threads per node-pass block
+constexpr int kNodesPerThread = 4;   // nodes per thread in the node passes
+constexpr int kNodeTile = kNodeBlock * kNodesPerThread;  // nodes per node-pass tile (4096)
 constexpr int kChunkTiles = 256;     // 64-lane wave tiles per accepted-sample chunk sum
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
 constexpr int kCommitBlock = 1024;   // threads per commit block (16 waves)

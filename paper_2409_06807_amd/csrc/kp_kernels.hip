@@ -126,8 +126,8 @@ __device__ __forceinline__ uint32_t tile_total(unsigned long long* st, uint32_t 
   return (uint32_t)w;
 }
 
-// Block-wide (4 waves) exclusive offsets: per-wave totals in s_wt, then thread
-// 0 resolves the tile's global prefix.  Returns the wave's offset inside the
+// Block-wide exclusive offsets (kNodeBlock / 64 waves): per-wave totals in
+// s_wt, then wave 0 resolves the tile's global prefix.  Returns the wave's offset inside the
 // tile; *prefix receives the tile's global exclusive prefix.
 __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t* s_wt,
                                                   uint32_t* s_pref, unsigned long long* st,
@@ -138,7 +138,7 @@ __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t*
   __syncthreads();
   uint32_t off = 0, agg = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kNodeBlock / 64; ++k) {
     const uint32_t t = s_wt[k];
     off += (k < w) ? t : 0u;
     agg += t;
@@ -494,10 +494,29 @@ __global__ void k_set_ctl(const Env* __restrict__ env, int32_t N, int32_t it) {
   for (int j = 0; j < d.nchunk; ++j) d.ssum[j] = 0u;
 }
 
+// flag bytes of the kNodesPerThread nodes a thread holds, as 32-bit words
+constexpr int kFlagWords = kNodesPerThread / 4;
+static_assert(kNodesPerThread == 4 || kNodesPerThread == 16, "flag word loads");
+__device__ __forceinline__ void load_flag_words(const uint8_t* f, uint32_t* w) {
+  if constexpr (kNodesPerThread == 16) {
+    const uint4 v = *reinterpret_cast<const uint4*>(f);
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+  } else {
+    w[0] = *reinterpret_cast<const uint32_t*>(f);
+  }
+}
+__device__ __forceinline__ void store_flag_words(uint8_t* f, const uint32_t* w) {
+  if constexpr (kNodesPerThread == 16) {
+    *reinterpret_cast<uint4*>(f) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else {
+    *reinterpret_cast<uint32_t*>(f) = w[0];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // frontier compaction shared by k_frontier and k_nodesets
 // ---------------------------------------------------------------------------
-// E-bits of the four nodes held by this thread -> F, in ascending id order.
+// E-bits of the nodes held by this thread -> F, in ascending id order.
 // Returns the number of E nodes up to and including this tile.
 __device__ __forceinline__ uint32_t compact_frontier(const Dev& d, unsigned long long* st,
                                                      uint32_t ebits, uint32_t base, uint32_t tile,
@@ -543,15 +562,15 @@ __global__ __launch_bounds__(kNodeBlock) void k_frontier(const Env* __restrict__
   const int done = c->done;
   const uint32_t epoch = c->epoch;
   const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
-  __shared__ uint32_t s_tile, s_pref, s_wt[4];
+  __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_front, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) break;
     const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
-    const uint4 fv = *reinterpret_cast<const uint4*>(d.flag + base);
-    const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
+    uint32_t fw[kFlagWords];
+    load_flag_words(d.flag + base, fw);
     uint32_t eb = 0;
 #pragma unroll
     for (int k = 0; k < kNodesPerThread; ++k)
@@ -982,25 +1001,44 @@ __global__ __launch_bounds__(kCommitBlock) void k_commit(const Env* __restrict__
   for (uint32_t wt = blockIdx.x * wpb + wave; wt < nwt; wt += nblk * wpb) {
     const uint32_t cnt = d.scount[wt];
     if (cnt == 0u) continue;
+    // The staged record and the parent id do not depend on the tile's
+    // offset: their loads go out together with the offset's.
+    const bool mine = lane < cnt;
+    const size_t slot = (size_t)wt * 64u + lane;
+    uint32_t sl = 0, scl = 0;
+    int32_t par = 0;
+    float xs[12], us[4];
+    if (mine) {
+      sl = d.slane[slot];
+      scl = d.scell[slot];
+#pragma unroll
+      for (int q = 0; q < 12; ++q)
+        if (q < p.n) xs[q] = d.sx[(size_t)q * d.capP + slot];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < p.m) us[q] = d.su[(size_t)q * d.capP + slot];
+      par = d.F[(int32_t)(sl >> 1) / lam];
+    }
     const uint32_t ch = wt / kChunkTiles;
     unsigned long long part = 0;
     for (uint32_t j = lane; j < ch; j += 64u) part += d.ssum[j];
     for (uint32_t j = ch * kChunkTiles + lane; j < wt; j += 64u) part += d.scount[j];
     const uint32_t pre = (uint32_t)wave_sum_u64(part);
-    if (lane < cnt) {
-      const size_t slot = (size_t)wt * 64u + lane;
+    if (mine) {
       const int32_t id = N + (int32_t)(pre + lane);
       if (id >= N + lanes) {  // cannot happen with consistent counts; never write past it
         atomicOr(&c->err, 2u);
       } else {
-        const uint32_t sl = d.slane[slot];
         const int32_t g = (int32_t)(sl >> 1);
-        const int32_t e = g / lam;
-        const int32_t s = g - e * lam;
-        for (int q = 0; q < p.n; ++q) d.x[(size_t)q * d.capP + id] = d.sx[(size_t)q * d.capP + slot];
-        for (int q = 0; q < p.m; ++q) d.u[(size_t)q * d.capP + id] = d.su[(size_t)q * d.capP + slot];
-        d.parent[id] = d.F[e];
-        d.cell[id] = d.scell[slot];
+        const int32_t s = g - (g / lam) * lam;
+#pragma unroll
+        for (int q = 0; q < 12; ++q)
+          if (q < p.n) d.x[(size_t)q * d.capP + id] = xs[q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < p.m) d.u[(size_t)q * d.capP + id] = us[q];
+        d.parent[id] = par;
+        d.cell[id] = scl;
         d.flag[id] = 1;
         d.birth[id] = (int32_t)it;
         d.sample[id] = (uint8_t)s;
@@ -1028,6 +1066,11 @@ __device__ __forceinline__ double region_score(double delta, unsigned long long 
 }
 
 // One workgroup of NT threads: three passes over the regions.
+// Up to kRegionsHeld regions per thread keep their score in registers
+// across the three passes (one read of the region counters); larger grids
+// recompute the score in each pass.  Same arithmetic either way.
+constexpr int kRegionsHeld = 4;
+
 template <int NT>
 __device__ void region_body(const Env* __restrict__ env) {
   const Params& p = env->p;
@@ -1037,10 +1080,24 @@ __device__ void region_body(const Env* __restrict__ env) {
   __shared__ double s_max[NT / 64];
   __shared__ unsigned long long s_sum[NT / 64];
   const int wave = threadIdx.x >> 6;
-  // pass 1: largest score
+  const bool held = p.R <= kRegionsHeld * NT;
+  double sc_h[kRegionsHeld];
+  // pass 1: largest score (a region outside R_avail scores -1)
   double mx = 0.0;
-  for (int r = threadIdx.x; r < p.R; r += NT)
-    if (d.avail[r]) mx = fmax(mx, region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r])));
+  if (held) {
+#pragma unroll
+    for (int k = 0; k < kRegionsHeld; ++k) {
+      const int r = threadIdx.x + k * NT;
+      sc_h[k] = -1.0;
+      if (r < p.R && d.avail[r])
+        sc_h[k] = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
+      mx = fmax(mx, sc_h[k]);
+    }
+  } else {
+    for (int r = threadIdx.x; r < p.R; r += NT)
+      if (d.avail[r])
+        mx = fmax(mx, region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r])));
+  }
   mx = wave_max_f64(mx);
   if (__lane_id() == 0) s_max[wave] = mx;
   __syncthreads();
@@ -1049,23 +1106,39 @@ __device__ void region_body(const Env* __restrict__ env) {
   const int e = (mx > 0.0) ? ilogb(mx) : 0;
   // pass 2: exact integer sum of the scores scaled by 2^(46 - e)
   unsigned long long q = 0;
-  for (int r = threadIdx.x; r < p.R; r += NT)
-    if (d.avail[r]) {
-      const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
-      q += (unsigned long long)floor(ldexp(sc, 46 - e));
-    }
+  if (held) {
+#pragma unroll
+    for (int k = 0; k < kRegionsHeld; ++k)
+      if (sc_h[k] >= 0.0) q += (unsigned long long)floor(ldexp(sc_h[k], 46 - e));
+  } else {
+    for (int r = threadIdx.x; r < p.R; r += NT)
+      if (d.avail[r]) {
+        const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
+        q += (unsigned long long)floor(ldexp(sc, 46 - e));
+      }
+  }
   q = wave_sum_u64(q);
   if (__lane_id() == 0) s_sum[wave] = q;
   __syncthreads();
   unsigned long long Q = 0;
   for (int k = 0; k < NT / 64; ++k) Q += s_sum[k];
   // pass 3: P_accept = min(1, q / Q + eps) as a 32-bit threshold
-  for (int r = threadIdx.x; r < p.R; r += NT) {
-    if (!d.avail[r]) continue;
-    const double sc = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
+  auto thr_of = [&](double sc) -> unsigned long long {
     const unsigned long long qr = (unsigned long long)floor(ldexp(sc, 46 - e));
     const double P = (Q > 0ull) ? (double)qr / (double)Q + p.eps : p.eps;
-    d.thr[r] = (P >= 1.0) ? (1ull << 32) : (unsigned long long)floor(P * 4294967296.0);
+    return (P >= 1.0) ? (1ull << 32) : (unsigned long long)floor(P * 4294967296.0);
+  };
+  if (held) {
+#pragma unroll
+    for (int k = 0; k < kRegionsHeld; ++k) {
+      const int r = threadIdx.x + k * NT;
+      if (r < p.R && sc_h[k] >= 0.0) d.thr[r] = thr_of(sc_h[k]);
+    }
+  } else {
+    for (int r = threadIdx.x; r < p.R; r += NT) {
+      if (!d.avail[r]) continue;
+      d.thr[r] = thr_of(region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r])));
+    }
   }
 }
 
@@ -1095,7 +1168,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
   // look-back only waits on tiles of blocks already running); later tiles
   // from the ticket counter, in order.  The block that holds the last tile
   // finalises the iteration once its look-back has given the total.
-  __shared__ uint32_t s_tile, s_pref, s_wt[4];
+  __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
   uint32_t tile = blockIdx.x;
   for (;;) {
     if (tile >= ntiles) break;
@@ -1105,9 +1178,10 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
     uint32_t run_r = 0xffffffffu;
     unsigned long long run_m = 0ull;
     if (base < (uint32_t)Nt) {
-      const uint4 fv = *reinterpret_cast<const uint4*>(d.flag + base);
-      const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
-      uint32_t nfw[4] = {fv.x, fv.y, fv.z, fv.w};
+      uint32_t fw[kFlagWords], nfw[kFlagWords];
+      load_flag_words(d.flag + base, fw);
+#pragma unroll
+      for (int q = 0; q < kFlagWords; ++q) nfw[q] = fw[q];
 #pragma unroll
       for (int q = 0; q < kNodesPerThread / 4; ++q) {
         const uint32_t b4 = base + 4u * q;
@@ -1147,8 +1221,10 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
           if (E) eb |= 1u << (4 * q + k);
         }
       }
-      if (nfw[0] != fw[0] || nfw[1] != fw[1] || nfw[2] != fw[2] || nfw[3] != fw[3])
-        *reinterpret_cast<uint4*>(d.flag + base) = make_uint4(nfw[0], nfw[1], nfw[2], nfw[3]);
+      bool changed = false;
+#pragma unroll
+      for (int q = 0; q < kFlagWords; ++q) changed |= nfw[q] != fw[q];
+      if (changed) store_flag_words(d.flag + base, nfw);
       if (run_m) {
         atomicOr(&d.visited[run_r], run_m);
         d.avail[run_r] = 1;
