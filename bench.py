@@ -111,6 +111,67 @@ def run_cpu_baseline(name: str, budget_s: float):
     }
 
 
+def percentile(v, q):
+    if not v:
+        return None
+    s = sorted(v)
+    k = (len(s) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def expand_only(G, p, dyn, integ, reps):
+    """Propagation at full occupancy: grow seed 0's tree step by step and stop
+    before the first expansion whose lane count would stop growing (the
+    largest iteration of the query), then time that expansion `reps` times,
+    reloading the tree before each one."""
+    import torch
+    G.reset(0)
+    best = None
+    while True:
+        st = G.stats()
+        if st["done_code"]:
+            break
+        lanes = st["n_frontier"] * st["lambda"]
+        if best is not None and lanes < best[0]:
+            break
+        if best is None or lanes >= max(best[0], 1 << 16):
+            best = (lanes, G.copy_tree())
+        G.expand()
+        G.update_regions()
+        G.update_tree()
+    lanes, tree = best
+    times = []
+    steps = boxes = 0
+    for _ in range(reps):
+        G.load_tree(tree)
+        s0 = G.stats()
+        G.set_profiling(True)
+        G.expand()
+        torch.cuda.synchronize()
+        kt = G.kernel_times()
+        G.set_profiling(False)
+        s1 = G.stats()
+        times.append(kt["propagate"][1])
+        steps = s1["steps_total"] - s0["steps_total"]
+        boxes = s1["box_tests_total"] - s0["box_tests_total"]
+        G.update_regions()
+        G.update_tree()
+    ms = statistics.median(times)
+    philox_per_lane = 2 if dyn == 1 else 1
+    ops = steps * STEP_OPS[(dyn, integ)] + boxes * BOX_TEST_OPS + lanes * philox_per_lane * PHILOX_OPS
+    tf = ops / (ms * 1e-3) / 1e12
+    print(json.dumps({
+        "mode": "expand-only", "workload": p["name"], "iteration": int(tree["it"]),
+        "tree_nodes": int(tree["N"]), "lanes": int(lanes), "repetitions": reps,
+        "propagate_ms_median": ms, "propagate_ms_all": times,
+        "lanes_per_us": lanes / (ms * 1e3), "steps_per_lane": steps / lanes,
+        "box_tests_per_step": boxes / steps if steps else None,
+        "algorithmic_tflops": tf, "peak_tflops": PEAK_FP32_TFLOPS,
+        "frac": tf / PEAK_FP32_TFLOPS}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +183,10 @@ def main():
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters-per-sync", type=int, default=0)
+    ap.add_argument("--expand-only", action="store_true",
+                    help="instead of whole queries, time the propagate kernel on the largest "
+                         "iteration of one query (the tree reloaded before each repetition) and "
+                         "print that measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (a kernel of known "
                          "traffic, used to calibrate hardware byte counters)")
@@ -144,6 +209,9 @@ def main():
     p = gpu_workload(args.workload, 0)
     G = Planner(p, device="cuda:0", iters_per_sync=args.iters_per_sync)
     dyn, integ = int(p["dynamics"]), int(p["integrator"])
+    if args.expand_only:
+        expand_only(G, p, dyn, integ, max(args.steps, 1))
+        return
 
     # warm-up and profiled queries reuse the timed seeds, so that a profiler's
     # per-kernel average over the whole run describes the same launch mix
@@ -211,6 +279,8 @@ def main():
         },
         "median_tts_ms": statistics.median(solved) if solved else None,
         "mean_tts_ms": statistics.mean(solved) if solved else None,
+        "p10_tts_ms": percentile(solved, 10),
+        "p90_tts_ms": percentile(solved, 90),
         "success_rate": len(solved) / len(results),
         "attempted_expansions_per_s": lanes / elapsed,
         "statuses": [r["status"] for r in results],

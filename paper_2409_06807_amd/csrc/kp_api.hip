@@ -275,7 +275,13 @@ kp_status sync_ctl(kp_problem* h) {
   if (e != hipSuccess) return hip_fail(h, e, "status copy");
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
-  if (h->hctl->err) return fail(h, KP_E_DEVICE, "a kernel hit an internal wait limit");
+  if (const uint32_t err = h->hctl->err) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg,
+                  "device check failed (bits 0x%x: 1 frontier look-back wait limit, 2 commit id "
+                  "past |T| + lanes, 4 node-set look-back wait limit)", err);
+    return fail(h, KP_E_DEVICE, msg);
+  }
   h->ctl_fresh = true;
   return KP_OK;
 }

@@ -76,7 +76,7 @@ __device__ __forceinline__ uint32_t wave_excl_small(uint32_t c, uint32_t* total)
 // for tiles with smaller tickets, all held by running blocks, so the wait
 // always ends; the spin bound only guards against a broken invariant.
 __device__ uint32_t lookback_prefix_wave(unsigned long long* st, uint32_t tile, uint32_t agg,
-                                         uint32_t epoch, uint32_t* err) {
+                                         uint32_t epoch, uint32_t* err, uint32_t err_bit) {
   const unsigned long long tag = (unsigned long long)(epoch & 0x3fffffffu) << 34;
   const int lane = (int)__lane_id();
   if (tile == 0) {
@@ -103,7 +103,7 @@ __device__ uint32_t lookback_prefix_wave(unsigned long long* st, uint32_t tile, 
     const unsigned long long need = (limit == 63) ? ~0ull : ((1ull << (limit + 1)) - 1ull);
     if ((rm & need) != need) {
       if (++spins > (1u << 22)) {
-        if (lane == 0) atomicOr(err, 1u);
+        if (lane == 0) atomicOr(err, err_bit);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -132,7 +132,8 @@ __device__ __forceinline__ uint32_t tile_total(unsigned long long* st, uint32_t 
 __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t* s_wt,
                                                   uint32_t* s_pref, unsigned long long* st,
                                                   uint32_t tile, uint32_t epoch, uint32_t* err,
-                                                  uint32_t* prefix, uint32_t* tile_total = nullptr) {
+                                                  uint32_t* prefix, uint32_t err_bit,
+                                                  uint32_t* tile_total = nullptr) {
   const int w = threadIdx.x >> 6;
   if (__lane_id() == 0) s_wt[w] = wave_total;
   __syncthreads();
@@ -144,7 +145,7 @@ __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t*
     agg += t;
   }
   if (w == 0) {
-    const uint32_t pre = lookback_prefix_wave(st, tile, agg, epoch, err);
+    const uint32_t pre = lookback_prefix_wave(st, tile, agg, epoch, err, err_bit);
     if (__lane_id() == 0) *s_pref = pre;
   }
   __syncthreads();
@@ -527,7 +528,8 @@ __device__ __forceinline__ uint32_t compact_frontier(const Dev& d, unsigned long
   const uint32_t ex = wave_excl_small(c, &wt);
   uint32_t prefix;
   const uint32_t woff =
-      block_offsets(wt, s_wt, s_pref, st, tile, epoch, &d.ctl->err, &prefix, &agg);
+      block_offsets(wt, s_wt, s_pref, st, tile, epoch, &d.ctl->err, &prefix,
+                    st == d.st_nodes ? 4u : 1u, &agg);
   uint32_t pos = prefix + woff + ex;
   while (ebits) {
     const int k = __ffs(ebits) - 1;
@@ -1164,12 +1166,22 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
   // accepted-sample chunk totals of this iteration's expansion: used up
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < d.nchunk; j += kNodeBlock) d.ssum[j] = 0u;
-  // First tile = block index (blocks start in index order, so a tile's
-  // look-back only waits on tiles of blocks already running); later tiles
-  // from the ticket counter, in order.  The block that holds the last tile
-  // finalises the iteration once its look-back has given the total.
+  // With a tile for every block, tile = block index: blocks start in index
+  // order, so a tile's look-back only waits on blocks that started earlier.
+  // With more tiles than blocks, every tile comes from the ticket counter
+  // (including the first): a block then only waits on tiles handed out
+  // before its own, all held by running blocks, whatever the number of
+  // blocks that fit on the device at once.  The block that holds the last
+  // tile finalises the iteration once its look-back has given the total.
   __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
+  const bool by_ticket = ntiles > gridDim.x;
   uint32_t tile = blockIdx.x;
+  if (by_ticket) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
+    __syncthreads();
+    tile = s_tile;
+    __syncthreads();
+  }
   for (;;) {
     if (tile >= ntiles) break;
     const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
@@ -1239,7 +1251,8 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
       c->epoch = epoch + 1u;
       c->iters_done += 1u;
     }
-    if (threadIdx.x == 0) s_tile = gridDim.x + atomicAdd(&c->tk_nodes, 1u);
+    if (!by_ticket) break;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
     __syncthreads();
     tile = s_tile;
     __syncthreads();

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import problem_small_di, problem_small_quad, RK4
+from workloads import problem_small_di, problem_small_quad, problem_c5, RK4
 
 import lockstep
 
@@ -28,6 +28,9 @@ CASES = {
     "di-rk4": lambda: problem_small_di(seed=3, cap=4096, n_obs=12, integrator=RK4),
     "di-sub1": lambda: problem_small_di(seed=4, cap=2500, n_obs=20, grid=(4, 4, 4), sub=1),
     "quad-rk4": lambda: problem_small_quad(seed=1, cap=8192, n_obs=60),
+    # the c5 building (1200 boxes, 32^3 regions, lambda_max 8) at a small cap:
+    # more regions than the region pass holds in registers
+    "c5-building": lambda: problem_c5(seed=1, node_cap=12000),
 }
 
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import problem_small_di, problem_small_quad, problem_c1, problem_c2
+from workloads import problem_small_di, problem_small_quad, problem_c1, problem_c2, problem_c5
 
 from test_oracle_planner import near_goal_problem, check_invariants, expected_controls
 
@@ -217,3 +217,63 @@ def test_c2_full_size_properties(iters):
     check_gpu_invariants(p, g, stats)
     worst = check_sampled_edges(p, g, 300)
     print(f"c2: N={g['N']} iterations={r['iterations']} worst edge rel err {worst:.2e}")
+
+
+def test_c5_full_size_properties():
+    p = problem_c5(seed=0, max_iters=10)
+    _say("c5 full size, 10 iterations")
+    G = planner(p)
+    r = G.plan()
+    g = G.copy_tree()
+    stats = G.stats()
+    assert stats["device_error"] == 0
+    assert r["iterations"] == 10 or r["status"] != oracle.TIMEOUT
+    check_gpu_invariants(p, g, stats)
+    worst = check_sampled_edges(p, g, 300)
+    print(f"c5: N={g['N']} iterations={r['iterations']} worst edge rel err {worst:.2e}")
+
+
+def replay_path_edgewise(p, g, path):
+    """FP64 replay of a returned path one edge at a time: each segment starts
+    from its parent's stored state (what the planner integrated from), runs
+    the stored control for K steps, must stay in the state box and off the
+    un-inflated obstacles at every step, and must end within 1e-5 relative of
+    the stored child.  The last end must lie in the goal ball.  (The quad is
+    open-loop unstable, so a single replay from the root would amplify FP32
+    rounding along the path instead of checking it.)"""
+    K = int(p["steps"])
+    worst = 0.0
+    for a, b in zip(path[:-1], path[1:]):
+        x = g["x"][a].astype(np.float64)
+        u = g["u"][b].astype(np.float64)
+        for _ in range(K):
+            y = oracle.step(p, x, u)
+            # the obstacles without the planner's margin, less the 1e-4 band
+            if not oracle.state_ok(p, y, relax=1e-4) or oracle.swept_hit(p, x, y, -1e-4):
+                return False, False, worst
+            x = y
+        worst = max(worst, float(np.max(np.abs(g["x"][b] - x) / np.maximum(1.0, np.abs(x)))))
+    c = np.asarray(p["goal_center"], np.float64)
+    reached = float(np.sqrt(np.sum((x[:3] - c) ** 2))) <= float(p["goal_radius"]) + 1e-4
+    return True, reached, worst
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c2_solution_replays_in_fp64(seed):
+    # the full-size forest query to its goal: every edge of the returned path
+    # replays in FP64 as valid against the un-inflated obstacles, and the path
+    # ends in the goal ball
+    p = problem_c2(seed=seed)
+    _say(f"c2 full solve seed={seed}")
+    G = planner(p)
+    r = G.plan()
+    assert r["status"] == oracle.SOLVED, r
+    path = G.path(r["goal_id"])
+    assert path[0] == 0 and path[-1] == r["goal_id"] and len(path) == r["path_len"]
+    g = G.copy_tree()
+    assert np.all(g["parent"][path[1:]] == path[:-1])
+    valid, reached, worst = replay_path_edgewise(p, g, path)
+    assert valid and reached and worst <= 1e-5, (valid, reached, worst)
+    print(f"c2 seed {seed}: path of {len(path)} nodes, worst edge rel err {worst:.2e}")
+    G.close()
+
