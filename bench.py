@@ -133,7 +133,7 @@ def expand_only(G, p, dyn, integ, reps):
         st = G.stats()
         if st["done_code"]:
             break
-        lanes = st["n_frontier"] * st["lambda"]
+        lanes = st["n_frontier"] * st["lam"]
         if best is not None and lanes < best[0]:
             break
         if best is None or lanes >= max(best[0], 1 << 16):

@@ -321,6 +321,41 @@ __device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const fl
   dx[11] = __builtin_fmaf(p.dIxy * P, Q, u[3]) * p.inv_Izz;
 }
 
+// the quadcopter derivative with sin / cos of the yaw angle supplied
+template <class PP>
+__device__ __forceinline__ void deriv_quad_y(const PP& p, const float* x, const float* u, float sp,
+                                             float cp, float* dx) {
+  float sf, cf, st, ct;
+  sincos_tilt(x[3], &sf, &cf);
+  sincos_tilt(x[4], &st, &ct);
+  const float ict = __builtin_amdgcn_rcpf(ct);
+  const float P = x[9], Q = x[10], R = x[11];
+  const float a = __builtin_fmaf(Q, sf, R * cf);
+  dx[0] = x[6];
+  dx[1] = x[7];
+  dx[2] = x[8];
+  dx[3] = __builtin_fmaf(a * st, ict, P);
+  dx[4] = __builtin_fmaf(Q, cf, -(R * sf));
+  dx[5] = a * ict;
+  const float tm = u[0] * p.inv_m;
+  const float cfst = cf * st;
+  dx[6] = tm * __builtin_fmaf(cfst, cp, sf * sp);
+  dx[7] = tm * __builtin_fmaf(cfst, sp, -(sf * cp));
+  dx[8] = __builtin_fmaf(tm, cf * ct, -p.grav);
+  dx[9] = __builtin_fmaf(p.dIyz * Q, R, u[1]) * p.inv_Ixx;
+  dx[10] = __builtin_fmaf(p.dIzx * P, R, u[2]) * p.inv_Iyy;
+  dx[11] = __builtin_fmaf(p.dIxy * P, Q, u[3]) * p.inv_Izz;
+}
+
+// sin / cos of psi0 + d from those of psi0 (angle addition); d is an RK4
+// stage's yaw increment, so sin d and cos d take the short polynomials
+__device__ __forceinline__ void sincos_shift(float s0, float c0, float d, float* s, float* c) {
+  float sd, cd;
+  sincos_tilt(d, &sd, &cd);
+  *s = __builtin_fmaf(s0, cd, c0 * sd);
+  *c = __builtin_fmaf(c0, cd, -(s0 * sd));
+}
+
 template <int DYN, class PP>
 __device__ __forceinline__ void deriv(const PP& p, const float* x, const float* u, float* dx) {
   if constexpr (DYN == KP_DYN_DI6) deriv_di(p, x, u, dx);
@@ -331,14 +366,47 @@ template <int DYN, int INTEG, class PP>
 __device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u) {
   constexpr int n = Dim<DYN>::n;
   const float h = p.h;
-  float k1[n];
-  deriv<DYN>(p, x, u, k1);
   if constexpr (INTEG == KP_INT_EULER) {
+    float k1[n];
+    deriv<DYN>(p, x, u, k1);
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h, k1[i], x[i]);
+  } else if constexpr (DYN == KP_DYN_QUAD12) {
+    // yaw: one full reduction per step; the stages shift it by their increments
+    const float hh = 0.5f * h;
+    const float h6 = h * (1.0f / 6.0f);
+    float sp0, cp0, sp, cp;
+    sincos_rr(x[5], &sp0, &cp0);
+    float t[n], k[n], acc[n];
+    deriv_quad_y(p, x, u, sp0, cp0, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      acc[i] = k[i];
+      t[i] = __builtin_fmaf(hh, k[i], x[i]);
+    }
+    sincos_shift(sp0, cp0, hh * k[5], &sp, &cp);
+    deriv_quad_y(p, t, u, sp, cp, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
+      t[i] = __builtin_fmaf(hh, k[i], x[i]);
+    }
+    sincos_shift(sp0, cp0, hh * k[5], &sp, &cp);
+    deriv_quad_y(p, t, u, sp, cp, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
+      t[i] = __builtin_fmaf(h, k[i], x[i]);
+    }
+    sincos_shift(sp0, cp0, h * k[5], &sp, &cp);
+    deriv_quad_y(p, t, u, sp, cp, k);
+#pragma unroll
+    for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
   } else {
     const float hh = 0.5f * h;
     const float h6 = h * (1.0f / 6.0f);
+    float k1[n];
+    deriv<DYN>(p, x, u, k1);
     float t[n], k[n], acc[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
