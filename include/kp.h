@@ -254,9 +254,10 @@ kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in);
 kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, int32_t* len);
 
 /* Per-kernel timing with HIP events on the handle's stream (0 = off).  While
- * on, every kernel launch is bracketed by two events; totals accumulate until
+ * on, every launch carries two events stamped with its dispatch's begin and end; totals accumulate until
  * the next call with on = 1.  kp_kernel_times fills, for kernel index k
- * (0 propagate, 1 region estimates, 2 node sets, 3 frontier, 4 V_U commit), the launch
+ * (0 propagate, 1 region estimates, 2 node sets, 3 frontier, 4 V_U commit, 5 the fused
+ * commit + region + node-set pass that kp_plan runs after each propagate), the launch
  * count and the summed duration in milliseconds.  Synchronises. */
 kp_status kp_set_profiling(kp_problem* h, int32_t on);
 kp_status kp_kernel_times(kp_problem* h, int32_t kernel, int64_t* launches, double* total_ms);

@@ -18,7 +18,7 @@ using namespace kp;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kProfKernels = 5;  // propagate, region, node sets, frontier, commit
+constexpr int kProfKernels = 6;  // propagate, region, node sets, frontier, commit, fused post
 constexpr int kEventPool = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -107,7 +107,7 @@ Layout make_layout(const kp_problem_desc* d) {
   L.scell = take(capP * 4);
   L.slane = take(capP * 4);
   L.scount = take(((size_t)d->node_cap / 64 + 2) * 4);  // one count per 64-lane wave tile
-  L.ssum = take((size_t)L.nchunk * 4);
+  L.ssum = take((size_t)L.nchunk * 2 * 4);
   L.total = off;
   return L;
 }
@@ -276,10 +276,11 @@ kp_status sync_ctl(kp_problem* h) {
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
   if (const uint32_t err = h->hctl->err) {
-    char msg[160];
+    char msg[200];
     std::snprintf(msg, sizeof msg,
                   "device check failed (bits 0x%x: 1 frontier look-back wait limit, 2 commit id "
-                  "past |T| + lanes, 4 node-set look-back wait limit)", err);
+                  "past |T| + lanes, 4 node-set look-back wait limit, 8 estimates wait limit)",
+                  err);
     return fail(h, KP_E_DEVICE, msg);
   }
   h->ctl_fresh = true;
@@ -339,7 +340,8 @@ kp_status do_frontier(kp_problem* h, long long n_nodes) {
 // grids from the last host-known sizes (exact after a status read; upper
 // bounds otherwise -- the kernels read the true sizes from device memory)
 // with_region: the commit launch also runs Alg. 3 in one extra block (kp_plan)
-kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_region) {
+// with_commit false: the caller follows with do_post (kp_plan)
+kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_commit) {
   h->ctl_fresh = false;
   long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
   int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
@@ -348,11 +350,25 @@ kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool 
                                   h->desc.n_obstacles, trace, grid, h->stream,
                                   prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
+  if (!with_commit) return KP_OK;
   const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   int cgrid = (int)(ctiles < h->grid_commit_max ? ctiles : h->grid_commit_max);
   if (cgrid < 1) cgrid = 1;
-  e = launch_commit(h->env_dev, trace, cgrid, with_region ? 1 : 0, h->stream, prof_slot(h, 4));
+  e = launch_commit(h->env_dev, trace, cgrid, 0, h->stream, prof_slot(h, 4));
   if (e != hipSuccess) return hip_fail(h, e, "commit launch");
+  return KP_OK;
+}
+
+// k_post after a propagate launch: commit, region and node-set blocks sized
+// from the host's bounds on the expansion and on the old tree
+kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
+  h->ctl_fresh = false;
+  const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
+  const long long ntiles = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
+  const int nc = (int)(ctiles < h->grid_commit_max ? ctiles : h->grid_commit_max);
+  const int nn = (int)(ntiles < h->grid_node_max ? ntiles : h->grid_node_max);
+  hipError_t e = launch_post(h->env_dev, nc, nn, h->stream, prof_slot(h, 5));
+  if (e != hipSuccess) return hip_fail(h, e, "post launch");
   return KP_OK;
 }
 
@@ -537,7 +553,7 @@ kp_status kp_expand(kp_problem* h, void* dev_trace) {
   if (!h) return KP_E_ARG;
   if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_expand must follow kp_update_tree");
   const long long ub = (long long)h->desc.node_cap - h->hctl->N;
-  kp_status st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1, false);
+  kp_status st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1, true);
   if (st != KP_OK) return st;
   h->stage = 1;
   return KP_OK;
@@ -596,9 +612,9 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
     for (long long b = 0; b < batch; ++b) {
       // exact sizes for the first iteration of a batch, bounds after it
       const long long lanes_ub = (b == 0) ? c.lanes : cap - c.N;
-      const long long nodes_ub = (b == 0) ? (long long)c.N + c.lanes : cap;
-      if ((st = do_propagate(h, nullptr, lanes_ub, true)) != KP_OK) return st;
-      if ((st = do_nodesets(h, nodes_ub)) != KP_OK) return st;
+      const long long old_nodes_ub = (b == 0) ? (long long)c.N : cap;
+      if ((st = do_propagate(h, nullptr, lanes_ub, false)) != KP_OK) return st;
+      if ((st = do_post(h, lanes_ub, old_nodes_ub)) != KP_OK) return st;
     }
     if ((st = sync_ctl(h)) != KP_OK) return st;
     prof_collect(h);

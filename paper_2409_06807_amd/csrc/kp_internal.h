@@ -48,8 +48,16 @@ struct alignas(256) Ctl {
   // rewrites N, it, epoch and done while other blocks may still start)
   int32_t sN, snU, sit, sdone;
   uint32_t sepoch;
+  // frontier list: entries e < f_expl are F[e]; entries e >= f_expl are the
+  // ids f_base + (e - f_expl) (the last admission, kept implicit by k_post)
+  int32_t f_expl, f_base;
+  uint32_t region_ready;  // epoch whose thresholds k_post's region block has written
+  uint32_t goal_hit;      // an accepted sample of this query reached X_goal
+  // the iteration as k_propagate found it, read by k_post (whose finaliser
+  // rewrites the fields above while other blocks may still start)
+  int32_t slanes, slam, sfexpl, sfbase;
   TotLine tot[kGroups];  // propagate totals per group; the host adds the groups
-  TkLine tkp[kGroups];   // propagate tile tickets per group; cleared by k_commit
+  TkLine tkp[kGroups];   // propagate tile tickets per group; cleared by k_commit / k_post
 };
 static_assert(sizeof(Ctl) <= 4096, "control block size");
 
@@ -98,7 +106,8 @@ struct Dev {
   uint32_t* scell;     // [capP]
   uint32_t* slane;     // [capP] lane index << 1 | goal bit
   uint32_t* scount;    // [node_cap / 64 + 2] accepted samples per 64-lane wave tile
-  uint32_t* ssum;      // [nchunk] accepted samples per kChunkTiles consecutive wave tiles
+  uint32_t* ssum;      // [2][nchunk] accepted samples per kChunkTiles consecutive wave
+                       // tiles; iteration it uses half it & 1
   int32_t* path;       // [kMaxPath + 1]
   int32_t capP;        // padded node capacity (multiple of kNodeTile)
   int32_t tiles_node;  // entries of st_front / st_nodes
@@ -141,6 +150,7 @@ hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, Trace
 hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
                          hipStream_t s, Timing t);
 hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
+hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s, Timing t);
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);

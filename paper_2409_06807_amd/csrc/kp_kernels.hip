@@ -502,13 +502,15 @@ __global__ void k_zero(const Env* __restrict__ env) {
     d.st_front[t] = 0ull;
     d.st_nodes[t] = 0ull;
   }
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.nchunk; t += stride) d.ssum[t] = 0u;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * d.nchunk; t += stride) d.ssum[t] = 0u;
 }
 
 __device__ void clear_counters(Ctl* c) {
   c->tk_front = c->tk_nodes = 0u;
   c->bd_front = c->bd_nodes = 0u;
   c->err = 0u;
+  c->f_expl = c->f_base = 0;
+  c->goal_hit = 0u;
   for (int g = 0; g < kGroups; ++g) {
     c->tot[g].lanes = c->tot[g].valid = c->tot[g].steps = c->tot[g].box = 0ull;
     c->tkp[g].v = 0u;
@@ -560,7 +562,7 @@ __global__ void k_set_ctl(const Env* __restrict__ env, int32_t N, int32_t it) {
   c->done = 0;
   c->epoch = c->epoch + 1u;
   clear_counters(c);
-  for (int j = 0; j < d.nchunk; ++j) d.ssum[j] = 0u;
+  for (int j = 0; j < 2 * d.nchunk; ++j) d.ssum[j] = 0u;
 }
 
 // flag bytes of the kNodesPerThread nodes a thread holds, as 32-bit words
@@ -607,6 +609,12 @@ __device__ __forceinline__ uint32_t compact_frontier(const Dev& d, unsigned long
   return prefix + agg;
 }
 
+// e-th frontier node: explicit list first, then the implicit tail of ids
+__device__ __forceinline__ int32_t frontier_node(const int32_t* F, int32_t e, int32_t f_expl,
+                                                 int32_t f_base) {
+  return (e < f_expl) ? F[e] : f_base + (e - f_expl);
+}
+
 // last-block finalisation of the frontier: |V_E|, eq. (6), termination codes
 __device__ __forceinline__ void finalize_frontier(const Params& p, Ctl* c, uint32_t nF,
                                                   int32_t N) {
@@ -616,6 +624,8 @@ __device__ __forceinline__ void finalize_frontier(const Params& p, Ctl* c, uint3
     if (lam > p.lambda_max) lam = p.lambda_max;
   }
   c->nF = (int32_t)nF;
+  c->f_expl = (int32_t)nF;
+  c->f_base = 0;
   c->lambda = lam;
   c->lanes = (int32_t)nF * lam;
   if (c->done == 0) {
@@ -705,7 +715,7 @@ __device__ __forceinline__ float box_separation(float lx, float ly, float lz, fl
 }
 
 template <int DYN, int INTEG>
-__global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict__ env,
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(const Env* __restrict__ env,
                                                            TraceRec* trace) {
   const Params& p = env->p;
   const Dev& d = env->d;
@@ -717,6 +727,22 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
   const int32_t lanes = c->lanes;
   const int32_t lam = c->lambda;
   const uint32_t it = (uint32_t)c->it;
+  const int32_t f_expl = c->f_expl, f_base = c->f_base;
+  // the node-set ticket counter, last used by the previous iteration's node
+  // pass, starts from zero for the next one; the iteration's sizes are
+  // copied for k_post
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->tk_nodes = 0u;
+    c->sN = c->N;
+    c->sit = (int32_t)it;
+    c->sdone = done;
+    c->sepoch = c->epoch;
+    c->slanes = lanes;
+    c->slam = lam;
+    c->sfexpl = f_expl;
+    c->sfbase = f_base;
+  }
+  uint32_t* ssum_it = d.ssum + (size_t)(it & 1u) * (size_t)d.nchunk;
   // tiles are single waves: each wave takes 64 lanes at a time from the ticket
   const uint32_t ntiles = done ? 0u : (uint32_t)((lanes + 63) / 64);
   const StepC<DYN> sc = load_step_consts<DYN>(p);
@@ -770,7 +796,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
     if (active) {
       e = g / lam;
       s = g - e * lam;
-      f = d.F[e];
+      f = frontier_node(d.F, e, f_expl, f_base);
 #pragma unroll
       for (int k = 0; k < n; ++k) x[k] = d.x[(size_t)k * d.capP + f];
       const U4 w = philox(it, (uint32_t)f, (uint32_t)s, 0u, p.key0, p.key1);
@@ -931,6 +957,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
         accept = unvisited || ((unsigned long long)w_acc < d.thr[r]);
         const float dx = x[0] - p.goal_c[0], dy = x[1] - p.goal_c[1], dz = x[2] - p.goal_c[2];
         goal = accept && (dx * dx + dy * dy + dz * dz <= p.goal_r2);
+        if (goal) c->goal_hit = 1u;
       }
     }
     // n_valid / n_invalid: one atomic per distinct (region, validity) in the wave
@@ -966,7 +993,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
     if (__lane_id() == 0) {
       const uint32_t na = (uint32_t)__popcll(ab);
       d.scount[tile] = na;
-      if (na) atomicAdd(&d.ssum[tile / kChunkTiles], na);
+      if (na) atomicAdd(&ssum_it[tile / kChunkTiles], na);
     }
     const int32_t id = -1;  // assigned by k_commit
     if (trace != nullptr && active) {
@@ -1020,6 +1047,69 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(const Env* __restrict_
 // ---------------------------------------------------------------------------
 // k_commit: ids of the accepted samples (V_U of Alg. 2), stable in lane order
 // ---------------------------------------------------------------------------
+// The V_U scatter of wave tiles first_wt, first_wt + stride, ...: each
+// staged sample gets id |T| + (accepted samples of all earlier tiles) +
+// (rank inside its tile) and its tree entries.
+struct CommitCtx {
+  int32_t N, lanes, lam, f_expl, f_base;
+  uint32_t it, nwt;
+};
+__device__ __forceinline__ void commit_tiles(const Params& p, const Dev& d, Ctl* c,
+                                             const CommitCtx& k, uint32_t first_wt,
+                                             uint32_t stride, TraceRec* trace) {
+  const uint32_t lane = __lane_id();
+  for (uint32_t wt = first_wt; wt < k.nwt; wt += stride) {
+    const uint32_t cnt = d.scount[wt];
+    if (cnt == 0u) continue;
+    // The staged record and the parent id do not depend on the tile's
+    // offset: their loads go out together with the offset's.
+    const bool mine = lane < cnt;
+    const size_t slot = (size_t)wt * 64u + lane;
+    uint32_t sl = 0, scl = 0;
+    int32_t par = 0;
+    float xs[12], us[4];
+    if (mine) {
+      sl = d.slane[slot];
+      scl = d.scell[slot];
+#pragma unroll
+      for (int q = 0; q < 12; ++q)
+        if (q < p.n) xs[q] = d.sx[(size_t)q * d.capP + slot];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < p.m) us[q] = d.su[(size_t)q * d.capP + slot];
+      par = frontier_node(d.F, (int32_t)(sl >> 1) / k.lam, k.f_expl, k.f_base);
+    }
+    const uint32_t ch = wt / kChunkTiles;
+    unsigned long long part = 0;
+    const uint32_t* ssum = d.ssum + (size_t)(k.it & 1u) * (size_t)d.nchunk;
+    for (uint32_t j = lane; j < ch; j += 64u) part += ssum[j];
+    for (uint32_t j = ch * kChunkTiles + lane; j < wt; j += 64u) part += d.scount[j];
+    const uint32_t pre = (uint32_t)wave_sum_u64(part);
+    if (mine) {
+      const int32_t id = k.N + (int32_t)(pre + lane);
+      if (id >= k.N + k.lanes) {  // cannot happen with consistent counts; never write past it
+        atomicOr(&c->err, 2u);
+      } else {
+        const int32_t g = (int32_t)(sl >> 1);
+        const int32_t s = g - (g / k.lam) * k.lam;
+#pragma unroll
+        for (int q = 0; q < 12; ++q)
+          if (q < p.n) d.x[(size_t)q * d.capP + id] = xs[q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < p.m) d.u[(size_t)q * d.capP + id] = us[q];
+        d.parent[id] = par;
+        d.cell[id] = scl;
+        d.flag[id] = 1;
+        d.birth[id] = (int32_t)k.it;
+        d.sample[id] = (uint8_t)s;
+        if (sl & 1u) atomicMin(&c->goal_id, id);
+        if (trace != nullptr) trace[g].new_id = id;
+      }
+    }
+  }
+}
+
 // Each wave takes 64-lane propagate tiles, grid-stride over the waves of the
 // commit blocks.  Its staged samples take ids |T| + (accepted samples of all
 // earlier tiles) + (rank inside the tile).  The earlier-tile count is the
@@ -1054,7 +1144,8 @@ __global__ __launch_bounds__(kCommitBlock) void k_commit(const Env* __restrict__
   if (blockIdx.x == 0 && wave == 0) {
     const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
     unsigned long long part = 0;
-    for (uint32_t j = lane; j < nch; j += 64u) part += d.ssum[j];
+    const uint32_t* ssum = d.ssum + (size_t)(it & 1u) * (size_t)d.nchunk;
+    for (uint32_t j = lane; j < nch; j += 64u) part += ssum[j];
     part = wave_sum_u64(part);
     if (lane == 0) {
       if (!done) c->nU = (int32_t)part;
@@ -1068,55 +1159,15 @@ __global__ __launch_bounds__(kCommitBlock) void k_commit(const Env* __restrict__
     if (lane < (uint32_t)kGroups) c->tkp[lane].v = 0u;
   }
   constexpr uint32_t wpb = kCommitBlock / 64;
-  for (uint32_t wt = blockIdx.x * wpb + wave; wt < nwt; wt += nblk * wpb) {
-    const uint32_t cnt = d.scount[wt];
-    if (cnt == 0u) continue;
-    // The staged record and the parent id do not depend on the tile's
-    // offset: their loads go out together with the offset's.
-    const bool mine = lane < cnt;
-    const size_t slot = (size_t)wt * 64u + lane;
-    uint32_t sl = 0, scl = 0;
-    int32_t par = 0;
-    float xs[12], us[4];
-    if (mine) {
-      sl = d.slane[slot];
-      scl = d.scell[slot];
-#pragma unroll
-      for (int q = 0; q < 12; ++q)
-        if (q < p.n) xs[q] = d.sx[(size_t)q * d.capP + slot];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q < p.m) us[q] = d.su[(size_t)q * d.capP + slot];
-      par = d.F[(int32_t)(sl >> 1) / lam];
-    }
-    const uint32_t ch = wt / kChunkTiles;
-    unsigned long long part = 0;
-    for (uint32_t j = lane; j < ch; j += 64u) part += d.ssum[j];
-    for (uint32_t j = ch * kChunkTiles + lane; j < wt; j += 64u) part += d.scount[j];
-    const uint32_t pre = (uint32_t)wave_sum_u64(part);
-    if (mine) {
-      const int32_t id = N + (int32_t)(pre + lane);
-      if (id >= N + lanes) {  // cannot happen with consistent counts; never write past it
-        atomicOr(&c->err, 2u);
-      } else {
-        const int32_t g = (int32_t)(sl >> 1);
-        const int32_t s = g - (g / lam) * lam;
-#pragma unroll
-        for (int q = 0; q < 12; ++q)
-          if (q < p.n) d.x[(size_t)q * d.capP + id] = xs[q];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q < p.m) d.u[(size_t)q * d.capP + id] = us[q];
-        d.parent[id] = par;
-        d.cell[id] = scl;
-        d.flag[id] = 1;
-        d.birth[id] = (int32_t)it;
-        d.sample[id] = (uint8_t)s;
-        if (sl & 1u) atomicMin(&c->goal_id, id);
-        if (trace != nullptr) trace[g].new_id = id;
-      }
-    }
-  }
+  CommitCtx k;
+  k.N = N;
+  k.lanes = lanes;
+  k.lam = lam;
+  k.f_expl = c->f_expl;
+  k.f_base = c->f_base;
+  k.it = it;
+  k.nwt = nwt;
+  commit_tiles(p, d, c, k, blockIdx.x * wpb + wave, nblk * wpb, trace);
 }
 
 // ---------------------------------------------------------------------------
@@ -1233,7 +1284,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
   const uint32_t ntiles = done ? 0u : (uint32_t)((Nt + kNodeTile - 1) / kNodeTile);
   // accepted-sample chunk totals of this iteration's expansion: used up
   if (blockIdx.x == 0)
-    for (int j = threadIdx.x; j < d.nchunk; j += kNodeBlock) d.ssum[j] = 0u;
+    for (int j = threadIdx.x; j < 2 * d.nchunk; j += kNodeBlock) d.ssum[j] = 0u;
   // With a tile for every block, tile = block index: blocks start in index
   // order, so a tile's look-back only waits on blocks that started earlier.
   // With more tiles than blocks, every tile comes from the ticket counter
@@ -1328,6 +1379,213 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// k_post: the rest of a kp_plan iteration after k_propagate, in one launch
+// ---------------------------------------------------------------------------
+//   block 0            UpdateEstimates (Alg. 3), then publishes region_ready
+//   blocks 1 .. nc     V_U: ids and tree entries (commit_tiles); once the
+//                      thresholds are out, the new nodes' visited bits and
+//                      R_avail (Alg. 4: V_U joins T)
+//   blocks nc+1 ..     UpdateNodeSets (Alg. 4) over the old nodes [0, N):
+//                      demote / promote once the thresholds are out, and
+//                      the compaction of their E flags into F
+//   last old tile      its block, once its look-back has the count of old E
+//                      nodes: |T| += |V_U|; the frontier is the old E nodes
+//                      (F) followed by the new ids N .. N + |V_U| - 1 (all
+//                      E, kept implicit); eq. (6); next iteration
+// Blocks wait only on block 0, which starts first and waits on nothing, and
+// on look-backs ordered as in k_nodesets.  Every block reads the sizes from
+// the copy k_propagate made, so the finaliser may run while late blocks
+// start.  Same results as k_commit, k_region and k_nodesets in sequence.
+// Thread 0 polls with relaxed device-scope loads.  No acquire fence follows
+// (on this GPU it would invalidate the cache of every wave of every waiting
+// block): the thresholds are then read with device-scope atomic loads, which
+// see the region block's writes once it has published the flag after its
+// own device-scope fence.
+__device__ __forceinline__ void wait_region(Ctl* c, uint32_t epoch) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&c->region_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+           epoch) {
+      if (++spins > (1u << 22)) {
+        atomicOr(&c->err, 8u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
+  static_assert(kCommitBlock == kNodeBlock, "one block shape for every role");
+  static_assert(kNodesPerThread == 4, "one flag word and one uint4 of cells per thread");
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  Ctl* c = d.ctl;
+  // sizes from k_propagate's copy: the finaliser below rewrites the live ones
+  const int done = c->sdone;
+  const int32_t N = c->sN;
+  const int32_t lanes = c->slanes;
+  const int32_t lam = c->slam;
+  const uint32_t it = (uint32_t)c->sit;
+  const uint32_t epoch = c->sepoch;
+  const uint32_t nwt = done ? 0u : (uint32_t)((lanes + 63) / 64);
+  const uint32_t* ssum = d.ssum + (size_t)(it & 1u) * (size_t)d.nchunk;
+  const uint32_t lane = __lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+  constexpr uint32_t wpb = kCommitBlock / 64;
+  __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
+
+  if (blockIdx.x == 0) {
+    // ---- UpdateEstimates; and the counters of the next expansion ----
+    uint32_t* nxt = d.ssum + (size_t)((it + 1u) & 1u) * (size_t)d.nchunk;
+    for (int j = threadIdx.x; j < d.nchunk; j += kCommitBlock) nxt[j] = 0u;
+    if (threadIdx.x < (unsigned)kGroups) c->tkp[threadIdx.x].v = 0u;
+    if (!done) region_body<kCommitBlock>(env);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_store(&c->region_ready, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  if (blockIdx.x <= (uint32_t)nc) {
+    // ---- V_U ----
+    CommitCtx k;
+    k.N = N;
+    k.lanes = lanes;
+    k.lam = lam;
+    k.f_expl = c->sfexpl;
+    k.f_base = c->sfbase;
+    k.it = it;
+    k.nwt = nwt;
+    const uint32_t first = (blockIdx.x - 1u) * wpb + wave, stride = (uint32_t)nc * wpb;
+    commit_tiles(p, d, c, k, first, stride, nullptr);
+    // visited bits of the block's samples, once the estimates have read the
+    // old ones: one atomic per distinct region among a tile's samples.  A
+    // block with no accepted sample does not wait.
+    bool any = false;
+    for (uint32_t wt = (blockIdx.x - 1u) * wpb; wt < nwt && !any; wt += stride)
+      for (uint32_t w = 0; w < wpb && wt + w < nwt; ++w) any |= d.scount[wt + w] != 0u;
+    if (!any) return;
+    wait_region(c, epoch);
+    for (uint32_t wt = first; wt < nwt; wt += stride) {
+      const uint32_t cnt = d.scount[wt];
+      if (cnt == 0u) continue;
+      const uint32_t cl = (lane < cnt) ? d.scell[(size_t)wt * 64u + lane] : 0u;
+      const uint32_t key = (lane < cnt) ? (cl >> 6) : 0xffffffffu;
+      unsigned long long pending = __ballot(lane < cnt);
+      while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const uint32_t r0 = (uint32_t)__shfl((int)key, leader);
+        const unsigned long long match = __ballot(key == r0);
+        unsigned long long bits = (key == r0) ? (1ull << (cl & 63u)) : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
+        if ((int)lane == leader) {
+          atomicOr(&d.visited[r0], bits);
+          d.avail[r0] = 1;
+        }
+        pending &= ~match;
+      }
+    }
+    return;
+  }
+  // ---- UpdateNodeSets over the old nodes ----
+  const uint32_t nb = gridDim.x - 1u - (uint32_t)nc;
+  const uint32_t bi = blockIdx.x - 1u - (uint32_t)nc;
+  const bool goal = c->goal_hit != 0u;
+  const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
+  const bool by_ticket = ntiles > nb;
+  uint32_t tile = bi;
+  if (by_ticket) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
+    __syncthreads();
+    tile = s_tile;
+    __syncthreads();
+  }
+  bool waited = false;
+  for (;;) {
+    if (tile >= ntiles) break;
+    const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
+    const bool in = base < (uint32_t)N;
+    uint32_t fw[kFlagWords] = {};
+    uint32_t cells[4] = {0u, 0u, 0u, 0u};
+    uint32_t wd[4] = {0u, 0u, 0u, 0u}, wp[4] = {0u, 0u, 0u, 0u};
+    if (in) {
+      load_flag_words(d.flag + base, fw);
+      const uint4 cw = *reinterpret_cast<const uint4*>(d.cell + base);
+      cells[0] = cw.x;
+      cells[1] = cw.y;
+      cells[2] = cw.z;
+      cells[3] = cw.w;
+      // node pair (2k, 2k+1) shares Philox block (it, k, 0, 3)
+      const U4 wa = philox(it, base >> 1, 0u, 3u, p.key0, p.key1);
+      const U4 wb = philox(it, (base >> 1) + 1u, 0u, 3u, p.key0, p.key1);
+      wd[0] = wa.w[0];
+      wd[1] = wa.w[2];
+      wd[2] = wb.w[0];
+      wd[3] = wb.w[2];
+      wp[0] = wa.w[1];
+      wp[1] = wa.w[3];
+      wp[2] = wb.w[1];
+      wp[3] = wb.w[3];
+    }
+    if (!waited) {
+      wait_region(c, epoch);
+      waited = true;
+    }
+    uint32_t eb = 0;
+    if (in) {
+      uint32_t nfw = fw[0];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = base + k;
+        if (i >= (uint32_t)N) continue;
+        const unsigned long long t = __hip_atomic_load(&d.thr[cells[k] >> 6], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        const bool wasE = ((fw[0] >> (8 * k)) & 0xffu) != 0u;
+        const bool stay = wasE && ((unsigned long long)wd[k] < t);          // V_E -> V_O w.p. 1-P
+        const bool E = stay || (!goal && ((unsigned long long)wp[k] < t));  // V_O -> V_E w.p. P
+        nfw = (nfw & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
+        if (E) eb |= 1u << k;
+      }
+      if (nfw != fw[0]) {
+        if (base + 4u <= (uint32_t)N) {
+          store_flag_words(d.flag + base, &nfw);
+        } else {
+          // the word reaches into V_U, whose flags the commit blocks write
+          for (uint32_t k = 0; base + k < (uint32_t)N; ++k)
+            d.flag[base + k] = (uint8_t)((nfw >> (8 * k)) & 0xffu);
+        }
+      }
+    }
+    const uint32_t upto = compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
+    if (tile == ntiles - 1u && threadIdx.x == 0) {
+      // every old tile has published its count; |V_U| from the chunk totals
+      const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
+      uint32_t nU = 0;
+      for (uint32_t j = 0; j < nch; ++j) nU += ssum[j];
+      const int32_t Nt = N + (int32_t)nU;
+      c->nU = (int32_t)nU;
+      c->N = Nt;
+      if (goal) c->done = KP_SOLVED;
+      finalize_frontier(p, c, upto + nU, Nt);
+      c->f_expl = (int32_t)upto;
+      c->f_base = N;
+      c->it = (int32_t)it + 1;
+      c->epoch = epoch + 1u;
+      c->iters_done += 1u;
+    }
+    if (!by_ticket) break;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
+    __syncthreads();
+    tile = s_tile;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_path: root-to-node walk along parent links
 // ---------------------------------------------------------------------------
 __global__ void k_path(const Env* __restrict__ env, int32_t node) {
@@ -1395,6 +1653,14 @@ hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_reg
   if (with_region) grid += 1;  // the extra, last block runs the region pass
   hipExtLaunchKernelGGL(k_commit, dim3(grid), dim3(kCommitBlock), 0, s, t.start, t.stop, 0, env,
                         trace, with_region);
+  return hipGetLastError();
+}
+
+hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s, Timing t) {
+  if (n_commit < 1) n_commit = 1;
+  if (n_nodes < 1) n_nodes = 1;
+  hipExtLaunchKernelGGL(k_post, dim3(1 + n_commit + n_nodes), dim3(kCommitBlock), 0, s, t.start,
+                        t.stop, 0, env, n_commit);
   return hipGetLastError();
 }
 

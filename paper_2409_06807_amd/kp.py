@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libkinopax.so")
 KP_ABI_VERSION = 1
 OK, SOLVED, TIMEOUT, TREE_FULL, FRONTIER_EMPTY = 0, 1, 2, 3, 4
 E_ARG, E_DEVICE, E_WORKSPACE, E_START_INVALID, E_GOAL_INVALID, E_ORDER = -1, -2, -3, -4, -5, -6
-KERNELS = {"propagate": 0, "region": 1, "nodesets": 2, "frontier": 3, "commit": 4}
+KERNELS = {"propagate": 0, "region": 1, "nodesets": 2, "frontier": 3, "commit": 4, "post": 5}
 
 EXPORTED = [
     "kp_workspace_bytes", "kp_trace_bytes", "kp_create_problem", "kp_destroy_problem",

@@ -277,3 +277,46 @@ def test_c2_solution_replays_in_fp64(seed):
     print(f"c2 seed {seed}: path of {len(path)} nodes, worst edge rel err {worst:.2e}")
     G.close()
 
+
+
+def _step_path_tree(p, iters):
+    G = planner(p)
+    done = 0
+    for _ in range(iters):
+        if G.stats()["done_code"]:
+            break
+        G.expand()
+        G.update_regions()
+        G.update_tree()
+        done += 1
+    g, st = G.copy_tree(), G.stats()
+    G.close()
+    return g, st, done
+
+
+@pytest.mark.parametrize("case", ["small-quad", "small-di", "c2", "c5"])
+def test_plan_equals_step_path(case):
+    # kp_plan runs one fused pass (commit + estimates + node sets) after each
+    # propagate; the step entry points run the three kernels the parity tests
+    # check against the oracle.  Both must grow the identical tree.
+    p = {"small-quad": lambda: problem_small_quad(seed=3, cap=8192, n_obs=60),
+         "small-di": lambda: problem_small_di(seed=5, cap=4096, n_obs=12),
+         "c2": lambda: problem_c2(seed=3),
+         "c5": lambda: problem_c5(seed=2)}[case]()
+    iters = {"small-quad": 8, "small-di": 14, "c2": 12, "c5": 9}[case]
+    _say(f"plan vs step path {case}, {iters} iterations")
+    ref, ref_st, n_done = _step_path_tree(p, iters)
+    q = dict(p)
+    q["max_iters"] = n_done
+    G = planner(q)
+    r = G.plan()
+    g, st = G.copy_tree(), G.stats()
+    G.close()
+    assert st["device_error"] == 0 and ref_st["device_error"] == 0
+    assert r["iterations"] == n_done
+    for k in ("n_nodes", "n_frontier", "lam", "iteration", "done_code", "goal_id"):
+        assert st[k] == ref_st[k], (k, st[k], ref_st[k])
+    for k in ("parent", "cell", "flag", "birth", "sample", "nv", "ni", "visited", "avail", "thr"):
+        assert np.array_equal(g[k], ref[k]), k
+    assert np.array_equal(g["x"].view(np.uint32), ref["x"].view(np.uint32))
+    assert np.array_equal(g["u"].view(np.uint32), ref["u"].view(np.uint32))
