@@ -495,6 +495,13 @@ int64_t kpo_num_lanes(const kpo_planner* P) { return (int64_t)P->nF * P->lambda;
  * the end of the segment, or the state at the first step that fails.
  * A non-finite x' is mapped to its parent's cell. */
 void kpo_expand_one(const kpo_planner* P, int32_t f, int32_t s, kpo_record* rec, double* traj_out) {
+  kpo_expand_one_u(P, f, s, NULL, rec, traj_out);
+}
+
+/* The same expansion with the control given by the caller (u_given: m FP32
+ * values; NULL draws it as above).  The acceptance word is drawn as above. */
+void kpo_expand_one_u(const kpo_planner* P, int32_t f, int32_t s, const float* u_given,
+                      kpo_record* rec, double* traj_out) {
   const kpo_problem* pb = &P->pb;
   const int n = P->n, m = P->m, K = P->K;
   double trajbuf[12 * 65];
@@ -508,6 +515,8 @@ void kpo_expand_one(const kpo_planner* P, int32_t f, int32_t s, kpo_record* rec,
   rec->parent = f;
   rec->sample = s;
   draw_expansion(pb, m, (uint32_t)P->it, (uint32_t)f, (uint32_t)s, rec->u, &rec->w_acc);
+  if (u_given)
+    for (int j = 0; j < m; ++j) rec->u[j] = u_given[j];
   double u[4] = {0, 0, 0, 0};
   for (int j = 0; j < m; ++j) u[j] = (double)rec->u[j];
   memcpy(traj, P->x + (size_t)f * n, sizeof(double) * n);
@@ -537,6 +546,15 @@ int64_t kpo_expand_all(const kpo_planner* P, kpo_record* recs) {
   int64_t k = 0;
   for (int32_t e = 0; e < P->nF; ++e)
     for (int32_t s = 0; s < P->lambda; ++s) kpo_expand_one(P, P->F[e], s, &recs[k++], NULL);
+  return k;
+}
+
+/* All lanes with given controls: U holds 4 floats per lane, lane order. */
+int64_t kpo_expand_all_u(const kpo_planner* P, const float* U, kpo_record* recs) {
+  int64_t k = 0;
+  for (int32_t e = 0; e < P->nF; ++e)
+    for (int32_t s = 0; s < P->lambda; ++s, ++k)
+      kpo_expand_one_u(P, P->F[e], s, U + 4 * k, &recs[k], NULL);
   return k;
 }
 

@@ -94,6 +94,9 @@ int32_t kpo_frontier(kpo_planner* P);                          /* eq. 6 + fronti
 int64_t kpo_num_lanes(const kpo_planner* P);                   /* |V_E| * lambda */
 void kpo_expand_one(const kpo_planner* P, int32_t f, int32_t s, kpo_record* rec, double* traj);
 int64_t kpo_expand_all(const kpo_planner* P, kpo_record* recs); /* Alg. 2, per-lane part */
+void kpo_expand_one_u(const kpo_planner* P, int32_t f, int32_t s, const float* u_given,
+                      kpo_record* rec, double* traj);               /* given control */
+int64_t kpo_expand_all_u(const kpo_planner* P, const float* U, kpo_record* recs);
 void kpo_apply(kpo_planner* P, const kpo_record* recs, int64_t n); /* Alg. 2 bookkeeping */
 void kpo_update_estimates(kpo_planner* P);                     /* Alg. 3 */
 int32_t kpo_update_node_sets(kpo_planner* P);                  /* Alg. 4; goal id or -1 */

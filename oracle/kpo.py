@@ -102,6 +102,9 @@ def lib():
         L.kpo_expand_one.argtypes = [P, C.c_int32, C.c_int32, vp, vp]
         L.kpo_expand_all.argtypes = [P, vp]
         L.kpo_expand_all.restype = C.c_int64
+        L.kpo_expand_one_u.argtypes = [P, C.c_int32, C.c_int32, vp, vp, vp]
+        L.kpo_expand_all_u.argtypes = [P, vp, vp]
+        L.kpo_expand_all_u.restype = C.c_int64
         L.kpo_apply.argtypes = [P, vp, C.c_int64]
         L.kpo_update_estimates.argtypes = [P]
         L.kpo_update_node_sets.argtypes = [P]
@@ -334,18 +337,29 @@ class OraclePlanner:
     def num_lanes(self) -> int:
         return lib().kpo_num_lanes(self.h)
 
-    def expand_all(self):
+    def expand_all(self, controls=None):
+        """Every lane of Alg. 2; controls (lanes x 4 FP32) replaces the
+        uniform draws when given."""
         n = self.num_lanes()
         recs = np.zeros(max(n, 1), RECORD_DTYPE)
-        lib().kpo_expand_all(self.h, _ptr(recs))
+        if controls is None:
+            lib().kpo_expand_all(self.h, _ptr(recs))
+        else:
+            U = np.zeros((max(n, 1), 4), np.float32)
+            U[:n] = np.asarray(controls, np.float32)[:n, :4] if n else U[:0]
+            lib().kpo_expand_all_u(self.h, _ptr(U), _ptr(recs))
         return recs[:n]
 
-    def expand_one(self, f, s, want_traj=False):
+    def expand_one(self, f, s, want_traj=False, control=None):
         rec = np.zeros(1, RECORD_DTYPE)
         K = int(self.problem["steps"])
         traj = np.zeros((K + 1, self.n)) if want_traj else None
-        lib().kpo_expand_one(self.h, int(f), int(s), _ptr(rec),
-                             _ptr(traj) if traj is not None else None)
+        u = None
+        if control is not None:
+            u = np.zeros(4, np.float32)
+            u[:self.m] = np.asarray(control, np.float32)[:self.m]
+        lib().kpo_expand_one_u(self.h, int(f), int(s), _ptr(u) if u is not None else None,
+                               _ptr(rec), _ptr(traj) if traj is not None else None)
         return (rec[0], traj) if want_traj else rec[0]
 
     def apply(self, recs):
