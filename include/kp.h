@@ -257,13 +257,112 @@ kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, in
  * on, every launch carries two events stamped with its dispatch's begin and end; totals accumulate until
  * the next call with on = 1.  kp_kernel_times fills, for kernel index k
  * (0 propagate, 1 region estimates, 2 node sets, 3 frontier, 4 V_U commit, 5 the fused
- * commit + region + node-set pass that kp_plan runs after each propagate), the launch
+ * commit + region + node-set pass that kp_plan runs after each propagate, 6 the learned
+ * proposal's network over the frontier), the launch
  * count and the summed duration in milliseconds.  Synchronises. */
 kp_status kp_set_profiling(kp_problem* h, int32_t on);
 kp_status kp_kernel_times(kp_problem* h, int32_t kernel, int64_t* launches, double* total_ms);
 
 const char* kp_status_str(kp_status s);
 const char* kp_last_error(const kp_problem* h);
+
+/* ---------------------------------------------------------------------------
+ * Learned control proposal
+ *
+ * Alg. 2 draws every control uniformly from U.  With a proposal set on a
+ * handle, expansion (iteration it, parent f, sample s) draws instead from a
+ * Gaussian that a small network predicts for f, with probability mix, and
+ * keeps the uniform draw otherwise.  The uniform share keeps a positive
+ * density on all of U, which the completeness argument of Sec. V (Theorem 1)
+ * relies on.
+ *
+ * Network: 16 inputs -> 128 -> 128 -> 8 outputs, relu after the two hidden
+ * layers.  Parameters: one FP32 vector of KP_MLP_PARAMS floats, W1 [128][16],
+ * b1 [128], W2 [128][128], b2 [128], W3 [8][128], b3 [8] (row-major, output
+ * index first).  Every product takes BF16 operands (round to nearest even of
+ * the FP32 weight or activation) and accumulates in FP32.
+ *
+ * Inputs of node x in region R: (raw_k - c_k) * s_k, raw = (x_0 .. x_{n-1},
+ * P_accept(R) of eq. 5, goal_center - x_{0..2}, zeros).  c and s map the state
+ * box to [-1, 1] and P_accept from [0, 1] to [-1, 1]; the goal offset is scaled
+ * by 2 / (x_hi - x_lo) of the workspace; unused inputs are zero.
+ *
+ * Head, control j < m (c_j, r_j: centre and half-width of U):
+ *   mean_j = c_j + r_j tanh(o_j),   std_j = r_j exp(clip(o_{4+j}, -4, 0)).
+ * Draw: learned iff word 0 of Philox(it, f, s, 4) < floor(mix * 2^32); then
+ * z_0, z_1 and z_2, z_3 are the Box-Muller transforms of words (0, 1) and
+ * (2, 3) of Philox(it, f, s, 5), with u1 = ((a >> 8) + 1) 2^-24 and
+ * u2 = (b >> 8) 2^-24; u_j = clip(mean_j + std_j z_j, u_lo_j, u_hi_j).
+ *
+ * Training objective: mean over a minibatch of
+ *   sum_{j<m} [ (t_j - tanh o_j)^2 exp(-2 ls_j) / 2 + ls_j ],
+ * ls_j = clip(o_{4+j}, -4, 0), t_j = (u_j - c_j) / r_j the logged control in
+ * normalised units (the Gaussian negative log-likelihood up to constants).
+ *
+ * The functions without a handle return KP_E_ARG for bad arguments and
+ * KP_E_DEVICE when a launch fails; they only enqueue on hip_stream.
+ * ---------------------------------------------------------------------------*/
+#define KP_MLP_INPUTS 16
+#define KP_MLP_HIDDEN 128
+#define KP_MLP_OUTPUTS 8
+#define KP_MLP_PARAMS 19720
+#define KP_MLP_PACKED_BYTES 87072   /* BF16 operand tiles + FP32 biases */
+#define KP_MLP_BLOCK_ROWS 64        /* minibatch rows per partial gradient */
+
+/* Convert FP32 parameters (device, KP_MLP_PARAMS floats) to the device layout
+ * the kernels read (dev_packed: KP_MLP_PACKED_BYTES bytes, 16-byte aligned,
+ * caller-owned).  Run again after every parameter change. */
+kp_status kp_mlp_pack(const float* dev_params, void* dev_packed, void* hip_stream);
+
+/* Raw outputs o (rows x 8 floats, device) of rows x 16 input features (device,
+ * 16-byte aligned rows).  rows = 0 is a no-op. */
+kp_status kp_mlp_forward(const void* dev_packed, const float* dev_x, int32_t rows, float* dev_out,
+                         void* hip_stream);
+
+/* Gradient of the training objective over one minibatch of `batch` rows
+ * drawn from n_rows rows of features dev_x (n_rows x 16) and targets dev_t
+ * (n_rows x 4; entries j >= n_ctrl ignored).  sample_key = 0: the minibatch is
+ * rows 0 .. batch-1 (batch <= n_rows); otherwise row k of the minibatch is
+ * (word 0 of Philox(step, k, 0, 6) with key sample_key) * n_rows >> 32.
+ * Writes ceil(batch / KP_MLP_BLOCK_ROWS) partial gradients (KP_MLP_PARAMS
+ * floats each, in parameter order; they sum to the gradient) to dev_partials
+ * and as many partial losses (summing to the objective) to dev_loss. */
+kp_status kp_mlp_grad(const void* dev_packed, const float* dev_x, const float* dev_t, int32_t n_rows,
+                      int32_t n_ctrl, int32_t batch, uint64_t sample_key, int32_t step,
+                      float* dev_partials, float* dev_loss, void* hip_stream);
+
+/* Adam step `step` (1-based, bias-corrected; Kingma & Ba, 2015) on dev_params
+ * with moments dev_m1, dev_m2 (KP_MLP_PARAMS floats each, zero before step 1),
+ * the gradient being the sum of n_partials partial gradients (in order). */
+kp_status kp_mlp_adam(float* dev_params, float* dev_m1, float* dev_m2, const float* dev_partials,
+                      int32_t n_partials, int32_t step, float lr, float beta1, float beta2,
+                      float eps, void* hip_stream);
+
+/* `steps` rounds of kp_mlp_pack, kp_mlp_grad (random minibatches, steps
+ * step0 .. step0+steps-1) and kp_mlp_adam (steps step0+1 ..).  dev_loss
+ * receives steps x ceil(batch / KP_MLP_BLOCK_ROWS) partial losses; on return
+ * dev_packed holds the updated parameters. */
+kp_status kp_mlp_train(float* dev_params, float* dev_m1, float* dev_m2, void* dev_packed,
+                       const float* dev_x, const float* dev_t, int32_t n_rows, int32_t n_ctrl,
+                       int32_t batch, int32_t steps, int32_t step0, float lr, uint64_t sample_key,
+                       float* dev_partials, float* dev_loss, void* hip_stream);
+
+/* Use the packed network dev_packed for the handle's expansions from the next
+ * kp_expand / kp_plan on, mixed with the uniform draw at rate mix in [0, 1]
+ * (dev_packed = NULL or mix = 0: uniform only).  dev_head: device scratch of
+ * head_rows x 8 floats, head_rows >= node_cap.  Both buffers are borrowed
+ * until the proposal is replaced.  KP_E_ORDER in the middle of an iteration.
+ * Synchronises. */
+kp_status kp_set_proposal(kp_problem* h, const void* dev_packed, float* dev_head, int64_t head_rows,
+                          float mix);
+
+/* Training rows from the tree path root -> node: row row0 + k holds the input
+ * features of the parent of edge k (dev_x, 16 floats per row) and the edge's
+ * control in normalised units (dev_t, 4 floats per row, zero past m), for
+ * edges that fit below cap_rows.  *n_rows receives the rows written.
+ * Synchronises. */
+kp_status kp_log_path(kp_problem* h, int32_t node, float* dev_x, float* dev_t, int32_t cap_rows,
+                      int32_t row0, int32_t* n_rows);
 
 #ifdef __cplusplus
 }

@@ -187,6 +187,18 @@ def loss_grad(params, X, T, m, quant=True):
     return L, pack(gW1, gb1, gW2, gb2, gW3, gb3)
 
 
+def abs_scale(params, X):
+    """The network's outputs evaluated with |.| on every weight, bias and
+    input and relu dropped: a bound on how far any one rounding of an input
+    or activation to a neighbouring BF16 value can move each output (times
+    the relative size of that rounding, 2^-8)."""
+    W1, b1, W2, b2, W3, b3 = unpack(params)
+    x = np.abs(bf16(np.atleast_2d(np.asarray(X, np.float64))))
+    a1 = x @ np.abs(bf16(W1)).T + np.abs(b1)
+    a2 = a1 @ np.abs(bf16(W2)).T + np.abs(b2)
+    return a2 @ np.abs(bf16(W3)).T + np.abs(b3)
+
+
 def loss_grad_abs(params, X, T, m):
     """The gradient's terms summed in absolute value (same contractions with
     |.| on every factor): a scale for the rounding error of any evaluation."""
@@ -234,17 +246,37 @@ def mix_threshold(mix):
     return min(int(math.floor(float(np.float32(mix)) * 2.0 ** 32)), 2 ** 32)
 
 
+def _key(seed):
+    return (int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF)
+
+
+def is_learned(seed, it, f, s, mix_thr):
+    """Mixture choice of expansion (it, f, s): an exact integer comparison."""
+    return int(philox4x32_10((it, f, s, TAG_MIX), _key(seed))[0]) < mix_thr
+
+
+def gaussians(seed, it, f, s):
+    """The four standard normal draws of expansion (it, f, s)."""
+    g = philox4x32_10((it, f, s, TAG_GAUSS), _key(seed))
+    z0, z1 = box_muller(g[0], g[1])
+    z2, z3 = box_muller(g[2], g[3])
+    return np.array([z0, z1, z2, z3])
+
+
+def uniform_control(seed, it, f, s, p, m):
+    """Alg. 2's uniform control of expansion (it, f, s) (FP32 values)."""
+    from .kpo import control_map
+    w = philox4x32_10((it, f, s, 0), _key(seed))
+    return np.array([control_map(w[j], np.float32(p["u_lo"][j]), np.float32(p["u_hi"][j]))
+                     for j in range(m)], np.float32)
+
+
 def draw(seed, it, f, s, mean, std, p, m, mix_thr):
     """Mixture draw of one expansion.  Returns (learned, u) with u in FP64 for
     a learned draw; None for a uniform draw (Alg. 2's own control map)."""
-    key = (int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF)
-    w = philox4x32_10((it, f, s, TAG_MIX), key)
-    if not int(w[0]) < mix_thr:
+    if not is_learned(seed, it, f, s, mix_thr):
         return False, None
-    g = philox4x32_10((it, f, s, TAG_GAUSS), key)
-    z0, z1 = box_muller(g[0], g[1])
-    z2, z3 = box_muller(g[2], g[3])
-    z = (z0, z1, z2, z3)
+    z = gaussians(seed, it, f, s)
     lo = np.asarray(p["u_lo"], np.float32).astype(np.float64)
     hi = np.asarray(p["u_hi"], np.float32).astype(np.float64)
     u = np.array([min(max(mean[j] + std[j] * z[j], lo[j]), hi[j]) for j in range(m)])

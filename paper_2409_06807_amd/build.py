@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkinopax.so")
-SOURCES = [os.path.join(CSRC, "kp_kernels.hip"), os.path.join(CSRC, "kp_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kp_kernels.hip", "kp_mlp.hip", "kp_api.hip")]
 ARCH = os.environ.get("KP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -18,7 +18,8 @@ using namespace kp;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kProfKernels = 6;  // propagate, region, node sets, frontier, commit, fused post
+constexpr int kProfKernels = 7;  // propagate, region, node sets, frontier, commit, fused post,
+                                  // proposal network
 constexpr int kEventPool = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -140,6 +141,7 @@ struct kp_problem {
   int grid_prop_max;
   int grid_node_max;
   int grid_commit_max;
+  int grid_head_max;
   int stage;  // 0: next is kp_expand; 1: next is kp_update_regions; 2: next is kp_update_tree
   bool ctl_fresh = false;  // hctl holds the device control block (no launch since the last read)
   Ctl* hctl;  // pinned host mirror of the control block
@@ -229,6 +231,20 @@ void fill_params(kp_problem* h) {
     const double tmax = std::fmax(std::fabs((double)d.u_lo[0]), std::fabs((double)d.u_hi[0]));
     amax = tmax / std::fabs((double)d.dyn_params[0]) + std::fabs((double)d.dyn_params[1]);
   }
+  // learned proposal off; input affine map of the network's features
+  p.mix_thr = 0ull;
+  for (int k = 0; k < 16; ++k) {
+    p.fc[k] = 0.0f;
+    p.fs[k] = 0.0f;
+  }
+  for (int k = 0; k < h->n; ++k) {
+    p.fc[k] = (float)(0.5 * ((double)d.x_lo[k] + (double)d.x_hi[k]));
+    p.fs[k] = (d.x_hi[k] > d.x_lo[k]) ? (float)(2.0 / ((double)d.x_hi[k] - (double)d.x_lo[k])) : 0.0f;
+  }
+  p.fc[h->n] = 0.5f;
+  p.fs[h->n] = 2.0f;
+  for (int a = 0; a < 3; ++a)
+    p.fs[h->n + 1 + a] = (float)(2.0 / ((double)d.x_hi[a] - (double)d.x_lo[a]));
   const double hh = d.h;
   const double per_step = (d.integrator == KP_INT_EULER) ? hh * vmax : hh * (vmax + hh * amax);
   double rc = d.steps * per_step * (1.0 + 1e-4) + 1e-3;
@@ -259,6 +275,8 @@ void carve(kp_problem* h, void* ws) {
   v.st_front = reinterpret_cast<unsigned long long*>(b + L.st_front);
   v.st_nodes = reinterpret_cast<unsigned long long*>(b + L.st_nodes);
   v.path = reinterpret_cast<int32_t*>(b + L.path);
+  v.mlp = nullptr;
+  v.head = nullptr;
   v.sx = reinterpret_cast<float*>(b + L.sx);
   v.su = reinterpret_cast<float*>(b + L.su);
   v.scell = reinterpret_cast<uint32_t*>(b + L.scell);
@@ -369,6 +387,19 @@ kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
   const int nn = (int)(ntiles < h->grid_node_max ? ntiles : h->grid_node_max);
   hipError_t e = launch_post(h->env_dev, nc, nn, h->stream, prof_slot(h, 5));
   if (e != hipSuccess) return hip_fail(h, e, "post launch");
+  return KP_OK;
+}
+
+// the proposal network over the frontier (before a propagate launch), when a
+// learned proposal is set; nf_ub bounds |V_E|
+kp_status do_head(kp_problem* h, long long nf_ub) {
+  if (h->prm.mix_thr == 0ull) return KP_OK;
+  h->ctl_fresh = false;
+  const long long blocks = (nf_ub + 63) / 64;
+  int grid = (int)(blocks < h->grid_head_max ? blocks : h->grid_head_max);
+  if (grid < 1) grid = 1;
+  hipError_t e = launch_mlp_head(h->env_dev, grid, h->stream, prof_slot(h, 6));
+  if (e != hipSuccess) return hip_fail(h, e, "proposal launch");
   return KP_OK;
 }
 
@@ -498,6 +529,7 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
   h->grid_prop_max = bp * h->cu_count;
   h->grid_node_max = bn * h->cu_count;
   h->grid_commit_max = bc * h->cu_count;
+  h->grid_head_max = mlp_head_grid_max(h->cu_count);
   if (hipHostMalloc(reinterpret_cast<void**>(&h->hctl), sizeof(Ctl), hipHostMallocDefault) !=
       hipSuccess) {
     delete h;
@@ -553,7 +585,9 @@ kp_status kp_expand(kp_problem* h, void* dev_trace) {
   if (!h) return KP_E_ARG;
   if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_expand must follow kp_update_tree");
   const long long ub = (long long)h->desc.node_cap - h->hctl->N;
-  kp_status st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1, true);
+  kp_status st = do_head(h, h->desc.node_cap);
+  if (st != KP_OK) return st;
+  st = do_propagate(h, static_cast<TraceRec*>(dev_trace), ub > 0 ? ub : 1, true);
   if (st != KP_OK) return st;
   h->stage = 1;
   return KP_OK;
@@ -613,6 +647,7 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
       // exact sizes for the first iteration of a batch, bounds after it
       const long long lanes_ub = (b == 0) ? c.lanes : cap - c.N;
       const long long old_nodes_ub = (b == 0) ? (long long)c.N : cap;
+      if ((st = do_head(h, (b == 0) ? (long long)c.nF : cap)) != KP_OK) return st;
       if ((st = do_propagate(h, nullptr, lanes_ub, false)) != KP_OK) return st;
       if ((st = do_post(h, lanes_ub, old_nodes_ub)) != KP_OK) return st;
     }
@@ -819,5 +854,118 @@ const char* kp_status_str(kp_status s) {
 }
 
 const char* kp_last_error(const kp_problem* h) { return h ? h->err.c_str() : ""; }
+
+// ---------------------------------------------------------------------------
+// learned proposal
+// ---------------------------------------------------------------------------
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+kp_status kp_mlp_pack(const float* dev_params, void* dev_packed, void* hip_stream) {
+  if (!dev_params || !dev_packed || !aligned16(dev_packed)) return KP_E_ARG;
+  if (launch_mlp_pack(dev_params, static_cast<uint4*>(dev_packed),
+                      static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return KP_E_DEVICE;
+  return KP_OK;
+}
+
+kp_status kp_mlp_forward(const void* dev_packed, const float* dev_x, int32_t rows, float* dev_out,
+                         void* hip_stream) {
+  if (rows < 0) return KP_E_ARG;
+  if (rows == 0) return KP_OK;
+  if (!dev_packed || !dev_x || !dev_out || !aligned16(dev_packed) || !aligned16(dev_x) ||
+      !aligned16(dev_out))
+    return KP_E_ARG;
+  if (launch_mlp_forward(static_cast<const uint4*>(dev_packed), dev_x, rows, dev_out,
+                         static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return KP_E_DEVICE;
+  return KP_OK;
+}
+
+kp_status kp_mlp_grad(const void* dev_packed, const float* dev_x, const float* dev_t, int32_t n_rows,
+                      int32_t n_ctrl, int32_t batch, uint64_t sample_key, int32_t step,
+                      float* dev_partials, float* dev_loss, void* hip_stream) {
+  if (!dev_packed || !dev_x || !dev_t || !dev_partials || !dev_loss || !aligned16(dev_packed) ||
+      !aligned16(dev_x))
+    return KP_E_ARG;
+  if (n_rows < 1 || batch < 1 || n_ctrl < 1 || n_ctrl > 4 || step < 0) return KP_E_ARG;
+  if (sample_key == 0 && batch > n_rows) return KP_E_ARG;
+  if (launch_mlp_grad(static_cast<const uint4*>(dev_packed), dev_x, dev_t, n_rows, n_ctrl, batch,
+                      sample_key, step, dev_partials, dev_loss,
+                      static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return KP_E_DEVICE;
+  return KP_OK;
+}
+
+kp_status kp_mlp_adam(float* dev_params, float* dev_m1, float* dev_m2, const float* dev_partials,
+                      int32_t n_partials, int32_t step, float lr, float beta1, float beta2,
+                      float eps, void* hip_stream) {
+  if (!dev_params || !dev_m1 || !dev_m2 || !dev_partials || n_partials < 1 || step < 1)
+    return KP_E_ARG;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+      !(lr >= 0.0f))
+    return KP_E_ARG;
+  const double bc1 = 1.0 - std::pow((double)beta1, (double)step);
+  const double bc2 = 1.0 - std::pow((double)beta2, (double)step);
+  if (!(bc1 > 0.0) || !(bc2 > 0.0)) return KP_E_ARG;
+  if (launch_mlp_adam(dev_params, dev_m1, dev_m2, dev_partials, n_partials, lr, beta1, beta2, eps,
+                      (float)(1.0 / bc1), (float)(1.0 / bc2),
+                      static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return KP_E_DEVICE;
+  return KP_OK;
+}
+
+kp_status kp_mlp_train(float* dev_params, float* dev_m1, float* dev_m2, void* dev_packed,
+                       const float* dev_x, const float* dev_t, int32_t n_rows, int32_t n_ctrl,
+                       int32_t batch, int32_t steps, int32_t step0, float lr, uint64_t sample_key,
+                       float* dev_partials, float* dev_loss, void* hip_stream) {
+  if (steps < 0 || step0 < 0 || sample_key == 0 || !dev_loss) return KP_E_ARG;
+  const int32_t nb = (batch + KP_MLP_BLOCK_ROWS - 1) / KP_MLP_BLOCK_ROWS;
+  for (int32_t k = 0; k < steps; ++k) {
+    kp_status st = kp_mlp_pack(dev_params, dev_packed, hip_stream);
+    if (st == KP_OK)
+      st = kp_mlp_grad(dev_packed, dev_x, dev_t, n_rows, n_ctrl, batch, sample_key, step0 + k,
+                       dev_partials, dev_loss + (size_t)k * nb, hip_stream);
+    if (st == KP_OK)
+      st = kp_mlp_adam(dev_params, dev_m1, dev_m2, dev_partials, nb, step0 + k + 1, lr, 0.9f,
+                       0.999f, 1e-8f, hip_stream);
+    if (st != KP_OK) return st;
+  }
+  return kp_mlp_pack(dev_params, dev_packed, hip_stream);
+}
+
+kp_status kp_set_proposal(kp_problem* h, const void* dev_packed, float* dev_head, int64_t head_rows,
+                          float mix) {
+  if (!h) return KP_E_ARG;
+  if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_set_proposal in the middle of an iteration");
+  if (!(mix >= 0.0f && mix <= 1.0f)) return fail(h, KP_E_ARG, "mix must be in [0, 1]");
+  const bool on = dev_packed != nullptr && mix > 0.0f;
+  if (on) {
+    if (!dev_head || head_rows < h->desc.node_cap || !aligned16(dev_packed) || !aligned16(dev_head))
+      return fail(h, KP_E_ARG, "kp_set_proposal: head buffer must hold node_cap rows of 8 floats");
+  }
+  h->prm.mix_thr = on ? (unsigned long long)std::floor((double)mix * 4294967296.0) : 0ull;
+  h->dev.mlp = on ? static_cast<const uint4*>(dev_packed) : nullptr;
+  h->dev.head = on ? dev_head : nullptr;
+  hipError_t e = upload_env(h);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "proposal upload");
+  return KP_OK;
+}
+
+kp_status kp_log_path(kp_problem* h, int32_t node, float* dev_x, float* dev_t, int32_t cap_rows,
+                      int32_t row0, int32_t* n_rows) {
+  if (!h || !n_rows || !dev_x || !dev_t || cap_rows < 0 || row0 < 0) return KP_E_ARG;
+  *n_rows = 0;
+  int32_t len = 0;
+  kp_status st = kp_get_path(h, node, nullptr, 0, &len);
+  if (st != KP_OK) return st;
+  const int32_t edges = len - 1;
+  if (edges <= 0 || row0 >= cap_rows) return KP_OK;
+  hipError_t e = launch_log_path(h->env_dev, dev_x, dev_t, cap_rows, row0, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "path logging");
+  *n_rows = edges < cap_rows - row0 ? edges : cap_rows - row0;
+  return KP_OK;
+}
 
 }  // extern "C"

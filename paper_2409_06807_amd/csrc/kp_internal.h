@@ -79,6 +79,11 @@ struct Params {
   float dIyz, dIzx, dIxy;   // Iyy - Izz, Izz - Ixx, Ixx - Iyy
   uint32_t key0, key1;
   double delta, eps;
+  // learned proposal: a sample takes the network's Gaussian when its mixture
+  // word is below mix_thr (0: uniform only); network inputs are
+  // (raw feature - fc) * fs
+  unsigned long long mix_thr;
+  float fc[16], fs[16];
 };
 
 // Device pointers carved from the caller's workspace.
@@ -109,6 +114,8 @@ struct Dev {
   uint32_t* ssum;      // [2][nchunk] accepted samples per kChunkTiles consecutive wave
                        // tiles; iteration it uses half it & 1
   int32_t* path;       // [kMaxPath + 1]
+  const uint4* mlp;    // packed network (kp_mlp_pack layout), borrowed; null if uniform
+  float* head;         // [rows][8] Gaussian mean (4) and std (4) per frontier entry, borrowed
   int32_t capP;        // padded node capacity (multiple of kNodeTile)
   int32_t tiles_node;  // entries of st_front / st_nodes
   int32_t nchunk;      // entries of ssum
@@ -154,6 +161,26 @@ hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s,
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
+
+// learned proposal (kp_mlp.hip)
+constexpr int kMlpIn = 16, kMlpHid = 128, kMlpOut = 8;
+constexpr int kMlpParams = kMlpHid * kMlpIn + kMlpHid + kMlpHid * kMlpHid + kMlpHid +
+                           kMlpOut * kMlpHid + kMlpOut;
+constexpr int kMlpRowsPerBlock = 64;  // rows per training block (one partial gradient each)
+size_t mlp_packed_bytes();
+hipError_t launch_mlp_pack(const float* params, uint4* packed, hipStream_t s);
+hipError_t launch_mlp_forward(const uint4* packed, const float* x, int32_t rows, float* out,
+                              hipStream_t s);
+hipError_t launch_mlp_head(const Env* env, int grid, hipStream_t s, Timing t);
+int mlp_head_grid_max(int cu_count);
+hipError_t launch_mlp_grad(const uint4* packed, const float* x, const float* t, int32_t n_rows,
+                           int32_t m, int32_t batch, uint64_t key, int32_t step, float* partials,
+                           float* loss, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* partials,
+                           int32_t n_partials, float lr, float beta1, float beta2, float eps,
+                           float inv_bc1, float inv_bc2, hipStream_t s);
+hipError_t launch_log_path(const Env* env, float* x, float* t, int32_t cap_rows, int32_t row0,
+                           hipStream_t s);
 int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
 int occupancy_commit(int* blocks_per_cu);

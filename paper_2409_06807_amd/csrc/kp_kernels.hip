@@ -23,6 +23,7 @@
 #include <hip/hip_ext.h>
 
 #include "kp.h"
+#include "kp_device.h"
 
 namespace kp {
 
@@ -152,36 +153,6 @@ __device__ __forceinline__ uint32_t block_offsets(uint32_t wave_total, uint32_t*
   *prefix = *s_pref;
   if (tile_total) *tile_total = agg;
   return off;
-}
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11) and the control map
-// ---------------------------------------------------------------------------
-struct U4 {
-  uint32_t w[4];
-};
-
-__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                     uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  U4 o;
-  o.w[0] = c0;
-  o.w[1] = c1;
-  o.w[2] = c2;
-  o.w[3] = c3;
-  return o;
 }
 
 // top 24 bits as a fraction in [0,1), then lo + (hi - lo) * r with one rounding
@@ -609,12 +580,6 @@ __device__ __forceinline__ uint32_t compact_frontier(const Dev& d, unsigned long
   return prefix + agg;
 }
 
-// e-th frontier node: explicit list first, then the implicit tail of ids
-__device__ __forceinline__ int32_t frontier_node(const int32_t* F, int32_t e, int32_t f_expl,
-                                                 int32_t f_base) {
-  return (e < f_expl) ? F[e] : f_base + (e - f_expl);
-}
-
 // last-block finalisation of the frontier: |V_E|, eq. (6), termination codes
 __device__ __forceinline__ void finalize_frontier(const Params& p, Ctl* c, uint32_t nF,
                                                   int32_t N) {
@@ -807,6 +772,24 @@ __global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4)))
       } else {
         const U4 w1 = philox(it, (uint32_t)f, (uint32_t)s, 1u, p.key0, p.key1);
         w_acc = w1.w[0];
+      }
+      // learned proposal: with probability mix_thr / 2^32 the control comes
+      // from the network's Gaussian for this frontier entry instead
+      if (p.mix_thr != 0ull) {
+        const U4 wm = philox(it, (uint32_t)f, (uint32_t)s, 4u, p.key0, p.key1);
+        if ((unsigned long long)wm.w[0] < p.mix_thr) {
+          const float4 mu = reinterpret_cast<const float4*>(d.head + (size_t)e * 8)[0];
+          const float4 sd = reinterpret_cast<const float4*>(d.head + (size_t)e * 8)[1];
+          const U4 wz = philox(it, (uint32_t)f, (uint32_t)s, 5u, p.key0, p.key1);
+          float z[4];
+          box_muller(wz.w[0], wz.w[1], &z[0], &z[1]);
+          box_muller(wz.w[2], wz.w[3], &z[2], &z[3]);
+          const float mv[4] = {mu.x, mu.y, mu.z, mu.w};
+          const float sv[4] = {sd.x, sd.y, sd.z, sd.w};
+#pragma unroll
+          for (int j = 0; j < m; ++j)
+            u[j] = fminf(fmaxf(__builtin_fmaf(sv[j], z[j], mv[j]), p.u_lo[j]), p.u_hi[j]);
+        }
       }
     } else {
 #pragma unroll

@@ -1,0 +1,636 @@
+// Learned control proposal for gfx950: a three-layer network
+// (16 -> 128 -> 128 -> 8) on MFMA, BF16 operands and FP32 accumulation.
+//
+// Alg. 2 draws every control uniformly from U.  The learned proposal keeps
+// that draw for a fixed share of the samples and otherwise draws from a
+// Gaussian whose mean and spread the network predicts from the parent node;
+// the uniform share keeps a positive density on all of U, which is what the
+// completeness argument of Sec. V needs.
+//
+//   k_mlp_pack     FP32 parameters -> BF16 A-operand fragments + FP32 biases
+//   k_mlp_forward  raw network outputs for rows of features
+//   k_mlp_head     per frontier entry of the planner: the node's features,
+//                  the network, and the Gaussian mean / std in control units
+//   k_mlp_grad     minibatch forward and backward of the Gaussian negative
+//                  log-likelihood; one partial gradient per 64-row block
+//   k_mlp_adam     fixed-order sum of the partial gradients, one Adam step
+//                  (Kingma & Ba, 2015)
+//   k_log_path     training rows (parent features, normalised control) from
+//                  the edges of a root-to-node path
+//
+// Layout of the network in registers.  Every product is computed transposed,
+// out^T = W * in^T, so the weights are the A operand (16 x 32 per MFMA) and
+// the activations of 16 rows are the B operand.  v_mfma_f32_16x16x32_bf16
+// leaves lane l holding outputs 16 t + 4 (l / 16) + r (r = 0..3) of row
+// l % 16 for output tile t.  Packing tiles 2s and 2s+1 of that accumulator to
+// BF16 gives, unchanged, the B operand of K-step s of the next layer when the
+// next layer's weights are stored with the matching K order (hid_k below), so
+// activations never leave registers between layers.
+#include "kp_internal.h"
+
+#include <hip/hip_ext.h>
+
+#include "kp.h"
+#include "kp_device.h"
+
+namespace kp {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + kMlpHid * kMlpIn;
+constexpr int OFF_W2 = OFF_B1 + kMlpHid;
+constexpr int OFF_B2 = OFF_W2 + kMlpHid * kMlpHid;
+constexpr int OFF_W3 = OFF_B2 + kMlpHid;
+constexpr int OFF_B3 = OFF_W3 + kMlpOut * kMlpHid;
+static_assert(OFF_B3 + kMlpOut == kMlpParams, "parameter layout");
+
+constexpr float kLsMin = -4.0f, kLsMax = 0.0f;  // clip of the log standard deviation
+constexpr uint32_t kTagBatch = 6u;              // Philox tag of the minibatch draws
+
+// Fragment entries (16 bytes: 8 BF16 values of one lane's A operand):
+//   F1  W1        8 tiles x 1 K-step       F2T  W2^T  8 tiles x 4 K-steps
+//   F2  W2        8 tiles x 4 K-steps      F3T  W3^T  8 tiles x 1 K-step
+//   F3  W3 (pad)  1 tile  x 4 K-steps
+// followed by the biases b1, b2, b3 as FP32.
+constexpr int E_F1 = 0;
+constexpr int E_F2 = E_F1 + 8 * 1 * 64;
+constexpr int E_F3 = E_F2 + 8 * 4 * 64;
+constexpr int E_F2T = E_F3 + 1 * 4 * 64;
+constexpr int E_F3T = E_F2T + 8 * 4 * 64;
+constexpr int E_END = E_F3T + 8 * 1 * 64;
+constexpr int E_FWD = E_F2T;  // entries of the forward pass (F1, F2, F3)
+constexpr int N_BIAS = kMlpHid + kMlpHid + kMlpOut;
+constexpr size_t kPackedBytes = (size_t)E_END * 16 + (size_t)N_BIAS * 4;
+static_assert(kPackedBytes == KP_MLP_PACKED_BYTES, "packed size in kp.h");
+static_assert(kMlpParams == KP_MLP_PARAMS, "parameter count in kp.h");
+
+// K index held in slot j of lane group g at K-step s, for a 128-long hidden
+// vector held in the accumulator layout (tiles 2s and 2s+1, four each)
+__host__ __device__ constexpr int hid_k(int s, int g, int j) {
+  return 16 * (2 * s + (j >> 2)) + 4 * g + (j & 3);
+}
+
+// parameter held by slot j of fragment entry e, or -1 for a zero
+__device__ int frag_param(int e, int j) {
+  const int lane = e & 63, i = lane & 15, g = lane >> 4;
+  if (e < E_F2) {  // F1: W1[16t + i][8g + j]; inputs 16..31 of the K-step are zero
+    const int t = (e - E_F1) >> 6;
+    return g < 2 ? OFF_W1 + (16 * t + i) * kMlpIn + 8 * g + j : -1;
+  }
+  if (e < E_F3) {  // F2: W2[16t + i][hid_k(s, g, j)]
+    const int ts = (e - E_F2) >> 6, t = ts >> 2, s = ts & 3;
+    return OFF_W2 + (16 * t + i) * kMlpHid + hid_k(s, g, j);
+  }
+  if (e < E_F2T) {  // F3: W3[i][hid_k(s, g, j)], rows 8..15 zero
+    const int s = (e - E_F3) >> 6;
+    return i < kMlpOut ? OFF_W3 + i * kMlpHid + hid_k(s, g, j) : -1;
+  }
+  if (e < E_F3T) {  // F2T: W2^T[16t + i][hid_k(s, g, j)] = W2[hid_k][16t + i]
+    const int ts = (e - E_F2T) >> 6, t = ts >> 2, s = ts & 3;
+    return OFF_W2 + hid_k(s, g, j) * kMlpHid + 16 * t + i;
+  }
+  // F3T: W3^T[16t + i][4g + j] for output 4g + j < 8 (lane groups 0, 1, slots 0..3)
+  const int t = (e - E_F3T) >> 6;
+  return (g < 2 && j < 4) ? OFF_W3 + (4 * g + j) * kMlpHid + 16 * t + i : -1;
+}
+
+// round to nearest BF16, ties to even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  uint32_t b = __float_as_uint(v);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return b >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t bits) { return __uint_as_float(bits << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 w) { return __builtin_bit_cast(bf16x8, w); }
+__device__ __forceinline__ u32x4 as_u32x4(bf16x8 v) { return __builtin_bit_cast(u32x4, v); }
+
+__device__ __forceinline__ bf16x8 pack8(const float* f) {
+  u32x4 w;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) w[h] = bf16_bits(f[2 * h]) | (bf16_bits(f[2 * h + 1]) << 16);
+  return as_bf16x8(w);
+}
+
+// BF16 relu of accumulator tiles a (slots 0..3) and b (slots 4..7)
+__device__ __forceinline__ bf16x8 pack_relu(const f32x4& a, const f32x4& b) {
+  float f[8];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    f[r] = fmaxf(a[r], 0.0f);
+    f[4 + r] = fmaxf(b[r], 0.0f);
+  }
+  return pack8(f);
+}
+
+// slot j of a packed operand, as BF16 bits
+__device__ __forceinline__ uint32_t slot_bits(bf16x8 v, int j) {
+  const u32x4 w = as_u32x4(v);
+  return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+}
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), b, c, 0, 0, 0);
+}
+
+struct Fwd {
+  f32x4 o;        // lane group 0: outputs 0..3, group 1: outputs 4..7 (row lane % 16)
+  bf16x8 h1[4];   // BF16 relu(layer 1), B operand of layer 2 per K-step
+  bf16x8 h2[4];   // BF16 relu(layer 2), B operand of layer 3 per K-step
+};
+
+// The network on the 16 rows whose layer-1 operand is xb.  frag: fragment
+// entries (LDS or global); bias: b1, b2, b3 (FP32).
+__device__ __forceinline__ void forward_wave(const u32x4* frag, const float* bias, bf16x8 xb,
+                                             Fwd& r) {
+  const int lane = __lane_id(), g = lane >> 4;
+  f32x4 acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[t][q] = bias[16 * t + 4 * g + q];
+    acc[t] = mfma(frag[E_F1 + t * 64 + lane], xb, acc[t]);
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) r.h1[s] = pack_relu(acc[2 * s], acc[2 * s + 1]);
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[t][q] = bias[kMlpHid + 16 * t + 4 * g + q];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = mfma(frag[E_F2 + (t * 4 + s) * 64 + lane], r.h1[s], acc[t]);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) r.h2[s] = pack_relu(acc[2 * s], acc[2 * s + 1]);
+  f32x4 o;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = g < 2 ? bias[2 * kMlpHid + 4 * g + q] : 0.0f;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o = mfma(frag[E_F3 + s * 64 + lane], r.h2[s], o);
+  r.o = o;
+}
+
+// raw feature k of a tree node: state, P_accept of its region, goal offset
+__device__ __forceinline__ float raw_feature(const Params& p, const Dev& d, int32_t node, int k,
+                                             float pacc) {
+  const int n = p.n;
+  if (k < n) return d.x[(size_t)k * d.capP + node];
+  if (k == n) return pacc;
+  if (k <= n + 3) {
+    const int a = k - n - 1;
+    return p.goal_c[a] - d.x[(size_t)a * d.capP + node];
+  }
+  return 0.0f;
+}
+
+__device__ __forceinline__ float node_pacc(const Dev& d, int32_t node) {
+  const unsigned long long thr = d.thr[d.cell[node] >> 6];
+  const unsigned long long t = thr < (1ull << 32) ? thr : (1ull << 32);
+  return (float)t * 0x1p-32f;
+}
+
+// layer-1 operand of row `node` for this lane: features 8g .. 8g+7 (g < 2)
+__device__ __forceinline__ bf16x8 node_operand(const Params& p, const Dev& d, int32_t node,
+                                               bool valid) {
+  const int g = __lane_id() >> 4;
+  float f[8];
+  if (valid && g < 2) {
+    const float pacc = node_pacc(d, node);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * g + j;
+      f[j] = (raw_feature(p, d, node, k, pacc) - p.fc[k]) * p.fs[k];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = 0.0f;
+  }
+  return pack8(f);
+}
+
+__device__ __forceinline__ bf16x8 row_operand(const float* x, int32_t row, bool valid) {
+  const int g = __lane_id() >> 4;
+  float f[8];
+  if (valid && g < 2) {
+    const float4 a = reinterpret_cast<const float4*>(x + (size_t)row * kMlpIn + 8 * g)[0];
+    const float4 b = reinterpret_cast<const float4*>(x + (size_t)row * kMlpIn + 8 * g)[1];
+    f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+    f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = 0.0f;
+  }
+  return pack8(f);
+}
+
+// forward-pass weights and biases into LDS
+__device__ __forceinline__ void stage_forward(const u32x4* packed, u32x4* sfrag, float* sbias) {
+  for (int k = threadIdx.x; k < E_FWD; k += blockDim.x) sfrag[k] = packed[k];
+  const float* b = reinterpret_cast<const float*>(packed + E_END);
+  for (int k = threadIdx.x; k < N_BIAS; k += blockDim.x) sbias[k] = b[k];
+  __syncthreads();
+}
+
+constexpr int kMlpBlock = 256;  // 4 waves of 16 rows each per pass
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ prm,
+                                                  u32x4* __restrict__ packed) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E_END) {
+    u32x4 w;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int a = frag_param(e, 2 * h), b = frag_param(e, 2 * h + 1);
+      const uint32_t lo = a >= 0 ? bf16_bits(prm[a]) : 0u;
+      const uint32_t hi = b >= 0 ? bf16_bits(prm[b]) : 0u;
+      w[h] = lo | (hi << 16);
+    }
+    packed[e] = w;
+  } else if (e < E_END + N_BIAS) {
+    const int k = e - E_END;
+    const int src = k < kMlpHid       ? OFF_B1 + k
+                    : k < 2 * kMlpHid ? OFF_B2 + (k - kMlpHid)
+                                      : OFF_B3 + (k - 2 * kMlpHid);
+    reinterpret_cast<float*>(packed + E_END)[k] = prm[src];
+  }
+}
+
+__global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(const u32x4* __restrict__ packed,
+                                                           const float* __restrict__ x,
+                                                           int32_t rows, float* __restrict__ out) {
+  __shared__ u32x4 sfrag[E_FWD];
+  __shared__ float sbias[N_BIAS];
+  const int groups = (rows + 15) / 16;
+  if ((int)blockIdx.x * 4 >= groups) return;
+  stage_forward(packed, sfrag, sbias);
+  const int wave = threadIdx.x >> 6, lane = __lane_id(), g = lane >> 4;
+  for (int q = blockIdx.x * 4 + wave; q < groups; q += gridDim.x * 4) {
+    const int32_t row = q * 16 + (lane & 15);
+    const bool valid = row < rows;
+    Fwd r;
+    forward_wave(sfrag, sbias, row_operand(x, row, valid), r);
+    if (valid && g < 2)
+      reinterpret_cast<float4*>(out + (size_t)row * kMlpOut)[g] =
+          make_float4(r.o[0], r.o[1], r.o[2], r.o[3]);
+  }
+}
+
+// Per frontier entry e (the layout the expansion lanes index by e = lane /
+// lambda): Gaussian mean (4 floats) and standard deviation (4 floats).
+__global__ __launch_bounds__(kMlpBlock) void k_mlp_head(const Env* __restrict__ env) {
+  __shared__ u32x4 sfrag[E_FWD];
+  __shared__ float sbias[N_BIAS];
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  const Ctl* c = d.ctl;
+  if (c->done) return;
+  const int32_t nF = c->nF, f_expl = c->f_expl, f_base = c->f_base;
+  const int groups = (nF + 15) / 16;
+  if ((int)blockIdx.x * 4 >= groups) return;
+  stage_forward(reinterpret_cast<const u32x4*>(d.mlp), sfrag, sbias);
+  const int wave = threadIdx.x >> 6, lane = __lane_id(), g = lane >> 4;
+  const int m = p.m;
+  for (int q = blockIdx.x * 4 + wave; q < groups; q += gridDim.x * 4) {
+    const int32_t e = q * 16 + (lane & 15);
+    const bool valid = e < nF;
+    const int32_t node = valid ? frontier_node(d.F, e, f_expl, f_base) : 0;
+    Fwd r;
+    forward_wave(sfrag, sbias, node_operand(p, d, node, valid), r);
+    if (valid && g < 2) {
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float lo = p.u_lo[j], hi = p.u_hi[j];
+        const float ctr = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
+        if (j >= m) v[j] = 0.0f;
+        else if (g == 0) v[j] = ctr + half * tanhf(r.o[j]);
+        else v[j] = half * expf(fminf(fmaxf(r.o[j], kLsMin), kLsMax));
+      }
+      reinterpret_cast<float4*>(d.head + (size_t)e * 8)[g] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+constexpr int kTrStride = 72;  // BF16 per row of a transposed activation tile (64 rows + pad)
+
+__device__ __forceinline__ u32x4 lds_frag(const uint16_t* base, int row, int col) {
+  return *reinterpret_cast<const u32x4*>(base + row * kTrStride + col);
+}
+
+// One 64-row block of a minibatch: forward, the loss gradient at the
+// outputs, backward through both hidden layers (register resident, weights
+// as A operands), then the weight gradients as products over the block's rows
+// with activations transposed through LDS.  Writes the block's gradient of
+// the mean loss (all kMlpParams entries) and its share of the mean loss.
+__global__ __launch_bounds__(kMlpBlock) void k_mlp_grad(const u32x4* __restrict__ packed,
+                                                        const float* __restrict__ X,
+                                                        const float* __restrict__ T,
+                                                        int32_t n_rows, int32_t m, int32_t batch,
+                                                        uint32_t key0, uint32_t key1,
+                                                        int32_t step, float* __restrict__ partials,
+                                                        float* __restrict__ loss_out) {
+  // phase A: H1T, DZ2T, DZ1T [128][kTrStride], XT [16][kTrStride]
+  // phase B: H2T [128][kTrStride], DOT [16][kTrStride]
+  __shared__ uint16_t tr[(3 * kMlpHid + kMlpIn) * kTrStride];
+  __shared__ float wloss[4];
+  uint16_t* H1T = tr;
+  uint16_t* DZ2T = tr + kMlpHid * kTrStride;
+  uint16_t* DZ1T = tr + 2 * kMlpHid * kTrStride;
+  uint16_t* XT = tr + 3 * kMlpHid * kTrStride;
+  uint16_t* H2T = tr;
+  uint16_t* DOT = tr + kMlpHid * kTrStride;
+
+  const int wave = threadIdx.x >> 6, lane = __lane_id(), g = lane >> 4, n = lane & 15;
+  const int col = wave * 16 + n;  // row of the block
+  const int32_t k = (int32_t)blockIdx.x * kMlpRowsPerBlock + col;
+  const bool valid = k < batch;
+  int32_t row = k;
+  if ((key0 | key1) != 0u) {
+    const U4 w = philox((uint32_t)step, (uint32_t)k, 0u, kTagBatch, key0, key1);
+    row = (int32_t)(((unsigned long long)w.w[0] * (unsigned long long)n_rows) >> 32);
+  }
+  const float* bias = reinterpret_cast<const float*>(packed + E_END);
+  const bf16x8 xb = row_operand(X, row, valid);
+  Fwd r;
+  forward_wave(packed, bias, xb, r);
+
+  // outputs: lane groups 0 and 1 of a row swap halves, so both see mean and log-std
+  float tj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) tj[j] = (valid && j < m) ? T[(size_t)row * 4 + j] : 0.0f;
+  float dv[4];
+  float lrow = 0.0f;
+  const float inv_b = 1.0f / (float)batch;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float other = __shfl_xor(r.o[j], 16);
+    const float om = (g == 0) ? r.o[j] : other;
+    const float ol = (g == 0) ? other : r.o[j];
+    const float a = tanhf(om);
+    const float ls = fminf(fmaxf(ol, kLsMin), kLsMax);
+    const float e2 = expf(-2.0f * ls);
+    const float rr = tj[j] - a;
+    const bool use = valid && j < m && g < 2;
+    if (g == 0) {
+      dv[j] = use ? -rr * (1.0f - a * a) * e2 * inv_b : 0.0f;
+      if (use) lrow += 0.5f * rr * rr * e2 + ls;
+    } else {
+      const bool inside = ol > kLsMin && ol < kLsMax;
+      dv[j] = (use && inside) ? (1.0f - rr * rr * e2) * inv_b : 0.0f;
+    }
+  }
+  // d loss / d outputs as the B operand of the W3^T products: slots 0..3 of
+  // lane group g hold outputs 4g .. 4g+3
+  u32x4 dw = {0u, 0u, 0u, 0u};
+  if (g < 2) {
+    dw[0] = bf16_bits(dv[0]) | (bf16_bits(dv[1]) << 16);
+    dw[1] = bf16_bits(dv[2]) | (bf16_bits(dv[3]) << 16);
+  }
+  const bf16x8 dob = as_bf16x8(dw);
+
+  // layer 3 backward: d h2 = W3^T d o, masked by relu
+  bf16x8 dz2[4];
+  {
+    f32x4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      acc[t] = mfma(packed[E_F3T + t * 64 + lane], dob, acc[t]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t hb = slot_bits(r.h2[t >> 1], 4 * (t & 1) + q);
+        if (!(hb != 0u && hb < 0x8000u)) acc[t][q] = 0.0f;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      float f[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f[q] = acc[2 * s][q];
+        f[4 + q] = acc[2 * s + 1][q];
+      }
+      dz2[s] = pack8(f);
+    }
+  }
+  // layer 2 backward: d h1 = W2^T d z2, masked by relu
+  bf16x8 dz1[4];
+  {
+    f32x4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] = mfma(packed[E_F2T + (t * 4 + s) * 64 + lane], dz2[s], acc[t]);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t hb = slot_bits(r.h1[t >> 1], 4 * (t & 1) + q);
+        if (!(hb != 0u && hb < 0x8000u)) acc[t][q] = 0.0f;
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      float f[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f[q] = acc[2 * s][q];
+        f[4 + q] = acc[2 * s + 1][q];
+      }
+      dz1[s] = pack8(f);
+    }
+  }
+
+  // phase A: transposes of h1, d z2, d z1, x
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = 16 * t + 4 * g + q, j = 4 * (t & 1) + q;
+      H1T[f * kTrStride + col] = (uint16_t)slot_bits(r.h1[t >> 1], j);
+      DZ2T[f * kTrStride + col] = (uint16_t)slot_bits(dz2[t >> 1], j);
+      DZ1T[f * kTrStride + col] = (uint16_t)slot_bits(dz1[t >> 1], j);
+    }
+  if (g < 2)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) XT[(8 * g + j) * kTrStride + col] = (uint16_t)slot_bits(xb, j);
+  {
+    float lw = lrow;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lw += __shfl_xor(lw, o);
+    if (lane == 0) wloss[wave] = lw;
+  }
+  __syncthreads();
+
+  float* gout = partials + (size_t)blockIdx.x * kMlpParams;
+  // W2 gradient: out feature tiles 2*wave, 2*wave+1; input feature tiles 0..7
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int tm = 2 * wave + a;
+    for (int tn = 0; tn < 8; ++tn) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        acc = mfma(lds_frag(DZ2T, 16 * tm + n, 32 * s + 8 * g),
+                   as_bf16x8(lds_frag(H1T, 16 * tn + n, 32 * s + 8 * g)), acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        gout[OFF_W2 + (16 * tm + 4 * g + q) * kMlpHid + 16 * tn + n] = acc[q];
+    }
+    // W1 gradient: the same out tiles, the 16 inputs
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      acc = mfma(lds_frag(DZ1T, 16 * tm + n, 32 * s + 8 * g),
+                 as_bf16x8(lds_frag(XT, n, 32 * s + 8 * g)), acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gout[OFF_W1 + (16 * tm + 4 * g + q) * kMlpIn + n] = acc[q];
+  }
+  {
+    // bias gradients of the hidden layers: sums over the block's rows
+    const int f = threadIdx.x & (kMlpHid - 1);
+    const uint16_t* src = (threadIdx.x < kMlpHid) ? DZ1T : DZ2T;
+    float sum = 0.0f;
+    for (int c2 = 0; c2 < kMlpRowsPerBlock; ++c2) sum += bf16_value(src[f * kTrStride + c2]);
+    gout[(threadIdx.x < kMlpHid ? OFF_B1 : OFF_B2) + f] = sum;
+  }
+  if (threadIdx.x == 0) loss_out[blockIdx.x] = (wloss[0] + wloss[1] + wloss[2] + wloss[3]) * inv_b;
+  __syncthreads();
+
+  // phase B: transposes of h2 and d o
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      H2T[(16 * t + 4 * g + q) * kTrStride + col] = (uint16_t)slot_bits(r.h2[t >> 1], 4 * (t & 1) + q);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) DOT[(4 * g + q) * kTrStride + col] = (uint16_t)slot_bits(dob, q);
+  __syncthreads();
+  // W3 gradient: outputs 0..7 (rows 8..15 of the tile are zero), inputs in
+  // tiles 2*wave, 2*wave+1
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int tn = 2 * wave + a;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      acc = mfma(lds_frag(DOT, n, 32 * s + 8 * g), as_bf16x8(lds_frag(H2T, 16 * tn + n, 32 * s + 8 * g)),
+                 acc);
+    if (g < 2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) gout[OFF_W3 + (4 * g + q) * kMlpHid + 16 * tn + n] = acc[q];
+  }
+  if (threadIdx.x < kMlpOut) {
+    float sum = 0.0f;
+    for (int c2 = 0; c2 < kMlpRowsPerBlock; ++c2) sum += bf16_value(DOT[threadIdx.x * kTrStride + c2]);
+    gout[OFF_B3 + threadIdx.x] = sum;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ prm, float* __restrict__ m1,
+                                                  float* __restrict__ m2,
+                                                  const float* __restrict__ partials, int32_t nb,
+                                                  float lr, float beta1, float beta2, float eps,
+                                                  float inv_bc1, float inv_bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kMlpParams) return;
+  float g = 0.0f;
+  for (int b = 0; b < nb; ++b) g += partials[(size_t)b * kMlpParams + i];
+  const float a = beta1 * m1[i] + (1.0f - beta1) * g;
+  const float v = beta2 * m2[i] + (1.0f - beta2) * (g * g);
+  m1[i] = a;
+  m2[i] = v;
+  prm[i] = prm[i] - lr * (a * inv_bc1) / (sqrtf(v * inv_bc2) + eps);
+}
+
+// training rows from the path that k_path left in d.path (root first):
+// row k = features of the parent of edge k, targets = the edge's control
+// in units of the control box's half-width around its centre
+__global__ __launch_bounds__(256) void k_log_path(const Env* __restrict__ env, float* __restrict__ X,
+                                                  float* __restrict__ T, int32_t cap_rows,
+                                                  int32_t row0) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  const int32_t len = d.path[0];
+  if (len < 2 || len > kMaxPath) return;
+  for (int32_t k = threadIdx.x; k < len - 1; k += blockDim.x) {
+    const int32_t row = row0 + k;
+    if (row >= cap_rows) break;
+    const int32_t parent = d.path[1 + k], child = d.path[2 + k];
+    const float pacc = node_pacc(d, parent);
+    for (int j = 0; j < kMlpIn; ++j)
+      X[(size_t)row * kMlpIn + j] = (raw_feature(p, d, parent, j, pacc) - p.fc[j]) * p.fs[j];
+    for (int j = 0; j < 4; ++j) {
+      const float lo = p.u_lo[j], hi = p.u_hi[j];
+      const float ctr = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
+      T[(size_t)row * 4 + j] =
+          (j < p.m && half > 0.0f) ? (d.u[(size_t)j * d.capP + child] - ctr) / half : 0.0f;
+    }
+  }
+}
+
+}  // namespace
+
+size_t mlp_packed_bytes() { return kPackedBytes; }
+
+hipError_t launch_mlp_pack(const float* params, uint4* packed, hipStream_t s) {
+  const int n = E_END + N_BIAS;
+  hipLaunchKernelGGL(k_mlp_pack, dim3((n + 255) / 256), dim3(256), 0, s, params,
+                     reinterpret_cast<u32x4*>(packed));
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint4* packed, const float* x, int32_t rows, float* out,
+                              hipStream_t s) {
+  const int groups = (rows + 15) / 16;
+  int grid = (groups + 3) / 4;
+  if (grid > 1024) grid = 1024;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kMlpBlock), 0, s,
+                     reinterpret_cast<const u32x4*>(packed), x, rows, out);
+  return hipGetLastError();
+}
+
+int mlp_head_grid_max(int cu_count) { return 2 * cu_count; }
+
+hipError_t launch_mlp_head(const Env* env, int grid, hipStream_t s, Timing t) {
+  if (grid < 1) grid = 1;
+  hipExtLaunchKernelGGL(k_mlp_head, dim3(grid), dim3(kMlpBlock), 0, s, t.start, t.stop, 0, env);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const uint4* packed, const float* x, const float* t, int32_t n_rows,
+                           int32_t m, int32_t batch, uint64_t key, int32_t step, float* partials,
+                           float* loss, hipStream_t s) {
+  const int grid = (batch + kMlpRowsPerBlock - 1) / kMlpRowsPerBlock;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(kMlpBlock), 0, s,
+                     reinterpret_cast<const u32x4*>(packed), x, t, n_rows, m, batch,
+                     (uint32_t)key, (uint32_t)(key >> 32), step, partials, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* partials,
+                           int32_t n_partials, float lr, float beta1, float beta2, float eps,
+                           float inv_bc1, float inv_bc2, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, m1, m2,
+                     partials, n_partials, lr, beta1, beta2, eps, inv_bc1, inv_bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_path(const Env* env, float* x, float* t, int32_t cap_rows, int32_t row0,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_log_path, dim3(1), dim3(256), 0, s, env, x, t, cap_rows, row0);
+  return hipGetLastError();
+}
+
+}  // namespace kp

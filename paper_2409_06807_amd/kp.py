@@ -19,13 +19,19 @@ LIB_PATH = os.path.join(HERE, "libkinopax.so")
 KP_ABI_VERSION = 1
 OK, SOLVED, TIMEOUT, TREE_FULL, FRONTIER_EMPTY = 0, 1, 2, 3, 4
 E_ARG, E_DEVICE, E_WORKSPACE, E_START_INVALID, E_GOAL_INVALID, E_ORDER = -1, -2, -3, -4, -5, -6
-KERNELS = {"propagate": 0, "region": 1, "nodesets": 2, "frontier": 3, "commit": 4, "post": 5}
+KERNELS = {"propagate": 0, "region": 1, "nodesets": 2, "frontier": 3, "commit": 4, "post": 5,
+           "proposal": 6}
+MLP_INPUTS, MLP_HIDDEN, MLP_OUTPUTS = 16, 128, 8
+MLP_PARAMS = 19720
+MLP_PACKED_BYTES = 87072
+MLP_BLOCK_ROWS = 64
 
 EXPORTED = [
     "kp_workspace_bytes", "kp_trace_bytes", "kp_create_problem", "kp_destroy_problem",
     "kp_reset", "kp_expand", "kp_update_regions", "kp_update_tree", "kp_plan", "kp_get_stats",
     "kp_copy_tree", "kp_load_tree", "kp_get_path", "kp_set_profiling", "kp_kernel_times",
-    "kp_status_str", "kp_last_error",
+    "kp_status_str", "kp_last_error", "kp_mlp_pack", "kp_mlp_forward", "kp_mlp_grad",
+    "kp_mlp_adam", "kp_mlp_train", "kp_set_proposal", "kp_log_path",
 ]
 
 
@@ -130,6 +136,19 @@ def load_library():
     L.kp_status_str.restype = C.c_char_p
     L.kp_last_error.argtypes = [P]
     L.kp_last_error.restype = C.c_char_p
+    L.kp_mlp_pack.argtypes = [P, P, P]
+    L.kp_mlp_forward.argtypes = [P, P, C.c_int32, P, P]
+    L.kp_mlp_grad.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32,
+                              P, P, P]
+    L.kp_mlp_adam.argtypes = [P, P, P, P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                              C.c_float, P]
+    L.kp_mlp_train.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_int32, C.c_float, C.c_uint64, P, P, P]
+    L.kp_set_proposal.argtypes = [P, P, P, C.c_int64, C.c_float]
+    L.kp_log_path.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    for name in ("kp_mlp_pack", "kp_mlp_forward", "kp_mlp_grad", "kp_mlp_adam", "kp_mlp_train",
+                 "kp_set_proposal", "kp_log_path"):
+        getattr(L, name).restype = C.c_int
     _lib = L
     return L
 
@@ -327,6 +346,34 @@ class Planner:
         t = self._tree_struct(a, N, int(s["it"]))
         self._check(self.lib.kp_load_tree(self.h, C.byref(t)))
 
+    # --- learned proposal ---
+    def set_proposal(self, packed=None, mix: float = 0.7):
+        """Draw controls from the packed network (kp_mlp_pack output) with
+        probability mix; packed=None returns to the uniform draw."""
+        import torch
+        if packed is None or mix == 0.0:
+            self._check(self.lib.kp_set_proposal(self.h, None, None, 0, C.c_float(0.0)))
+            self._proposal = None
+            return
+        head = torch.empty((self.cap, 8), dtype=torch.float32, device=self.device)
+        self._check(self.lib.kp_set_proposal(self.h, C.c_void_p(packed.data_ptr()),
+                                             C.c_void_p(head.data_ptr()), self.cap,
+                                             C.c_float(float(mix))))
+        self._proposal = (packed, head)   # borrowed by the library
+
+    def head_rows(self, rows: int):
+        """Gaussian mean and std per frontier entry from the last network pass."""
+        if getattr(self, "_proposal", None) is None:
+            raise KPError(E_ARG, "no learned proposal set")
+        return self._proposal[1][:rows].cpu().numpy()
+
+    def log_path(self, node: int, X, T, row0: int) -> int:
+        n = C.c_int32(0)
+        self._check(self.lib.kp_log_path(self.h, int(node), C.c_void_p(X.data_ptr()),
+                                         C.c_void_p(T.data_ptr()), int(X.shape[0]), int(row0),
+                                         C.byref(n)))
+        return n.value
+
     def path(self, node: int):
         n = C.c_int32(0)
         ids = np.zeros(1 << 16, np.int32)
@@ -345,3 +392,78 @@ class Planner:
             self._check(self.lib.kp_kernel_times(self.h, k, C.byref(n), C.byref(ms)))
             out[name] = (int(n.value), float(ms.value))
         return out
+
+
+# ---------------------------------------------------------------------------
+# learned proposal: network kernels without a planner handle
+# ---------------------------------------------------------------------------
+def _stream_ptr(t):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _mlp_check(st, what):
+    if st != OK:
+        raise KPError(st, what)
+
+
+def mlp_pack(params, packed=None):
+    """FP32 parameters (device tensor of MLP_PARAMS floats) -> packed tensor."""
+    import torch
+    if packed is None:
+        packed = torch.empty(MLP_PACKED_BYTES, dtype=torch.uint8, device=params.device)
+    _mlp_check(load_library().kp_mlp_pack(C.c_void_p(params.data_ptr()), C.c_void_p(packed.data_ptr()),
+                                          _stream_ptr(params)), "kp_mlp_pack")
+    return packed
+
+
+def mlp_forward(packed, X):
+    """Raw outputs (rows x 8) of the rows of X (rows x 16, FP32 device tensor)."""
+    import torch
+    rows = int(X.shape[0])
+    out = torch.zeros((rows, MLP_OUTPUTS), dtype=torch.float32, device=X.device)
+    _mlp_check(load_library().kp_mlp_forward(C.c_void_p(packed.data_ptr()), C.c_void_p(X.data_ptr()),
+                                             rows, C.c_void_p(out.data_ptr()), _stream_ptr(X)),
+               "kp_mlp_forward")
+    return out
+
+
+def mlp_partials(batch: int) -> int:
+    return (int(batch) + MLP_BLOCK_ROWS - 1) // MLP_BLOCK_ROWS
+
+
+def mlp_grad(packed, X, T, n_ctrl: int, batch: int, key: int = 0, step: int = 0):
+    """Partial gradients (ceil(batch/64) x MLP_PARAMS) and partial losses."""
+    import torch
+    nb = mlp_partials(batch)
+    partials = torch.empty((nb, MLP_PARAMS), dtype=torch.float32, device=X.device)
+    loss = torch.empty(nb, dtype=torch.float32, device=X.device)
+    _mlp_check(load_library().kp_mlp_grad(
+        C.c_void_p(packed.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+        int(X.shape[0]), int(n_ctrl), int(batch), int(key) & ((1 << 64) - 1), int(step),
+        C.c_void_p(partials.data_ptr()), C.c_void_p(loss.data_ptr()), _stream_ptr(X)), "kp_mlp_grad")
+    return partials, loss
+
+
+def mlp_adam(params, m1, m2, partials, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step on params, m1, m2 in place."""
+    _mlp_check(load_library().kp_mlp_adam(
+        C.c_void_p(params.data_ptr()), C.c_void_p(m1.data_ptr()), C.c_void_p(m2.data_ptr()),
+        C.c_void_p(partials.data_ptr()), int(partials.shape[0]), int(step), C.c_float(lr),
+        C.c_float(beta1), C.c_float(beta2), C.c_float(eps), _stream_ptr(params)), "kp_mlp_adam")
+
+
+def mlp_train(params, m1, m2, packed, X, T, n_ctrl: int, batch: int, steps: int, lr: float,
+              key: int, step0: int = 0):
+    """`steps` minibatch Adam steps; returns the per-step losses (device tensor)."""
+    import torch
+    nb = mlp_partials(batch)
+    partials = torch.empty((nb, MLP_PARAMS), dtype=torch.float32, device=X.device)
+    loss = torch.empty((max(steps, 1), nb), dtype=torch.float32, device=X.device)
+    _mlp_check(load_library().kp_mlp_train(
+        C.c_void_p(params.data_ptr()), C.c_void_p(m1.data_ptr()), C.c_void_p(m2.data_ptr()),
+        C.c_void_p(packed.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+        int(X.shape[0]), int(n_ctrl), int(batch), int(steps), int(step0), C.c_float(lr),
+        int(key) & ((1 << 64) - 1), C.c_void_p(partials.data_ptr()), C.c_void_p(loss.data_ptr()),
+        _stream_ptr(X)), "kp_mlp_train")
+    return loss[:steps].sum(dim=1)

@@ -36,6 +36,7 @@ class Report:
         self.ambiguous_lanes = 0
         self.adopted = 0
         self.max_rel_err = 0.0
+        self.learned_lanes = 0
         self.failures = []
         self.final_status = None
 
@@ -156,6 +157,52 @@ def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
     return merged
 
 
+def check_proposal(p, W, G, tr, prop, rep, it):
+    """Learned proposal, one expansion: the network's Gaussian per frontier
+    entry against the FP64 reference, the mixture choice of every lane (exact:
+    a uniform lane keeps Alg. 2's control bit for bit), and each learned
+    control within the bound that the network tolerance and the FP32
+    transcendentals allow."""
+    from oracle import proposal as P
+    s = W.state(copy=False)
+    m = W.m
+    nF, lam = int(s["nF"]), int(s["lam"])
+    F = np.asarray(s["F"][:nF])
+    X = P.features(p, np.asarray(s["x"])[F], np.asarray(s["thr"])[np.asarray(s["cell"])[F] >> 6])
+    o, _ = P.forward(prop["params"], X)
+    mean, std = P.head(o, p, m)
+    tol_o = 2.0 ** -6 * P.abs_scale(prop["params"], X) + 1e-6
+    c, r = P.control_box(p, m)
+    heads = G.head_rows(nF).astype(np.float64)
+    dm = np.abs(heads[:, :m] - mean) - (r * tol_o[:, :m] + 1e-6 * r)
+    ds = np.abs(heads[:, 4:4 + m] - std) - (r * tol_o[:, 4:4 + m] + 1e-6 * r)
+    if np.any(dm > 0) or np.any(ds > 0):
+        e = int(np.nonzero(np.any(dm > 0, axis=1) | np.any(ds > 0, axis=1))[0][0])
+        rep.fail(f"it{it}: proposal head of frontier entry {e} differs "
+                 f"(gpu {heads[e]}, mean {mean[e]}, std {std[e]})")
+        return
+    seed = int(p["seed"])
+    itp = int(s["it"])   # the Philox counter's iteration word
+    thr = P.mix_threshold(prop["mix"])
+    gu = np.asarray(tr["u"], np.float64)
+    for k in range(nF * lam):
+        e, smp = divmod(k, lam)
+        f = int(F[e])
+        if not P.is_learned(seed, itp, f, smp, thr):
+            ref = P.uniform_control(seed, itp, f, smp, p, m)
+            if not np.array_equal(np.asarray(tr["u"][k][:m], np.float32).view(np.uint32), ref.view(np.uint32)):
+                rep.fail(f"it{it}: lane {k} uniform control bits differ")
+            continue
+        rep.learned_lanes += 1
+        z = P.gaussians(seed, itp, f, smp)[:m]
+        lo = np.asarray(p["u_lo"], np.float32)[:m].astype(np.float64)
+        hi = np.asarray(p["u_hi"], np.float32)[:m].astype(np.float64)
+        u_ref = np.clip(mean[e] + std[e] * z, lo, hi)
+        bound = r * (tol_o[e, :m] + np.abs(z) * tol_o[e, 4:4 + m]) + 1e-5 * r * (1.0 + np.abs(z))
+        if np.any(np.abs(gu[k, :m] - u_ref) > bound):
+            rep.fail(f"it{it}: lane {k} learned control {gu[k, :m]} vs {u_ref} (bound {bound})")
+
+
 def compare_state(p, W, g, rep, it, where, gpu_prev=None):
     s = W.state()
     N = s["N"]
@@ -189,11 +236,13 @@ def compare_state(p, W, g, rep, it, where, gpu_prev=None):
         rep.fail(f"it{it} {where}: stored states rel err {e:.2e}")
 
 
-def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=None):
+def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=None, proposal=None):
     """Run `iterations` lock-step iterations from the root.  reload=True loads
     the oracle's state into the GPU before every iteration (identical inputs);
     reload=False lets the GPU continue from its own state (exercises the fused
-    next-frontier pass)."""
+    next-frontier pass).  proposal: dict(params (FP64 array of FP32 values),
+    packed (device tensor from mlp_pack), mix) runs the learned proposal; the
+    oracle then checks the draws and adopts the GPU's controls."""
     from paper_2409_06807_amd import Planner
     import torch
 
@@ -202,6 +251,8 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
     if G is None:
         G = Planner(p, device=device)
     trace = G.trace_buffer()
+    if proposal is not None:
+        G.set_proposal(proposal["packed"], proposal["mix"])
     gpu_prev = None
     for it in range(iterations):
         if W.state(copy=False)["goal_id"] >= 0:
@@ -221,10 +272,17 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
                 rep.fail(f"it{it}: termination code gpu {gs['done_code']} oracle {st}")
             rep.final_status = st
             break
-        recs = W.expand_all()
-        G.expand(trace)
-        torch.cuda.synchronize()
-        tr = G.trace(trace, len(recs))
+        if proposal is None:
+            recs = W.expand_all()
+            G.expand(trace)
+            torch.cuda.synchronize()
+            tr = G.trace(trace, len(recs))
+        else:
+            G.expand(trace)
+            torch.cuda.synchronize()
+            tr = G.trace(trace, W.num_lanes())
+            check_proposal(p, W, G, tr, proposal, rep, it)
+            recs = W.expand_all(controls=np.pad(tr["u"][:, :W.m], ((0, 0), (0, 4 - W.m))))
         merged = compare_expansion(p, W, recs, tr, rep, it, gpu_prev)
         W.apply(merged)
         g = G.copy_tree()
