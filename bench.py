@@ -172,6 +172,85 @@ def expand_only(G, p, dyn, integ, reps):
         "frac": tf / PEAK_FP32_TFLOPS}))
 
 
+TRAIN_SEED0 = 1000  # training queries use planner seeds disjoint from the evaluated ones
+
+
+def learned_leg(G, p, steps, warmup, n_paths, train_steps, batch, lr, mix):
+    """Learned proposal against the uniform planner: log the solution paths
+    of uniform queries on training seeds, train the network on the GPU, then
+    time the same evaluation seeds with the learned proposal mixed in."""
+    import torch
+    import paper_2409_06807_amd as kp
+    from paper_2409_06807_amd import SOLVED
+    from workloads import mlp_inputs
+    m = 3 if int(p["dynamics"]) == 0 else 4
+    cap = 64 * n_paths
+    X = torch.zeros((cap, 16), dtype=torch.float32, device="cuda:0")
+    T = torch.zeros((cap, 4), dtype=torch.float32, device="cuda:0")
+    rows = solved_paths = 0
+    t0 = time.perf_counter()
+    for s in range(TRAIN_SEED0, TRAIN_SEED0 + n_paths):
+        G.reset(s)
+        r = G.plan()
+        if r["status"] == SOLVED:
+            rows += G.log_path(r["goal_id"], X, T, rows)
+            solved_paths += 1
+    collect_s = time.perf_counter() - t0
+    params = torch.tensor(mlp_inputs.params(13), dtype=torch.float32, device="cuda:0")
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    pk = torch.empty(kp.MLP_PACKED_BYTES, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = kp.mlp_train(params, m1, m2, pk, X[:rows], T[:rows], m, batch, train_steps, lr, key=5)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3
+    lv = losses.cpu().numpy()
+    G.set_proposal(pk, mix)
+    for s in range(warmup):
+        G.reset(s % max(steps, 1))
+        G.plan()
+    torch.cuda.synchronize()
+    results, per_ms = [], []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        a = time.perf_counter()
+        G.reset(s)
+        results.append(G.plan())
+        per_ms.append((time.perf_counter() - a) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    G.set_profiling(True)
+    for s in range(steps):
+        G.reset(s)
+        G.plan()
+    kt = G.kernel_times()
+    G.set_profiling(False)
+    G.set_proposal(None)
+    solved = [ms for ms, r in zip(per_ms, results) if r["status"] == SOLVED]
+    n_head, head_ms = kt["proposal"]
+    return {
+        "mix": mix,
+        "median_tts_ms": statistics.median(solved) if solved else None,
+        "mean_tts_ms": statistics.mean(solved) if solved else None,
+        "p10_tts_ms": percentile(solved, 10),
+        "p90_tts_ms": percentile(solved, 90),
+        "success_rate": len(solved) / len(results),
+        "valid_expansions_per_s": sum(r["valid_total"] for r in results) / elapsed,
+        "iterations": [r["iterations"] for r in results],
+        "tree_nodes": [r["n_nodes"] for r in results],
+        "kernel_ms_per_query": {k: v[1] / max(steps, 1) for k, v in kt.items()},
+        "proposal_launches": n_head,
+        "proposal_ms_per_launch": head_ms / n_head if n_head else None,
+        "training": {
+            "seeds": f"{TRAIN_SEED0}..{TRAIN_SEED0 + n_paths - 1} (uniform planner)",
+            "solved_paths": solved_paths, "rows": rows, "steps": train_steps, "batch": batch,
+            "lr": lr, "loss_first10": float(lv[:10].mean()), "loss_last10": float(lv[-10:].mean()),
+            "collect_s": collect_s, "train_ms": train_ms,
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +266,12 @@ def main():
                     help="instead of whole queries, time the propagate kernel on the largest "
                          "iteration of one query (the tree reloaded before each repetition) and "
                          "print that measurement")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal leg")
+    ap.add_argument("--learned-paths", type=int, default=256,
+                    help="uniform training queries whose solution paths are logged")
+    ap.add_argument("--learned-train-steps", type=int, default=1000)
+    ap.add_argument("--learned-mix", type=float, default=0.7)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (a kernel of known "
                          "traffic, used to calibrate hardware byte counters)")
@@ -303,6 +388,12 @@ def main():
         "kernel_ms": {k: v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},
     }
+    if not args.no_learned:
+        lrn = learned_leg(G, p, args.steps, args.warmup, args.learned_paths,
+                          args.learned_train_steps, 512, 3e-3, args.learned_mix)
+        um, lm = line["median_tts_ms"], lrn["median_tts_ms"]
+        lrn["median_tts_ratio_learned_over_uniform"] = lm / um if (um and lm) else None
+        line["learned"] = lrn
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_budget_s)
     print(json.dumps(line))

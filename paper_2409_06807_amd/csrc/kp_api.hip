@@ -395,7 +395,8 @@ kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
 kp_status do_head(kp_problem* h, long long nf_ub) {
   if (h->prm.mix_thr == 0ull) return KP_OK;
   h->ctl_fresh = false;
-  const long long blocks = (nf_ub + 63) / 64;
+  const long long rpb = mlp_head_rows_per_block();
+  const long long blocks = (nf_ub + rpb - 1) / rpb;
   int grid = (int)(blocks < h->grid_head_max ? blocks : h->grid_head_max);
   if (grid < 1) grid = 1;
   hipError_t e = launch_mlp_head(h->env_dev, grid, h->stream, prof_slot(h, 6));

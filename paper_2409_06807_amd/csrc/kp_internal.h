@@ -173,6 +173,7 @@ hipError_t launch_mlp_forward(const uint4* packed, const float* x, int32_t rows,
                               hipStream_t s);
 hipError_t launch_mlp_head(const Env* env, int grid, hipStream_t s, Timing t);
 int mlp_head_grid_max(int cu_count);
+int mlp_head_rows_per_block();
 hipError_t launch_mlp_grad(const uint4* packed, const float* x, const float* t, int32_t n_rows,
                            int32_t m, int32_t batch, uint64_t key, int32_t step, float* partials,
                            float* loss, hipStream_t s);

@@ -109,11 +109,13 @@ __device__ __forceinline__ float bf16_value(uint32_t bits) { return __uint_as_fl
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 w) { return __builtin_bit_cast(bf16x8, w); }
 __device__ __forceinline__ u32x4 as_u32x4(bf16x8 v) { return __builtin_bit_cast(u32x4, v); }
 
+// eight FP32 values to BF16, round to nearest even (the hardware's packed
+// conversion on gfx950)
 __device__ __forceinline__ bf16x8 pack8(const float* f) {
-  u32x4 w;
+  bf16x8 v;
 #pragma unroll
-  for (int h = 0; h < 4; ++h) w[h] = bf16_bits(f[2 * h]) | (bf16_bits(f[2 * h + 1]) << 16);
-  return as_bf16x8(w);
+  for (int j = 0; j < 8; ++j) v[j] = (__bf16)f[j];
+  return v;
 }
 
 // BF16 relu of accumulator tiles a (slots 0..3) and b (slots 4..7)
@@ -175,6 +177,72 @@ __device__ __forceinline__ void forward_wave(const u32x4* frag, const float* bia
   r.o = o;
 }
 
+// The network on NG groups of 16 rows at once (layer-1 operands xb[0..NG-1]):
+// each weight fragment read from LDS feeds NG products, and layer 2 is
+// computed one pair of output tiles at a time, so only 8 NG accumulators
+// are live.  Raw outputs in o[] (same layout as Fwd::o).
+template <int NG>
+__device__ __forceinline__ void forward_rows(const u32x4* frag, const float* bias,
+                                             const bf16x8* xb, f32x4* o) {
+  const int lane = __lane_id(), g = lane >> 4;
+  bf16x8 h1[NG][4], h2[NG][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const u32x4 A0 = frag[E_F1 + (2 * s) * 64 + lane];
+    const u32x4 A1 = frag[E_F1 + (2 * s + 1) * 64 + lane];
+    f32x4 b0, b1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      b0[q] = bias[16 * (2 * s) + 4 * g + q];
+      b1[q] = bias[16 * (2 * s + 1) + 4 * g + q];
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) h1[k][s] = pack_relu(mfma(A0, xb[k], b0), mfma(A1, xb[k], b1));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2) {
+    f32x4 b0, b1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      b0[q] = bias[kMlpHid + 16 * (2 * s2) + 4 * g + q];
+      b1[q] = bias[kMlpHid + 16 * (2 * s2 + 1) + 4 * g + q];
+    }
+    f32x4 a0[NG], a1[NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      a0[k] = b0;
+      a1[k] = b1;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const u32x4 A0 = frag[E_F2 + ((2 * s2) * 4 + s) * 64 + lane];
+      const u32x4 A1 = frag[E_F2 + ((2 * s2 + 1) * 4 + s) * 64 + lane];
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+        a0[k] = mfma(A0, h1[k][s], a0[k]);
+        a1[k] = mfma(A1, h1[k][s], a1[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) h2[k][s2] = pack_relu(a0[k], a1[k]);
+    // keep the next tile pair's weight loads below this point: hoisting all
+    // of them ahead would need the whole weight set in registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  f32x4 b3;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) b3[q] = g < 2 ? bias[2 * kMlpHid + 4 * g + q] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < NG; ++k) o[k] = b3;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const u32x4 A = frag[E_F3 + s * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) o[k] = mfma(A, h2[k][s], o[k]);
+  }
+}
+
 // raw feature k of a tree node: state, P_accept of its region, goal offset
 __device__ __forceinline__ float raw_feature(const Params& p, const Dev& d, int32_t node, int k,
                                              float pacc) {
@@ -228,15 +296,35 @@ __device__ __forceinline__ bf16x8 row_operand(const float* x, int32_t row, bool 
   return pack8(f);
 }
 
-// forward-pass weights and biases into LDS
+// forward-pass weights and biases into LDS.  Every load of a thread is
+// issued before its first store, so the copy costs one memory latency
+// rather than one per entry.
+template <int BLOCK>
 __device__ __forceinline__ void stage_forward(const u32x4* packed, u32x4* sfrag, float* sbias) {
-  for (int k = threadIdx.x; k < E_FWD; k += blockDim.x) sfrag[k] = packed[k];
+  constexpr int kPer = (E_FWD + BLOCK - 1) / BLOCK;
+  u32x4 v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = (int)threadIdx.x + i * BLOCK;
+    if (k < E_FWD) v[i] = packed[k];
+  }
   const float* b = reinterpret_cast<const float*>(packed + E_END);
-  for (int k = threadIdx.x; k < N_BIAS; k += blockDim.x) sbias[k] = b[k];
+  const float bv = (int)threadIdx.x < N_BIAS ? b[threadIdx.x] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = (int)threadIdx.x + i * BLOCK;
+    if (k < E_FWD) sfrag[k] = v[i];
+  }
+  if ((int)threadIdx.x < N_BIAS) sbias[threadIdx.x] = bv;
   __syncthreads();
 }
 
-constexpr int kMlpBlock = 256;  // 4 waves of 16 rows each per pass
+constexpr int kMlpBlock = 256;   // training: 4 waves of 16 rows (one 64-row block)
+constexpr int kInfBlock = 512;   // inference: 8 waves (2 per SIMD) share one LDS copy
+static_assert(kInfBlock >= 264, "one bias per thread when staging");
+constexpr int kInfWaves = kInfBlock / 64;
+constexpr int kInfNG = 4;        // 16-row groups per wave pass
+constexpr int kInfRows = 16 * kInfNG;  // rows per wave pass
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ prm,
@@ -261,29 +349,46 @@ __global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ prm,
   }
 }
 
-__global__ __launch_bounds__(kMlpBlock) void k_mlp_forward(const u32x4* __restrict__ packed,
+__global__ __launch_bounds__(kInfBlock) void k_mlp_forward(const u32x4* __restrict__ packed,
                                                            const float* __restrict__ x,
                                                            int32_t rows, float* __restrict__ out) {
   __shared__ u32x4 sfrag[E_FWD];
   __shared__ float sbias[N_BIAS];
-  const int groups = (rows + 15) / 16;
-  if ((int)blockIdx.x * 4 >= groups) return;
-  stage_forward(packed, sfrag, sbias);
+  const int passes = (rows + kInfRows - 1) / kInfRows;
+  if ((int)blockIdx.x * kInfWaves >= passes) return;
   const int wave = threadIdx.x >> 6, lane = __lane_id(), g = lane >> 4;
-  for (int q = blockIdx.x * 4 + wave; q < groups; q += gridDim.x * 4) {
-    const int32_t row = q * 16 + (lane & 15);
-    const bool valid = row < rows;
-    Fwd r;
-    forward_wave(sfrag, sbias, row_operand(x, row, valid), r);
-    if (valid && g < 2)
-      reinterpret_cast<float4*>(out + (size_t)row * kMlpOut)[g] =
-          make_float4(r.o[0], r.o[1], r.o[2], r.o[3]);
+  // the first pass's inputs load while the weights are staged
+  bf16x8 xb[kInfNG];
+  int q = blockIdx.x * kInfWaves + wave;
+#pragma unroll
+  for (int k = 0; k < kInfNG; ++k) {
+    const int32_t row = q * kInfRows + 16 * k + (lane & 15);
+    xb[k] = row_operand(x, row, row < rows);
+  }
+  stage_forward<kInfBlock>(packed, sfrag, sbias);
+  for (; q < passes; q += gridDim.x * kInfWaves) {
+    if (q != (int)blockIdx.x * kInfWaves + wave) {
+#pragma unroll
+      for (int k = 0; k < kInfNG; ++k) {
+        const int32_t row = q * kInfRows + 16 * k + (lane & 15);
+        xb[k] = row_operand(x, row, row < rows);
+      }
+    }
+    f32x4 o[kInfNG];
+    forward_rows<kInfNG>(sfrag, sbias, xb, o);
+#pragma unroll
+    for (int k = 0; k < kInfNG; ++k) {
+      const int32_t row = q * kInfRows + 16 * k + (lane & 15);
+      if (row < rows && g < 2)
+        reinterpret_cast<float4*>(out + (size_t)row * kMlpOut)[g] =
+            make_float4(o[k][0], o[k][1], o[k][2], o[k][3]);
+    }
   }
 }
 
 // Per frontier entry e (the layout the expansion lanes index by e = lane /
 // lambda): Gaussian mean (4 floats) and standard deviation (4 floats).
-__global__ __launch_bounds__(kMlpBlock) void k_mlp_head(const Env* __restrict__ env) {
+__global__ __launch_bounds__(kInfBlock) void k_mlp_head(const Env* __restrict__ env) {
   __shared__ u32x4 sfrag[E_FWD];
   __shared__ float sbias[N_BIAS];
   const Params& p = env->p;
@@ -291,28 +396,48 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_head(const Env* __restrict__ 
   const Ctl* c = d.ctl;
   if (c->done) return;
   const int32_t nF = c->nF, f_expl = c->f_expl, f_base = c->f_base;
-  const int groups = (nF + 15) / 16;
-  if ((int)blockIdx.x * 4 >= groups) return;
-  stage_forward(reinterpret_cast<const u32x4*>(d.mlp), sfrag, sbias);
+  const int passes = (nF + kInfRows - 1) / kInfRows;
+  if ((int)blockIdx.x * kInfWaves >= passes) return;
   const int wave = threadIdx.x >> 6, lane = __lane_id(), g = lane >> 4;
   const int m = p.m;
-  for (int q = blockIdx.x * 4 + wave; q < groups; q += gridDim.x * 4) {
-    const int32_t e = q * 16 + (lane & 15);
+  // the first pass's node features load while the weights are staged
+  bf16x8 xb[kInfNG];
+  int q = blockIdx.x * kInfWaves + wave;
+#pragma unroll
+  for (int k = 0; k < kInfNG; ++k) {
+    const int32_t e = q * kInfRows + 16 * k + (lane & 15);
     const bool valid = e < nF;
     const int32_t node = valid ? frontier_node(d.F, e, f_expl, f_base) : 0;
-    Fwd r;
-    forward_wave(sfrag, sbias, node_operand(p, d, node, valid), r);
-    if (valid && g < 2) {
-      float v[4];
+    xb[k] = node_operand(p, d, node, valid);
+  }
+  stage_forward<kInfBlock>(reinterpret_cast<const u32x4*>(d.mlp), sfrag, sbias);
+  for (; q < passes; q += gridDim.x * kInfWaves) {
+    if (q != (int)blockIdx.x * kInfWaves + wave) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float lo = p.u_lo[j], hi = p.u_hi[j];
-        const float ctr = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
-        if (j >= m) v[j] = 0.0f;
-        else if (g == 0) v[j] = ctr + half * tanhf(r.o[j]);
-        else v[j] = half * expf(fminf(fmaxf(r.o[j], kLsMin), kLsMax));
+      for (int k = 0; k < kInfNG; ++k) {
+        const int32_t e = q * kInfRows + 16 * k + (lane & 15);
+        const bool valid = e < nF;
+        const int32_t node = valid ? frontier_node(d.F, e, f_expl, f_base) : 0;
+        xb[k] = node_operand(p, d, node, valid);
       }
-      reinterpret_cast<float4*>(d.head + (size_t)e * 8)[g] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    f32x4 o[kInfNG];
+    forward_rows<kInfNG>(sfrag, sbias, xb, o);
+#pragma unroll
+    for (int k = 0; k < kInfNG; ++k) {
+      const int32_t e = q * kInfRows + 16 * k + (lane & 15);
+      if (e < nF && g < 2) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float lo = p.u_lo[j], hi = p.u_hi[j];
+          const float ctr = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
+          if (j >= m) v[j] = 0.0f;
+          else if (g == 0) v[j] = ctr + half * tanhf(o[k][j]);
+          else v[j] = half * expf(fminf(fmaxf(o[k][j], kLsMin), kLsMax));
+        }
+        reinterpret_cast<float4*>(d.head + (size_t)e * 8)[g] = make_float4(v[0], v[1], v[2], v[3]);
+      }
     }
   }
 }
@@ -592,20 +717,21 @@ hipError_t launch_mlp_pack(const float* params, uint4* packed, hipStream_t s) {
 
 hipError_t launch_mlp_forward(const uint4* packed, const float* x, int32_t rows, float* out,
                               hipStream_t s) {
-  const int groups = (rows + 15) / 16;
-  int grid = (groups + 3) / 4;
+  const int passes = (rows + kInfRows - 1) / kInfRows;
+  int grid = (passes + kInfWaves - 1) / kInfWaves;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kMlpBlock), 0, s,
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kInfBlock), 0, s,
                      reinterpret_cast<const u32x4*>(packed), x, rows, out);
   return hipGetLastError();
 }
 
-int mlp_head_grid_max(int cu_count) { return 2 * cu_count; }
+int mlp_head_rows_per_block() { return kInfRows * kInfWaves; }
+int mlp_head_grid_max(int cu_count) { return cu_count; }
 
 hipError_t launch_mlp_head(const Env* env, int grid, hipStream_t s, Timing t) {
   if (grid < 1) grid = 1;
-  hipExtLaunchKernelGGL(k_mlp_head, dim3(grid), dim3(kMlpBlock), 0, s, t.start, t.stop, 0, env);
+  hipExtLaunchKernelGGL(k_mlp_head, dim3(grid), dim3(kInfBlock), 0, s, t.start, t.stop, 0, env);
   return hipGetLastError();
 }
 
