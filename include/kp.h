@@ -364,6 +364,49 @@ kp_status kp_set_proposal(kp_problem* h, const void* dev_packed, float* dev_head
 kp_status kp_log_path(kp_problem* h, int32_t node, float* dev_x, float* dev_t, int32_t cap_rows,
                       int32_t row0, int32_t* n_rows);
 
+/* ---------------------------------------------------------------------------
+ * Batched planning
+ *
+ * Many independent problems advance together: every iteration kernel is
+ * launched once for the whole batch, with one grid row per problem, and a
+ * batch of iterations between two status reads can be replayed from a
+ * captured HIP graph.  Each problem's work and result are exactly those of
+ * kp_plan on that problem alone (the kernels' results do not depend on grid
+ * shapes).  The problems must share dynamics and integrator; each must be
+ * between iterations (after create, reset or kp_update_tree).
+ * ---------------------------------------------------------------------------*/
+typedef struct kp_batch kp_batch;
+
+typedef struct {
+  int32_t iters_per_sync;   /* iterations enqueued between status reads, 1..64 */
+  int32_t use_graph;        /* 1: replay a captured HIP graph of those iterations */
+  int32_t prop_blocks;      /* most propagate workgroups per problem and launch (>= 1) */
+  int32_t node_blocks;      /* most commit / node-set workgroups per problem and launch (>= 1) */
+} kp_batch_config;
+
+/* Device workspace of a batch of n problems (the problem table and status). */
+size_t kp_batch_workspace_bytes(int32_t n);
+
+/* problems: n handles (borrowed for the batch's lifetime); dev_workspace:
+ * device memory of kp_batch_workspace_bytes(n) bytes, 256-byte aligned,
+ * borrowed.  The batch launches on a stream of its own (default priority)
+ * after the work already queued on the first problem's stream.  The default
+ * configuration uses the single-problem grid sizes and 8 iterations per read. */
+kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_workspace, size_t bytes,
+                          kp_batch** out);
+kp_status kp_batch_set_config(kp_batch* b, const kp_batch_config* cfg);
+kp_status kp_batch_get_config(const kp_batch* b, kp_batch_config* cfg);
+
+/* Alg. 1's loop for every problem of the batch until each one stops
+ * (goal, full tree, empty frontier, or its own iteration / time budget).
+ * results: n entries; elapsed_ms of entry i is the wall time from the call
+ * until the status read that saw problem i stop.  *batch_ms (nullable): wall
+ * time of the whole call.  Synchronous. */
+kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms);
+
+kp_status kp_batch_destroy(kp_batch* b);
+const char* kp_batch_last_error(const kp_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

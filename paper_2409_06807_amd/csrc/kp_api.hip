@@ -969,4 +969,288 @@ kp_status kp_log_path(kp_problem* h, int32_t node, float* dev_x, float* dev_t, i
   return KP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched planning
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct kp_batch {
+  std::vector<kp_problem*> P;
+  const Env** table = nullptr;        // device: Env* of every problem
+  BatchStatus* st_dev = nullptr;      // device: status of every problem
+  BatchStatus* st_host = nullptr;     // pinned mirror
+  hipStream_t stream = nullptr;       // the batch's own stream
+  hipStream_t user_stream = nullptr;  // the problems' stream
+  int dyn = 0, integ = 0, n_obs_max = 0;
+  int prop_max = 1, node_max = 1;     // single-problem grid maxima
+  kp_batch_config cfg{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+};
+
+namespace {
+
+size_t batch_table_bytes(int32_t n) { return align_up((size_t)n * sizeof(void*), kAlign); }
+
+kp_status bfail(kp_batch* b, kp_status st, const std::string& msg) {
+  if (b) b->err = msg;
+  return st;
+}
+kp_status bhip(kp_batch* b, hipError_t e, const char* what) {
+  return bfail(b, KP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void drop_graph(kp_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// one iteration for every problem: grids from per-problem bounds (capped)
+hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_ub) {
+  const int n = (int)b->P.size();
+  long long t = (lanes_ub + kPropBlock - 1) / kPropBlock;
+  const int gp = (int)(t < b->cfg.prop_blocks ? t : b->cfg.prop_blocks);
+  t = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
+  const int nc = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
+  t = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
+  const int nn = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
+  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->table, n, b->n_obs_max,
+                                        gp < 1 ? 1 : gp, b->stream);
+  if (e == hipSuccess) e = launch_post_batch(b->table, n, nc, nn, b->stream);
+  return e;
+}
+
+kp_status batch_status(kp_batch* b) {
+  const int n = (int)b->P.size();
+  hipError_t e = launch_batch_status(b->table, n, b->st_dev, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->st_host, b->st_dev, (size_t)n * sizeof(BatchStatus), hipMemcpyDeviceToHost,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bhip(b, e, "batch status");
+  for (int i = 0; i < n; ++i)
+    if (b->st_host[i].err)
+      return bfail(b, KP_E_DEVICE, "device check failed in problem " + std::to_string(i));
+  return KP_OK;
+}
+
+// the graph of cfg.iters_per_sync iterations at the capped grids
+kp_status batch_graph(kp_batch* b) {
+  if (b->exec) return KP_OK;
+  const long long big = (long long)1 << 40;
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bhip(b, e, "graph capture");
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < b->cfg.iters_per_sync && le == hipSuccess; ++k) le = batch_iteration(b, big, big);
+  e = hipStreamEndCapture(b->stream, &b->graph);
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return bhip(b, e, "graph instantiate");
+  }
+  return KP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kp_batch_workspace_bytes(int32_t n) {
+  if (n < 1) return 0;
+  return batch_table_bytes(n) + (size_t)n * sizeof(BatchStatus);
+}
+
+kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_workspace, size_t bytes,
+                          kp_batch** out) {
+  if (!out) return KP_E_ARG;
+  *out = nullptr;
+  if (!problems || n < 1 || n > 65535 || !dev_workspace) return KP_E_ARG;
+  if (bytes < kp_batch_workspace_bytes(n) || (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign))
+    return KP_E_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    if (!problems[i]) return KP_E_ARG;
+    if (problems[i]->desc.dynamics != problems[0]->desc.dynamics ||
+        problems[i]->desc.integrator != problems[0]->desc.integrator)
+      return KP_E_ARG;
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return KP_E_ARG;
+  }
+  kp_batch* b = new (std::nothrow) kp_batch();
+  if (!b) return KP_E_ARG;
+  b->P.assign(problems, problems + n);
+  b->user_stream = problems[0]->stream;
+  b->dyn = problems[0]->desc.dynamics;
+  b->integ = problems[0]->desc.integrator;
+  int prop_max = 1, node_max = 1;
+  for (int i = 0; i < n; ++i) {
+    const kp_problem* h = problems[i];
+    if (h->desc.n_obstacles > b->n_obs_max) b->n_obs_max = h->desc.n_obstacles;
+    if (h->grid_node_max > node_max) node_max = h->grid_node_max;
+    if (h->grid_commit_max > node_max) node_max = h->grid_commit_max;
+  }
+  int bp = 1;
+  occupancy_propagate(b->dyn, b->integ, b->n_obs_max, &bp);
+  prop_max = bp * problems[0]->cu_count;
+  b->prop_max = prop_max;
+  b->node_max = node_max;
+  b->cfg.iters_per_sync = 8;
+  b->cfg.use_graph = 0;
+  b->cfg.prop_blocks = prop_max;
+  b->cfg.node_blocks = node_max;
+  char* base = static_cast<char*>(dev_workspace);
+  b->table = reinterpret_cast<const Env**>(base);
+  b->st_dev = reinterpret_cast<BatchStatus*>(base + batch_table_bytes(n));
+  std::vector<const Env*> tab((size_t)n);
+  for (int i = 0; i < n; ++i) tab[(size_t)i] = problems[i]->env_dev;
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->st_host), (size_t)n * sizeof(BatchStatus),
+                      hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->table, tab.data(), (size_t)n * sizeof(void*), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    if (b->st_host) (void)hipHostFree(b->st_host);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return KP_E_DEVICE;
+  }
+  *out = b;
+  return KP_OK;
+}
+
+kp_status kp_batch_set_config(kp_batch* b, const kp_batch_config* cfg) {
+  if (!b || !cfg) return KP_E_ARG;
+  if (cfg->iters_per_sync < 1 || cfg->iters_per_sync > 64 || cfg->prop_blocks < 1 ||
+      cfg->node_blocks < 1 || (cfg->use_graph != 0 && cfg->use_graph != 1))
+    return bfail(b, KP_E_ARG, "kp_batch_set_config: field out of range");
+  b->cfg = *cfg;
+  drop_graph(b);
+  return KP_OK;
+}
+
+kp_status kp_batch_get_config(const kp_batch* b, kp_batch_config* cfg) {
+  if (!b || !cfg) return KP_E_ARG;
+  *cfg = b->cfg;
+  return KP_OK;
+}
+
+kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms) {
+  if (!b || !results) return KP_E_ARG;
+  const int n = (int)b->P.size();
+  for (int i = 0; i < n; ++i)
+    if (b->P[i]->stage != 0)
+      return bfail(b, KP_E_ORDER, "problem " + std::to_string(i) + " is in the middle of an iteration");
+  const auto t0 = std::chrono::steady_clock::now();
+  auto now_ms = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  // order after the work already queued on the problems' stream
+  hipError_t e = hipStreamSynchronize(b->user_stream);
+  if (e != hipSuccess) return bhip(b, e, "problem stream");
+  for (int i = 0; i < n; ++i) b->P[i]->ctl_fresh = false;
+  kp_status st = batch_status(b);
+  if (st != KP_OK) return st;
+  std::vector<uint32_t> it0((size_t)n);
+  std::vector<int> active((size_t)n, 1), stopped_by_host((size_t)n, 0);
+  std::vector<double> t_end((size_t)n, 0.0);
+  std::vector<int> code((size_t)n, KP_TIMEOUT);
+  for (int i = 0; i < n; ++i) it0[(size_t)i] = (uint32_t)b->st_host[i].iters_done;
+  for (;;) {
+    const double ms = now_ms();
+    int n_active = 0;
+    long long min_left = (long long)1 << 40, lanes_ub = 0, nodes_ub = 0, lanes_ub2 = 0, nodes_ub2 = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!active[(size_t)i]) continue;
+      const BatchStatus& s = b->st_host[i];
+      const kp_problem* h = b->P[(size_t)i];
+      const long long done_iters = (long long)(uint32_t)s.iters_done - it0[(size_t)i];
+      if (s.done) {
+        code[(size_t)i] = s.done;
+      } else if (done_iters >= h->desc.max_iters || ms >= h->desc.t_max_ms) {
+        // this problem's own budget: its kernels return at once from now on
+        code[(size_t)i] = KP_TIMEOUT;
+        stopped_by_host[(size_t)i] = 1;
+        e = launch_set_done(h->env_dev, KP_TIMEOUT, b->stream);
+        if (e != hipSuccess) return bhip(b, e, "budget stop");
+      } else {
+        ++n_active;
+        const long long left = h->desc.max_iters - done_iters;
+        if (left < min_left) min_left = left;
+        if (s.lanes > lanes_ub) lanes_ub = s.lanes;
+        if (s.N > nodes_ub) nodes_ub = s.N;
+        const long long cap = h->desc.node_cap;
+        if (cap - s.N > lanes_ub2) lanes_ub2 = cap - s.N;
+        if (cap > nodes_ub2) nodes_ub2 = cap;
+        continue;
+      }
+      active[(size_t)i] = 0;
+      t_end[(size_t)i] = ms;
+    }
+    if (n_active == 0) break;
+    long long len = b->cfg.iters_per_sync;
+    if (len > min_left) len = min_left;
+    if (b->cfg.use_graph && len == b->cfg.iters_per_sync) {
+      if ((st = batch_graph(b)) != KP_OK) return st;
+      e = hipGraphLaunch(b->exec, b->stream);
+      if (e != hipSuccess) return bhip(b, e, "graph launch");
+    } else {
+      for (long long k = 0; k < len; ++k) {
+        // exact sizes for the first iteration after a read, bounds after it
+        e = batch_iteration(b, k == 0 ? lanes_ub : lanes_ub2, k == 0 ? nodes_ub : nodes_ub2);
+        if (e != hipSuccess) return bhip(b, e, "batch launch");
+      }
+    }
+    if ((st = batch_status(b)) != KP_OK) return st;
+  }
+  const double total = now_ms();
+  for (int i = 0; i < n; ++i) {
+    kp_problem* h = b->P[(size_t)i];
+    const BatchStatus& s = b->st_host[i];
+    if (stopped_by_host[(size_t)i]) {
+      // a budget stop is the host's decision, as in kp_plan: the device state
+      // stays resumable
+      e = launch_set_done(h->env_dev, 0, b->stream);
+      if (e != hipSuccess) return bhip(b, e, "budget resume");
+    }
+    kp_plan_result& r = results[i];
+    std::memset(&r, 0, sizeof(r));
+    r.status = code[(size_t)i];
+    r.goal_id = (s.goal_id == kNoGoal) ? -1 : s.goal_id;
+    r.iterations = (int32_t)((uint32_t)s.iters_done - it0[(size_t)i]);
+    r.n_nodes = s.N;
+    r.elapsed_ms = t_end[(size_t)i];
+    r.lanes_total = s.lanes_total;
+    r.valid_total = s.valid_total;
+  }
+  e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bhip(b, e, "batch end");
+  for (int i = 0; i < n; ++i) {
+    kp_plan_result& r = results[i];
+    if (r.goal_id >= 0) {
+      int32_t len = 0;
+      if (kp_get_path(b->P[(size_t)i], r.goal_id, nullptr, 0, &len) == KP_OK) r.path_len = len;
+    }
+  }
+  if (batch_ms) *batch_ms = total;
+  return KP_OK;
+}
+
+kp_status kp_batch_destroy(kp_batch* b) {
+  if (!b) return KP_E_ARG;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  (void)hipHostFree(b->st_host);
+  (void)hipStreamDestroy(b->stream);
+  delete b;
+  return KP_OK;
+}
+
+const char* kp_batch_last_error(const kp_batch* b) { return b ? b->err.c_str() : ""; }
+
 }  // extern "C"

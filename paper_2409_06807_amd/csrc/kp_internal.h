@@ -160,6 +160,18 @@ hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
 hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s, Timing t);
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
+
+// batched planning: one grid row (blockIdx.y) per problem of an Env* table
+struct BatchStatus {
+  int32_t done, N, nF, lanes, iters_done, goal_id, err, pad;
+  unsigned long long lanes_total, valid_total;
+};
+hipError_t launch_propagate_batch(int dyn, int integ, const Env* const* envs, int n, int n_obs_max,
+                                  int grid, hipStream_t s);
+hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
+                             hipStream_t s);
+hipError_t launch_batch_status(const Env* const* envs, int n, BatchStatus* out, hipStream_t s);
+hipError_t launch_set_done(const Env* env, int32_t code, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
 
 // learned proposal (kp_mlp.hip)

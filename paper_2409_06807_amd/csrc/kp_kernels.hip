@@ -680,8 +680,7 @@ __device__ __forceinline__ float box_separation(float lx, float ly, float lz, fl
 }
 
 template <int DYN, int INTEG>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(const Env* __restrict__ env,
-                                                           TraceRec* trace) {
+__device__ __forceinline__ void propagate_body(const Env* __restrict__ env, TraceRec* trace) {
   const Params& p = env->p;
   const Dev& d = env->d;
   constexpr int n = Dim<DYN>::n;
@@ -1399,7 +1398,7 @@ __device__ __forceinline__ void wait_region(Ctl* c, uint32_t epoch) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
+__device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
   static_assert(kCommitBlock == kNodeBlock, "one block shape for every role");
   static_assert(kNodesPerThread == 4, "one flag word and one uint4 of cells per thread");
   const Params& p = env->p;
@@ -1568,6 +1567,57 @@ __global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ e
   }
 }
 
+// One problem per launch, or one problem per grid row (blockIdx.y) of a
+// batched launch over a table of problems; the work of each problem is the
+// same either way.
+template <int DYN, int INTEG>
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(
+    const Env* __restrict__ env, TraceRec* trace) {
+  propagate_body<DYN, INTEG>(env, trace);
+}
+template <int DYN, int INTEG>
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate_batch(
+    const Env* const* __restrict__ envs) {
+  propagate_body<DYN, INTEG>(envs[blockIdx.y], nullptr);
+}
+
+__global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
+  post_body(env, nc);
+}
+__global__ __launch_bounds__(kCommitBlock) void k_post_batch(const Env* const* __restrict__ envs, int nc) {
+  post_body(envs[blockIdx.y], nc);
+}
+
+// compact status of every problem of a batch, for one host read
+__global__ void k_batch_status(const Env* const* __restrict__ envs, int n, BatchStatus* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Ctl* c = envs[i]->d.ctl;
+  BatchStatus s;
+  s.done = c->done;
+  s.N = c->N;
+  s.nF = c->nF;
+  s.lanes = c->lanes;
+  s.iters_done = (int32_t)c->iters_done;
+  s.goal_id = c->goal_id;
+  s.err = (int32_t)c->err;
+  s.pad = 0;
+  unsigned long long l = 0, v = 0;
+  for (int g = 0; g < kGroups; ++g) {
+    l += c->tot[g].lanes;
+    v += c->tot[g].valid;
+  }
+  s.lanes_total = l;
+  s.valid_total = v;
+  out[i] = s;
+}
+
+// ends (code > 0) or resumes (code 0) a problem's iterations: every kernel of
+// an iteration returns at once while done != 0
+__global__ void k_set_done(const Env* __restrict__ env, int32_t code) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) env->d.ctl->done = code;
+}
+
 // ---------------------------------------------------------------------------
 // k_path: root-to-node walk along parent links
 // ---------------------------------------------------------------------------
@@ -1654,6 +1704,45 @@ hipError_t launch_region(const Env* env, hipStream_t s, Timing t) {
 
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t) {
   hipExtLaunchKernelGGL(k_nodesets, dim3(grid), dim3(kNodeBlock), 0, s, t.start, t.stop, 0, env);
+  return hipGetLastError();
+}
+
+template <int DYN, int INTEG>
+static hipError_t launch_prop_batch_t(const Env* const* envs, int n, int n_obs_max, int grid,
+                                      hipStream_t s) {
+  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG>), dim3(grid, n), dim3(kPropBlock),
+                     (uint32_t)propagate_lds_bytes(n_obs_max), s, envs);
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate_batch(int dyn, int integ, const Env* const* envs, int n, int n_obs_max,
+                                  int grid, hipStream_t s) {
+  if (grid < 1) grid = 1;
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
+    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_EULER>(envs, n, n_obs_max, grid, s);
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
+    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_RK4>(envs, n, n_obs_max, grid, s);
+  if (dyn == KP_DYN_QUAD12 && integ == KP_INT_EULER)
+    return launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER>(envs, n, n_obs_max, grid, s);
+  return launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4>(envs, n, n_obs_max, grid, s);
+}
+
+hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
+                             hipStream_t s) {
+  if (n_commit < 1) n_commit = 1;
+  if (n_nodes < 1) n_nodes = 1;
+  hipLaunchKernelGGL(k_post_batch, dim3(1 + n_commit + n_nodes, n), dim3(kCommitBlock), 0, s, envs,
+                     n_commit);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const Env* const* envs, int n, BatchStatus* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_status, dim3((n + 255) / 256), dim3(256), 0, s, envs, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_done(const Env* env, int32_t code, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, s, env, code);
   return hipGetLastError();
 }
 

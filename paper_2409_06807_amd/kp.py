@@ -32,6 +32,8 @@ EXPORTED = [
     "kp_copy_tree", "kp_load_tree", "kp_get_path", "kp_set_profiling", "kp_kernel_times",
     "kp_status_str", "kp_last_error", "kp_mlp_pack", "kp_mlp_forward", "kp_mlp_grad",
     "kp_mlp_adam", "kp_mlp_train", "kp_set_proposal", "kp_log_path",
+    "kp_batch_workspace_bytes", "kp_batch_create", "kp_batch_set_config", "kp_batch_get_config",
+    "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error",
 ]
 
 
@@ -56,6 +58,11 @@ class PlanResult(C.Structure):
         ("n_nodes", C.c_int32), ("path_len", C.c_int32), ("pad", C.c_int32),
         ("elapsed_ms", C.c_double), ("lanes_total", C.c_uint64), ("valid_total", C.c_uint64),
     ]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("iters_per_sync", C.c_int32), ("use_graph", C.c_int32),
+                ("prop_blocks", C.c_int32), ("node_blocks", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -149,6 +156,18 @@ def load_library():
     for name in ("kp_mlp_pack", "kp_mlp_forward", "kp_mlp_grad", "kp_mlp_adam", "kp_mlp_train",
                  "kp_set_proposal", "kp_log_path"):
         getattr(L, name).restype = C.c_int
+    L.kp_batch_workspace_bytes.argtypes = [C.c_int32]
+    L.kp_batch_workspace_bytes.restype = C.c_size_t
+    L.kp_batch_create.argtypes = [P, C.c_int32, P, C.c_size_t, C.POINTER(P)]
+    L.kp_batch_set_config.argtypes = [P, C.POINTER(BatchConfig)]
+    L.kp_batch_get_config.argtypes = [P, C.POINTER(BatchConfig)]
+    L.kp_batch_plan.argtypes = [P, P, C.POINTER(C.c_double)]
+    L.kp_batch_destroy.argtypes = [P]
+    for name in ("kp_batch_create", "kp_batch_set_config", "kp_batch_get_config", "kp_batch_plan",
+                 "kp_batch_destroy"):
+        getattr(L, name).restype = C.c_int
+    L.kp_batch_last_error.argtypes = [P]
+    L.kp_batch_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -467,3 +486,66 @@ def mlp_train(params, m1, m2, packed, X, T, n_ctrl: int, batch: int, steps: int,
         int(key) & ((1 << 64) - 1), C.c_void_p(partials.data_ptr()), C.c_void_p(loss.data_ptr()),
         _stream_ptr(X)), "kp_mlp_train")
     return loss[:steps].sum(dim=1)
+
+
+# ---------------------------------------------------------------------------
+# batched planning
+# ---------------------------------------------------------------------------
+class Batch:
+    """Planners advanced together by kp_batch_plan (one launch per kernel and
+    iteration for the whole batch).  The planners stay usable on their own."""
+
+    def __init__(self, planners):
+        import torch
+        self.lib = load_library()
+        self.planners = list(planners)
+        n = len(self.planners)
+        nbytes = int(self.lib.kp_batch_workspace_bytes(n))
+        if nbytes == 0:
+            raise KPError(E_ARG, "empty batch")
+        dev = self.planners[0].device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        hs = (C.c_void_p * n)(*[p.h for p in self.planners])
+        h = C.c_void_p()
+        st = self.lib.kp_batch_create(hs, n, C.c_void_p(self.workspace.data_ptr()), nbytes, C.byref(h))
+        if st != OK:
+            raise KPError(st, self.lib.kp_status_str(st).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != OK:
+            msg = self.lib.kp_batch_last_error(self.h).decode() if self.h else ""
+            raise KPError(st, f"{self.lib.kp_status_str(st).decode()} {msg}")
+
+    def config(self) -> dict:
+        c = BatchConfig()
+        self._check(self.lib.kp_batch_get_config(self.h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in BatchConfig._fields_}
+
+    def set_config(self, **kw):
+        cur = self.config()
+        cur.update(kw)
+        c = BatchConfig(**{k: int(v) for k, v in cur.items()})
+        self._check(self.lib.kp_batch_set_config(self.h, C.byref(c)))
+
+    def plan(self):
+        """Returns (per-problem result dicts, batch wall time in ms)."""
+        n = len(self.planners)
+        res = (PlanResult * n)()
+        ms = C.c_double(0.0)
+        self._check(self.lib.kp_batch_plan(self.h, res, C.byref(ms)))
+        out = [dict(status=r.status, goal_id=r.goal_id, iterations=r.iterations, n_nodes=r.n_nodes,
+                    path_len=r.path_len, elapsed_ms=r.elapsed_ms, lanes_total=int(r.lanes_total),
+                    valid_total=int(r.valid_total)) for r in res]
+        return out, ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.kp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

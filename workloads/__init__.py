@@ -16,6 +16,7 @@ from .scenes import (  # noqa: F401
     problem_c5,
     problem_small_di,
     problem_small_quad,
+    problem_batch,
     random_boxes,
     forest,
     building,

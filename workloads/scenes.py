@@ -291,3 +291,43 @@ def problem_small_quad(seed=0, scene_seed=12, n_obs=60, cap=8192, lambda_max=32,
     p["name"] = "small-quad12"
     p.update(kw)
     return p
+
+
+def problem_batch(n=256, batch_seed=3, dynamics=DI6, obs_range=(10, 1536),
+                  cap_range=(16384, 1048576), min_sep=50.0, occupancy=0.03, **kw):
+    """Independent queries of uneven size for batched planning.  Query k has
+    its own generator PCG64([batch_seed, k]): an obstacle count and a node cap
+    drawn log-uniformly from obs_range and cap_range, box sides around
+    s = (occupancy * 100^3 / count)^(1/3) (per axis U[s/2, 3s/2], so the
+    occupied volume stays near `occupancy` whatever the count), and a start
+    and a goal centre uniform in [5, 95]^3 at least min_sep apart, the start
+    at rest.  Double integrator (c1 dynamics, 8^3 regions) or quadcopter (c2
+    dynamics, 16^3 regions); lambda_max 4; planner seed k."""
+    out = []
+    for k in range(n):
+        rng = np.random.Generator(np.random.PCG64([batch_seed, k]))
+        n_obs = int(round(np.exp(rng.uniform(np.log(obs_range[0]), np.log(obs_range[1])))))
+        cap = int(round(np.exp(rng.uniform(np.log(cap_range[0]), np.log(cap_range[1])))))
+        while True:
+            start = rng.uniform(5.0, 95.0, size=3)
+            goal = rng.uniform(5.0, 95.0, size=3)
+            if np.linalg.norm(goal - start) >= min_sep:
+                break
+        s = (occupancy * W_HI ** 3 / n_obs) ** (1.0 / 3.0)
+        start = [float(v) for v in _f32(start)]
+        goal = [float(v) for v in _f32(goal)]
+        obs = random_boxes(int(rng.integers(1 << 31)), n_obs, 0.5 * s, 1.5 * s, start, goal, 5.0)
+        if dynamics == DI6:
+            p = _base(DI6, EULER, 0.1, 10)
+            p.update(_di_fields(start + [0.0] * 3))
+            grid = (8, 8, 8)
+        else:
+            p = _base(QUAD12, RK4, 0.02, 20)
+            p.update(_quad_fields(start + [0.0] * 9))
+            grid = (16, 16, 16)
+        p.update(obstacles=obs, goal_center=_f32(goal), goal_radius=f32(5.0))
+        p.update(_planner_fields(grid, 4, cap, 4, k))
+        p["name"] = f"c3-batch-{'di6' if dynamics == DI6 else 'quad12'}-q{k}"
+        p.update(kw)
+        out.append(p)
+    return out
