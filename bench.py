@@ -251,6 +251,62 @@ def learned_leg(G, p, steps, warmup, n_paths, train_steps, batch, lr, mix):
     }
 
 
+def batched_leg(n_queries, batch_seed=3):
+    """Batched planning of uneven queries against planning them one by one:
+    the same queries and seeds, identical per-query results required."""
+    import tempfile
+    from paper_2409_06807_amd import Planner, Batch, SOLVED, TREE_FULL, autotune
+    from workloads import problem_batch
+    ps = problem_batch(n=n_queries, batch_seed=batch_seed)
+    planners = [Planner(p) for p in ps]
+
+    def reset():
+        for G, p in zip(planners, ps):
+            G.reset(p["seed"])
+
+    seq_ms, seq = [], []
+    for rep in range(2):   # the first pass warms every handle up
+        seq_ms, seq = [], []
+        t0 = time.perf_counter()
+        for G, p in zip(planners, ps):
+            a = time.perf_counter()
+            G.reset(p["seed"])
+            seq.append(G.plan())
+            seq_ms.append((time.perf_counter() - a) * 1e3)
+        seq_total = (time.perf_counter() - t0) * 1e3
+    B = Batch(planners)
+    keys = ("status", "goal_id", "iterations", "n_nodes", "lanes_total", "valid_total")
+
+    def run():
+        t0 = time.perf_counter()
+        reset()
+        res, bms = B.plan()
+        total = (time.perf_counter() - t0) * 1e3
+        same = all(r[k] == s[k] for s, r in zip(seq, res) for k in keys)
+        return dict(total_ms=total, batch_ms=bms,
+                    median_completion_ms=statistics.median(r["elapsed_ms"] for r in res),
+                    identical_to_sequential=same)
+
+    run()
+    default = dict(config=B.config(), **run())
+    cfg, table = autotune.tune(B, reset, autotune.signature(ps, "mi355x"),
+                               cache_path=tempfile.mktemp(suffix=".json"))
+    tuned = dict(config=cfg, **run())
+    B.close()
+    st = [r["status"] for r in seq]
+    return {
+        "workload": f"c3-batch-di6: {n_queries} double-integrator queries, boxes log-uniform in "
+                    "[10, 1536], caps log-uniform in [16k, 1M], start/goal >= 50 apart",
+        "queries": n_queries, "solved": st.count(SOLVED), "tree_full": st.count(TREE_FULL),
+        "sequential": {"total_ms": seq_total, "median_query_ms": statistics.median(seq_ms),
+                       "queries_per_s": n_queries / (seq_total * 1e-3)},
+        "batched_default": default,
+        "batched_tuned": dict(tuned, queries_per_s=n_queries / (tuned["total_ms"] * 1e-3),
+                              candidates=len(table)),
+        "speedup_total_tuned": seq_total / tuned["total_ms"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +328,8 @@ def main():
                     help="uniform training queries whose solution paths are logged")
     ap.add_argument("--learned-train-steps", type=int, default=1000)
     ap.add_argument("--learned-mix", type=float, default=0.7)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-planning leg")
+    ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (a kernel of known "
                          "traffic, used to calibrate hardware byte counters)")
@@ -394,6 +452,8 @@ def main():
         um, lm = line["median_tts_ms"], lrn["median_tts_ms"]
         lrn["median_tts_ratio_learned_over_uniform"] = lm / um if (um and lm) else None
         line["learned"] = lrn
+    if not args.no_batched:
+        line["batched"] = batched_leg(args.batch_queries)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_budget_s)
     print(json.dumps(line))

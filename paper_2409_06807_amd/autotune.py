@@ -40,7 +40,7 @@ def candidates(default: dict) -> list:
     out = []
     for ips in (4, 8, 16):
         for graph in (0, 1):
-            for div in (1, 4, 16):
+            for div in (1, 4, 16, 64):
                 out.append(dict(iters_per_sync=ips, use_graph=graph,
                                 prop_blocks=max(1, default["prop_blocks"] // div),
                                 node_blocks=max(1, default["node_blocks"] // div)))

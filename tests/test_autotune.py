@@ -37,8 +37,8 @@ def test_tune_picks_fastest_and_caches(tmp_path):
     path = str(tmp_path / "cache.json")
     b = FakeBatch()
     cfg, table = autotune.tune(b, lambda: None, "sig-a", cache_path=path)
-    assert cfg == dict(iters_per_sync=8, use_graph=1, prop_blocks=64, node_blocks=32)
-    assert b.config() == cfg and len(table) == 18
+    assert cfg == dict(iters_per_sync=8, use_graph=1, prop_blocks=16, node_blocks=8)
+    assert b.config() == cfg and len(table) == 24
     # a second tuning of the same signature reads the cache and plans nothing
     b2 = FakeBatch()
     cfg2, _ = autotune.tune(b2, lambda: None, "sig-a", cache_path=path)
