@@ -260,9 +260,11 @@ def batched_leg(n_queries, batch_seed=3):
     ps = problem_batch(n=n_queries, batch_seed=batch_seed)
     planners = [Planner(p) for p in ps]
 
+    seeds = [p["seed"] for p in ps]
+    B = None
+
     def reset():
-        for G, p in zip(planners, ps):
-            G.reset(p["seed"])
+        B.reset(seeds)
 
     seq_ms, seq = [], []
     for rep in range(2):   # the first pass warms every handle up
@@ -307,6 +309,43 @@ def batched_leg(n_queries, batch_seed=3):
     }
 
 
+def sweep(workload, seeds, caps, eps_delta):
+    """Time-to-solution and failures against the tree capacity t_e (the
+    paper's only scaling experiment, Sec. VI), then against epsilon and delta
+    at the workload's own capacity.  One JSON line per setting."""
+    from paper_2409_06807_amd import Planner, SOLVED
+
+    def run(p):
+        G = Planner(p)
+        G.reset(0)
+        G.plan()   # warm-up
+        ms, st, it = [], [], []
+        for s in seeds:
+            a = time.perf_counter()
+            G.reset(s)
+            r = G.plan()
+            ms.append((time.perf_counter() - a) * 1e3)
+            st.append(r["status"])
+            it.append(r["iterations"])
+        G.close()
+        solved = [m for m, s in zip(ms, st) if s == SOLVED]
+        return {"success_rate": len(solved) / len(st),
+                "median_tts_ms": statistics.median(solved) if solved else None,
+                "mean_tts_ms": statistics.mean(solved) if solved else None,
+                "median_iterations": statistics.median(it), "statuses": st}
+
+    for cap in caps:
+        p = gpu_workload(workload, 0)
+        p["node_cap"] = int(cap)
+        print(json.dumps({"mode": "t_e sweep", "workload": p["name"], "node_cap": int(cap),
+                          "seeds": len(seeds), **run(p)}), flush=True)
+    for eps, delta in eps_delta:
+        p = gpu_workload(workload, 0)
+        p["epsilon"], p["delta"] = float(eps), float(delta)
+        print(json.dumps({"mode": "epsilon/delta sweep", "workload": p["name"], "epsilon": eps,
+                          "delta": delta, "seeds": len(seeds), **run(p)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +367,9 @@ def main():
                     help="uniform training queries whose solution paths are logged")
     ap.add_argument("--learned-train-steps", type=int, default=1000)
     ap.add_argument("--learned-mix", type=float, default=0.7)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the bench line, sweep the tree capacity t_e and then epsilon "
+                         "and delta on the workload (one JSON line per setting)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-planning leg")
     ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
@@ -348,6 +390,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.sweep:
+        seeds = list(range(max(args.steps, 1)))
+        base = int(gpu_workload(args.workload, 0)["node_cap"])
+        caps = [base // 8, base // 4, base // 2, base, base * 2]
+        eps_delta = [(1e-2, 1e-3), (1e-3, 1e-3), (1e-1, 1e-3), (1e-2, 1e-1), (1e-2, 1e-5)]
+        sweep(args.workload, seeds, caps, eps_delta)
+        return
 
     p = gpu_workload(args.workload, 0)
     G = Planner(p, device="cuda:0", iters_per_sync=args.iters_per_sync)

@@ -404,6 +404,10 @@ kp_status kp_batch_get_config(const kp_batch* b, kp_batch_config* cfg);
  * time of the whole call.  Synchronous. */
 kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms);
 
+/* kp_reset of every problem of the batch (seeds: one per problem), enqueued
+ * back to back with a single wait at the end. */
+kp_status kp_batch_reset(kp_batch* b, const uint64_t* seeds);
+
 kp_status kp_batch_destroy(kp_batch* b);
 const char* kp_batch_last_error(const kp_batch* b);
 

@@ -1241,6 +1241,32 @@ kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms) 
   return KP_OK;
 }
 
+kp_status kp_batch_reset(kp_batch* b, const uint64_t* seeds) {
+  if (!b || !seeds) return KP_E_ARG;
+  // the set-up of every problem (as kp_reset) enqueued back to back, one wait
+  for (size_t i = 0; i < b->P.size(); ++i) {
+    kp_problem* h = b->P[i];
+    h->desc.seed = seeds[i];
+    h->prm.key0 = (uint32_t)seeds[i];
+    h->prm.key1 = (uint32_t)(seeds[i] >> 32);
+    h->ctl_fresh = false;
+    hipError_t e = upload_env(h);
+    if (e == hipSuccess) e = launch_zero(h->prm, h->dev, h->env_dev, h->stream);
+    if (e == hipSuccess) {
+      Vec12 xi;
+      for (int k = 0; k < 12; ++k) xi.v[k] = h->desc.x_init[k];
+      e = launch_root(h->env_dev, xi, h->stream);
+    }
+    if (e != hipSuccess) return bhip(b, e, "batch reset");
+    kp_status st = do_frontier(h, 1);
+    if (st != KP_OK) return bfail(b, st, h->err);
+    h->stage = 0;
+  }
+  hipError_t e = hipStreamSynchronize(b->user_stream);
+  if (e != hipSuccess) return bhip(b, e, "batch reset");
+  return KP_OK;
+}
+
 kp_status kp_batch_destroy(kp_batch* b) {
   if (!b) return KP_E_ARG;
   (void)hipStreamSynchronize(b->stream);

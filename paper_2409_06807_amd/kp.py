@@ -33,7 +33,7 @@ EXPORTED = [
     "kp_status_str", "kp_last_error", "kp_mlp_pack", "kp_mlp_forward", "kp_mlp_grad",
     "kp_mlp_adam", "kp_mlp_train", "kp_set_proposal", "kp_log_path",
     "kp_batch_workspace_bytes", "kp_batch_create", "kp_batch_set_config", "kp_batch_get_config",
-    "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error",
+    "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error", "kp_batch_reset",
 ]
 
 
@@ -163,8 +163,9 @@ def load_library():
     L.kp_batch_get_config.argtypes = [P, C.POINTER(BatchConfig)]
     L.kp_batch_plan.argtypes = [P, P, C.POINTER(C.c_double)]
     L.kp_batch_destroy.argtypes = [P]
+    L.kp_batch_reset.argtypes = [P, P]
     for name in ("kp_batch_create", "kp_batch_set_config", "kp_batch_get_config", "kp_batch_plan",
-                 "kp_batch_destroy"):
+                 "kp_batch_destroy", "kp_batch_reset"):
         getattr(L, name).restype = C.c_int
     L.kp_batch_last_error.argtypes = [P]
     L.kp_batch_last_error.restype = C.c_char_p
@@ -527,6 +528,13 @@ class Batch:
         cur.update(kw)
         c = BatchConfig(**{k: int(v) for k, v in cur.items()})
         self._check(self.lib.kp_batch_set_config(self.h, C.byref(c)))
+
+    def reset(self, seeds):
+        """kp_reset of every problem with its seed, one wait for all."""
+        a = np.ascontiguousarray(np.asarray(seeds, np.uint64))
+        if a.shape != (len(self.planners),):
+            raise KPError(E_ARG, "one seed per problem")
+        self._check(self.lib.kp_batch_reset(self.h, _ptr(a)))
 
     def plan(self):
         """Returns (per-problem result dicts, batch wall time in ms)."""

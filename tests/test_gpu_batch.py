@@ -74,9 +74,8 @@ def test_batch_equals_single_planner(ci):
     res, ms = B.plan()
     assert ms > 0 and all(r["elapsed_ms"] <= ms for r in res)
     check_same(ref, planners, res)
-    # the same batch again after resets: identical again (graphs replay)
-    for G, p in zip(planners, ps):
-        G.reset(p["seed"])
+    # the same batch again after a batch reset: identical again (graphs replay)
+    B.reset([p["seed"] for p in ps])
     res2, _ = B.plan()
     check_same(ref, planners, res2)
     B.close()
