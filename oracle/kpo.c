@@ -77,6 +77,18 @@ static void draw_expansion(const kpo_problem* pb, int m, uint32_t it, uint32_t f
   }
 }
 
+/* Alg. 2 draws the segment duration dt in (0, T_prop].  With dur_mode = 1
+ * it is k steps of h, k uniform in {1 .. K} (T_prop = K h), from word 1 of
+ * the counter (it, f, s, 1); with dur_mode = 0 every segment is K steps. */
+int32_t kpo_segment_steps(const kpo_problem* pb, uint32_t it, uint32_t f, uint32_t s) {
+  if (!pb->dur_mode) return pb->steps;
+  uint32_t key[2] = {(uint32_t)pb->seed, (uint32_t)(pb->seed >> 32)};
+  uint32_t ctr[4] = {it, f, s, 1u};
+  uint32_t w[4];
+  kpo_philox4x32_10(ctr, key, w);
+  return 1 + (int32_t)(((uint64_t)w[1] * (uint64_t)pb->steps) >> 32);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Dynamics, eq. (1).                                                        */
 /* ------------------------------------------------------------------------ */
@@ -517,16 +529,18 @@ void kpo_expand_one_u(const kpo_planner* P, int32_t f, int32_t s, const float* u
   draw_expansion(pb, m, (uint32_t)P->it, (uint32_t)f, (uint32_t)s, rec->u, &rec->w_acc);
   if (u_given)
     for (int j = 0; j < m; ++j) rec->u[j] = u_given[j];
+  const int Kl = kpo_segment_steps(pb, (uint32_t)P->it, (uint32_t)f, (uint32_t)s);
+  rec->k_seg = Kl;
   double u[4] = {0, 0, 0, 0};
   for (int j = 0; j < m; ++j) u[j] = (double)rec->u[j];
   memcpy(traj, P->x + (size_t)f * n, sizeof(double) * n);
-  for (int j = 1; j <= K; ++j) kpo_step(pb, traj + (size_t)(j - 1) * n, u, traj + (size_t)j * n);
+  for (int j = 1; j <= Kl; ++j) kpo_step(pb, traj + (size_t)(j - 1) * n, u, traj + (size_t)j * n);
   const double tol = pb->amb_tol;
-  const int fail = first_fail(pb, traj, n, K, 0.0);
-  rec->fail_strict = first_fail(pb, traj, n, K, -tol);
-  rec->fail_loose = first_fail(pb, traj, n, K, +tol);
-  rec->valid = (fail == K + 1);
-  rec->steps = rec->valid ? K : fail;
+  const int fail = first_fail(pb, traj, n, Kl, 0.0);
+  rec->fail_strict = first_fail(pb, traj, n, Kl, -tol);
+  rec->fail_loose = first_fail(pb, traj, n, Kl, +tol);
+  rec->valid = (fail == Kl + 1);
+  rec->steps = rec->valid ? Kl : fail;
   const double* xe = traj + (size_t)rec->steps * n;
   memcpy(rec->x, xe, sizeof(double) * n);
   if (isfinite(xe[0]) && isfinite(xe[1]) && isfinite(xe[2])) {
@@ -701,6 +715,12 @@ int32_t kpo_path(const kpo_planner* P, int32_t node, int32_t* ids, int32_t cap) 
 
 int32_t kpo_replay(const kpo_problem* pb, const double* x0, int32_t n_edges, const float* controls,
                    double margin, double* end_states, int32_t* reached_goal) {
+  return kpo_replay_k(pb, x0, n_edges, controls, NULL, margin, end_states, reached_goal);
+}
+
+int32_t kpo_replay_k(const kpo_problem* pb, const double* x0, int32_t n_edges, const float* controls,
+                     const int32_t* edge_steps, double margin, double* end_states,
+                     int32_t* reached_goal) {
   const int n = state_dim(pb->dyn), m = ctrl_dim(pb->dyn);
   kpo_problem q = *pb;
   q.margin = margin;
@@ -709,7 +729,8 @@ int32_t kpo_replay(const kpo_problem* pb, const double* x0, int32_t n_edges, con
   int valid = kpo_state_ok(&q, x, 0.0) && !kpo_swept_hit(&q, x, x, margin);
   for (int32_t e = 0; e < n_edges; ++e) {
     for (int j = 0; j < m; ++j) u[j] = (double)controls[(size_t)e * m + j];
-    for (int k = 0; k < pb->steps; ++k) {
+    const int ke = edge_steps ? edge_steps[e] : pb->steps;
+    for (int k = 0; k < ke; ++k) {
       kpo_step(&q, x, u, xn);
       if (!kpo_state_ok(&q, xn, 0.0) || kpo_swept_hit(&q, x, xn, margin)) valid = 0;
       memcpy(x, xn, sizeof(double) * n);

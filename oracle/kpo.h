@@ -51,6 +51,8 @@ typedef struct {
   double delta, eps;
   uint64_t seed;
   double amb_tol;       /* ambiguity band for decisions taken on FP values */
+  int32_t dur_mode;     /* 0: every segment takes `steps` steps; 1: k ~ U{1..steps} per expansion */
+  int32_t pad_;
 } kpo_problem;
 
 /* One expansion (parent f, sample s) of Alg. 2, before any bookkeeping. */
@@ -68,7 +70,7 @@ typedef struct {
   int32_t fail_loose;   /* first failing step with every test relaxed by amb_tol */
   int32_t amb_cell;     /* x' within amb_tol of an interior cell plane */
   int32_t amb_goal;     /* x' within amb_tol of the goal sphere */
-  int32_t pad;
+  int32_t k_seg;        /* integration steps of this segment (its duration / h) */
 } kpo_record;
 
 typedef struct kpo_planner kpo_planner;
@@ -85,6 +87,10 @@ double kpo_region_score(double delta, uint64_t nv, uint64_t ni, int cov);
 void kpo_estimates(int R, const uint8_t* avail, const uint64_t* nv, const uint64_t* ni,
                    const uint64_t* visited, double delta, double eps,
                    double* score_out, uint64_t* q_out, double* p_out, uint64_t* thr_out);
+
+/* Steps of the segment of expansion (it, f, s): `steps` when dur_mode = 0,
+ * else 1 + floor(w * steps / 2^32) for word 1 of Philox(it, f, s, 1). */
+int32_t kpo_segment_steps(const kpo_problem* pb, uint32_t it, uint32_t f, uint32_t s);
 
 /* --- planner --- */
 kpo_planner* kpo_create(const kpo_problem* pb, int32_t* status);
@@ -110,6 +116,10 @@ int32_t kpo_path(const kpo_planner* P, int32_t node, int32_t* ids, int32_t cap);
  * and test the goal at the end.  Writes the FP64 end state of every edge. */
 int32_t kpo_replay(const kpo_problem* pb, const double* x0, int32_t n_edges, const float* controls,
                    double margin, double* end_states, int32_t* reached_goal);
+/* The same with edge_steps[e] integration steps for edge e (NULL: `steps`). */
+int32_t kpo_replay_k(const kpo_problem* pb, const double* x0, int32_t n_edges, const float* controls,
+                     const int32_t* edge_steps, double margin, double* end_states,
+                     int32_t* reached_goal);
 
 void kpo_integrate_batch(const kpo_problem* pb, int64_t n_seg, const double* x0, const float* u,
                          const int32_t* steps, double* out);

@@ -39,7 +39,8 @@ class Problem(C.Structure):
         ("x_init", C.c_double * 12), ("goal_c", C.c_double * 3), ("goal_r", C.c_double),
         ("grid", C.c_int32 * 3), ("sub", C.c_int32), ("cap", C.c_int32),
         ("lambda_max", C.c_int32), ("delta", C.c_double), ("eps", C.c_double),
-        ("seed", C.c_uint64), ("amb_tol", C.c_double),
+        ("seed", C.c_uint64), ("amb_tol", C.c_double), ("dur_mode", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 
@@ -60,7 +61,7 @@ class View(C.Structure):
 
 RECORD_DTYPE = np.dtype({
     "names": ["parent", "sample", "u", "x", "steps", "valid", "cell", "goal", "w_acc",
-              "fail_strict", "fail_loose", "amb_cell", "amb_goal", "pad"],
+              "fail_strict", "fail_loose", "amb_cell", "amb_goal", "k_seg"],
     "formats": [np.int32, np.int32, (np.float32, 4), (np.float64, 12), np.int32, np.int32,
                 np.uint32, np.int32, np.uint32, np.int32, np.int32, np.int32, np.int32, np.int32],
     "offsets": [0, 4, 8, 24, 120, 124, 128, 132, 136, 140, 144, 148, 152, 156],
@@ -103,6 +104,8 @@ def lib():
         L.kpo_expand_all.argtypes = [P, vp]
         L.kpo_expand_all.restype = C.c_int64
         L.kpo_expand_one_u.argtypes = [P, C.c_int32, C.c_int32, vp, vp, vp]
+        L.kpo_segment_steps.argtypes = [C.POINTER(Problem), C.c_uint32, C.c_uint32, C.c_uint32]
+        L.kpo_segment_steps.restype = C.c_int32
         L.kpo_expand_all_u.argtypes = [P, vp, vp]
         L.kpo_expand_all_u.restype = C.c_int64
         L.kpo_apply.argtypes = [P, vp, C.c_int64]
@@ -119,6 +122,9 @@ def lib():
         L.kpo_replay.argtypes = [C.POINTER(Problem), vp, C.c_int32, vp, C.c_double, vp,
                                  C.POINTER(C.c_int32)]
         L.kpo_replay.restype = C.c_int32
+        L.kpo_replay_k.argtypes = [C.POINTER(Problem), vp, C.c_int32, vp, vp, C.c_double, vp,
+                                   C.POINTER(C.c_int32)]
+        L.kpo_replay_k.restype = C.c_int32
         L.kpo_integrate_batch.argtypes = [C.POINTER(Problem), C.c_int64, vp, vp, vp, vp]
         L.kpo_get_view.argtypes = [P, C.POINTER(View)]
         L.kpo_set_counters.argtypes = [P, C.c_int32, C.c_int32]
@@ -165,6 +171,7 @@ def problem_struct(p: dict, amb_tol: float = AMB_TOL):
     s.eps = float(p["epsilon"])
     s.seed = int(p["seed"]) & ((1 << 64) - 1)
     s.amb_tol = float(amb_tol)
+    s.dur_mode = int(p.get("duration_mode", 0))
     return s, obs
 
 
@@ -177,6 +184,13 @@ def philox4x32_10(ctr, key):
     out = np.zeros(4, np.uint32)
     lib().kpo_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def segment_steps(p, it, f, s):
+    """Integration steps of expansion (it, f, s) (random duration when the
+    problem's duration_mode is 1)."""
+    pb = _PB(p)
+    return int(lib().kpo_segment_steps(C.byref(pb.s), int(it), int(f), int(s)))
 
 
 def control_map(w, lo, hi):
@@ -259,15 +273,18 @@ def integrate_batch(p, x0, u, steps):
     return out
 
 
-def replay(p, x0, controls, margin=0.0):
-    """FP64 replay of a path; returns (valid, reached_goal, end_states)."""
+def replay(p, x0, controls, margin=0.0, edge_steps=None):
+    """FP64 replay of a path; returns (valid, reached_goal, end_states).
+    edge_steps: integration steps per edge (default: the problem's steps)."""
     pb = _PB(p)
     x0 = np.ascontiguousarray(np.asarray(x0, np.float64))
     ctl = np.ascontiguousarray(np.asarray(controls, np.float32).reshape(-1, pb.m))
     ends = np.zeros((max(len(ctl), 1), pb.n))
     g = C.c_int32(0)
-    v = lib().kpo_replay(C.byref(pb.s), _ptr(x0), len(ctl), _ptr(ctl), float(margin), _ptr(ends),
-                         C.byref(g))
+    ks = None if edge_steps is None else np.ascontiguousarray(np.asarray(edge_steps, np.int32))
+    v = lib().kpo_replay_k(C.byref(pb.s), _ptr(x0), len(ctl), _ptr(ctl),
+                           _ptr(ks) if ks is not None else None, float(margin), _ptr(ends),
+                           C.byref(g))
     return bool(v), bool(g.value), ends[:len(ctl)]
 
 
