@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define KP_ABI_VERSION 1u
+#define KP_ABI_VERSION 2u
 #define KP_MAX_STATE 12
 #define KP_MAX_CONTROL 4
 #define KP_MAX_OBSTACLES 1536  /* per-block LDS (obstacle table + candidate lists) stays under 64 KiB */
@@ -104,6 +104,10 @@ typedef struct {
   double t_max_ms;
   int32_t max_iters;
   int32_t iters_per_sync;
+  int32_t duration_mode;       /* 0: every segment is `steps` steps (default); 1: Alg. 2's random
+                                  duration, k uniform in 1..steps steps per expansion, from word 1
+                                  of Philox(it, parent, sample, 1) as 1 + (w * steps >> 32) */
+  int32_t reserved;            /* must be 0 */
 } kp_problem_desc;
 
 typedef struct kp_problem kp_problem;

@@ -67,6 +67,8 @@ std::string check_desc(const kp_problem_desc* d) {
   if (!(d->goal_radius >= 0.0f)) return "goal_radius must be >= 0";
   if (d->max_iters < 0) return "max_iters must be >= 0";
   if (d->iters_per_sync < 0 || d->iters_per_sync > 4096) return "iters_per_sync out of range";
+  if (d->duration_mode != 0 && d->duration_mode != 1) return "duration_mode must be 0 or 1";
+  if (d->reserved != 0) return "reserved must be 0";
   return std::string();
 }
 
@@ -210,6 +212,7 @@ void fill_params(kp_problem* h) {
   p.dIyz = p.Iyy - p.Izz;
   p.dIzx = p.Izz - p.Ixx;
   p.dIxy = p.Ixx - p.Iyy;
+  p.dur_mode = d.duration_mode;
   p.key0 = (uint32_t)d.seed;
   p.key1 = (uint32_t)(d.seed >> 32);
   p.delta = d.delta;

@@ -65,6 +65,7 @@ static_assert(sizeof(Ctl) <= 4096, "control block size");
 struct Params {
   int32_t n, m, K, cap;
   int32_t lambda_max, n_obs, S, R;
+  int32_t dur_mode, pad_;   // 1: segment of 1 + (w * K >> 32) steps, w = word 1 of tag 1
   int32_t G[3];
   int32_t na[3];        // fine cells per axis = G * S
   float h, margin, goal_r2, rc;

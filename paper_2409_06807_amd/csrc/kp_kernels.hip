@@ -757,6 +757,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     float x[n];
     float u[m];
     uint32_t w_acc = 0;
+    int kl = K;  // this segment's steps
     if (active) {
       e = g / lam;
       s = g - e * lam;
@@ -768,9 +769,14 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       for (int j = 0; j < m; ++j) u[j] = ctrl_map(w.w[j], p.u_lo[j], p.u_hi[j]);
       if constexpr (m < 4) {
         w_acc = w.w[3];
+        if (p.dur_mode) {
+          const U4 w1 = philox(it, (uint32_t)f, (uint32_t)s, 1u, p.key0, p.key1);
+          kl = 1 + (int)__umulhi(w1.w[1], (uint32_t)K);
+        }
       } else {
         const U4 w1 = philox(it, (uint32_t)f, (uint32_t)s, 1u, p.key0, p.key1);
         w_acc = w1.w[0];
+        if (p.dur_mode) kl = 1 + (int)__umulhi(w1.w[1], (uint32_t)K);
       }
       // learned proposal: with probability mix_thr / 2^32 the control comes
       // from the network's Gaussian for this frontier entry instead
@@ -922,6 +928,8 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
         if (!ok) {
           alive = false;
           valid = false;
+        } else if (j + 1 == kl) {
+          alive = false;  // the segment's duration is over
         }
       }
     }

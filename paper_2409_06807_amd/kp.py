@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkinopax.so")
 
-KP_ABI_VERSION = 1
+KP_ABI_VERSION = 2
 OK, SOLVED, TIMEOUT, TREE_FULL, FRONTIER_EMPTY = 0, 1, 2, 3, 4
 E_ARG, E_DEVICE, E_WORKSPACE, E_START_INVALID, E_GOAL_INVALID, E_ORDER = -1, -2, -3, -4, -5, -6
 KERNELS = {"propagate": 0, "region": 1, "nodesets": 2, "frontier": 3, "commit": 4, "post": 5,
@@ -48,7 +48,7 @@ class Desc(C.Structure):
         ("grid", C.c_int32 * 3), ("sub", C.c_int32), ("node_cap", C.c_int32),
         ("lambda_max", C.c_int32), ("delta", C.c_double), ("epsilon", C.c_double),
         ("seed", C.c_uint64), ("t_max_ms", C.c_double), ("max_iters", C.c_int32),
-        ("iters_per_sync", C.c_int32),
+        ("iters_per_sync", C.c_int32), ("duration_mode", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -210,6 +210,7 @@ def make_desc(p: dict, iters_per_sync: int = 0):
     d.t_max_ms = float(p["t_max_ms"])
     d.max_iters = int(p["max_iters"])
     d.iters_per_sync = int(iters_per_sync)
+    d.duration_mode = int(p.get("duration_mode", 0))
     return d, obs
 
 

@@ -109,8 +109,9 @@ def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
                      f"gpu {g_fail[k]}, band [{recs['fail_strict'][k]}, {recs['fail_loose'][k]}])")
             continue
         # admissible: adopt the GPU's first failing step, oracle state at that step
-        rec, traj = W.expand_one(recs["parent"][k], recs["sample"][k], want_traj=True)
-        steps = min(int(g_fail[k]), K)
+        rec, traj = W.expand_one(recs["parent"][k], recs["sample"][k], want_traj=True,
+                                 control=recs["u"][k])
+        steps = min(int(g_fail[k]), int(recs["k_seg"][k]))
         merged["valid"][k] = 1 if g_fail[k] == K + 1 else 0
         merged["steps"][k] = steps
         merged["x"][k][:n] = traj[steps]

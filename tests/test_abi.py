@@ -115,4 +115,14 @@ def test_struct_layouts_match_header(lib):
     assert C.sizeof(kp.kp.TreeHost) == 8 + 12 * 8
     assert kp.TRACE_DTYPE.itemsize == 96
     src = open(os.path.join(ROOT, "include", "kp.h")).read()
-    assert "KP_ABI_VERSION 1u" in src
+    assert f"KP_ABI_VERSION {kp.kp.KP_ABI_VERSION}u" in src
+    # the description's last fields: duration mode and a zero reserved word
+    assert kp.kp.Desc.duration_mode.offset + 8 == C.sizeof(kp.kp.Desc)
+    p = problem_small_di()
+    d, keep = kp.make_desc(p)
+    assert lib.kp_workspace_bytes(C.byref(d)) > 0
+    d.duration_mode = 2
+    assert lib.kp_workspace_bytes(C.byref(d)) == 0
+    d.duration_mode = 1
+    d.reserved = 5
+    assert lib.kp_workspace_bytes(C.byref(d)) == 0

@@ -31,6 +31,9 @@ CASES = {
     # the c5 building (1200 boxes, 32^3 regions, lambda_max 8) at a small cap:
     # more regions than the region pass holds in registers
     "c5-building": lambda: problem_c5(seed=1, node_cap=12000),
+    # Alg. 2's random segment duration (k uniform in 1..K steps)
+    "di-duration": lambda: problem_small_di(seed=8, cap=4096, n_obs=12, duration_mode=1),
+    "quad-duration": lambda: problem_small_quad(seed=4, cap=8192, n_obs=60, duration_mode=1),
 }
 
 

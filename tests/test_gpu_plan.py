@@ -233,7 +233,7 @@ def test_c5_full_size_properties():
     print(f"c5: N={g['N']} iterations={r['iterations']} worst edge rel err {worst:.2e}")
 
 
-def replay_path_edgewise(p, g, path):
+def replay_path_edgewise(p, g, path, edge_steps=None):
     """FP64 replay of a returned path one edge at a time: each segment starts
     from its parent's stored state (what the planner integrated from), runs
     the stored control for K steps, must stay in the state box and off the
@@ -243,10 +243,10 @@ def replay_path_edgewise(p, g, path):
     rounding along the path instead of checking it.)"""
     K = int(p["steps"])
     worst = 0.0
-    for a, b in zip(path[:-1], path[1:]):
+    for e, (a, b) in enumerate(zip(path[:-1], path[1:])):
         x = g["x"][a].astype(np.float64)
         u = g["u"][b].astype(np.float64)
-        for _ in range(K):
+        for _ in range(K if edge_steps is None else int(edge_steps[e])):
             y = oracle.step(p, x, u)
             # the obstacles without the planner's margin, less the 1e-4 band
             if not oracle.state_ok(p, y, relax=1e-4) or oracle.swept_hit(p, x, y, -1e-4):
@@ -320,3 +320,21 @@ def test_plan_equals_step_path(case):
         assert np.array_equal(g[k], ref[k]), k
     assert np.array_equal(g["x"].view(np.uint32), ref["x"].view(np.uint32))
     assert np.array_equal(g["u"].view(np.uint32), ref["u"].view(np.uint32))
+
+
+def test_c2_random_duration_solution_replays_in_fp64():
+    # Alg. 2's random segment duration on the full-size forest: each edge
+    # replays over its own number of steps (from the Philox word of its
+    # creating expansion)
+    p = problem_c2(seed=0, duration_mode=1)
+    _say("c2 full solve, random durations")
+    G = planner(p)
+    r = G.plan()
+    assert r["status"] == oracle.SOLVED, r
+    path = G.path(r["goal_id"])
+    g = G.copy_tree()
+    ks = [oracle.segment_steps(p, int(g["birth"][b]), int(g["parent"][b]), int(g["sample"][b]))
+          for b in path[1:]]
+    assert len(set(ks)) > 1
+    valid, reached, worst = replay_path_edgewise(p, g, path, ks)
+    assert valid and reached and worst <= 1e-5, (valid, reached, worst)
