@@ -339,6 +339,27 @@ def sweep(workload, seeds, caps, eps_delta):
         p["node_cap"] = int(cap)
         print(json.dumps({"mode": "t_e sweep", "workload": p["name"], "node_cap": int(cap),
                           "seeds": len(seeds), **run(p)}), flush=True)
+    # Remark 1: start small and grow the capacity by 2x whenever the tree fills
+    from paper_2409_06807_amd import plan_adaptive
+    p0 = gpu_workload(workload, 0)
+    start = int(p0["node_cap"]) // 8
+    ms, st, rs = [], [], []
+    for s in seeds:
+        p = dict(p0, node_cap=start, seed=s)
+        a = time.perf_counter()
+        r, G, resizes = plan_adaptive(p, growth=2, cap_max=int(p0["node_cap"]) * 2)
+        ms.append((time.perf_counter() - a) * 1e3)
+        st.append(r["status"])
+        rs.extend(resizes)
+        G.close()
+    solved = [m for m, s_ in zip(ms, st) if s_ == SOLVED]
+    print(json.dumps({"mode": "adaptive t_e", "workload": p0["name"], "start_cap": start,
+                      "growth": 2, "seeds": len(seeds), "success_rate": len(solved) / len(st),
+                      "median_ms_with_resizes": statistics.median(solved) if solved else None,
+                      "resizes": len(rs),
+                      "mean_transfer_ms": statistics.mean(t for _, t in rs) if rs else None,
+                      "note": "wall time includes creating each larger planner",
+                      "statuses": st}), flush=True)
     for eps, delta in eps_delta:
         p = gpu_workload(workload, 0)
         p["epsilon"], p["delta"] = float(eps), float(delta)

@@ -252,6 +252,12 @@ kp_status kp_copy_tree(kp_problem* h, kp_tree_host* out);
  * call must be kp_expand.  Synchronous. */
 kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in);
 
+/* Remark 1's adaptive t_e: move the tree of src (between iterations) into dst,
+ * a handle of the same problem and seed with a capacity >= |T|, device to
+ * device; dst then continues as if it had grown the tree itself (frontier
+ * and eq. (6) recomputed with its capacity).  Synchronous. */
+kp_status kp_transfer_tree(kp_problem* src, kp_problem* dst);
+
 /* Node ids from the root to `node` ("return trajectory x_init to x",
  * the goal test of Alg. 4).  ids: host array of cap entries; *len receives the path
  * length.  KP_E_ARG if node is out of range or the path exceeds cap. */

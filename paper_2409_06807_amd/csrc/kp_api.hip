@@ -791,6 +791,58 @@ kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in) {
   return sync_ctl(h);
 }
 
+kp_status kp_transfer_tree(kp_problem* src, kp_problem* dst) {
+  if (!src || !dst || src == dst) return KP_E_ARG;
+  const kp_problem_desc& a = src->desc;
+  const kp_problem_desc& b = dst->desc;
+  if (a.dynamics != b.dynamics || a.integrator != b.integrator || a.steps != b.steps ||
+      a.grid[0] != b.grid[0] || a.grid[1] != b.grid[1] || a.grid[2] != b.grid[2] ||
+      a.sub != b.sub || a.seed != b.seed || a.duration_mode != b.duration_mode)
+    return fail(dst, KP_E_ARG, "kp_transfer_tree: problems differ beyond their capacity");
+  if (src->stage != 0) return fail(dst, KP_E_ORDER, "kp_transfer_tree: source mid-iteration");
+  kp_status st = sync_ctl(src);
+  if (st != KP_OK) return fail(dst, st, src->err);
+  const int32_t N = src->hctl->N;
+  const int32_t it = src->hctl->it;
+  if (N > b.node_cap) return fail(dst, KP_E_ARG, "kp_transfer_tree: tree larger than the capacity");
+  hipError_t e = hipStreamSynchronize(dst->stream);
+  // device to device on the destination's stream; the source is idle (synchronised above)
+  const size_t ps = (size_t)src->L.capP * 4, pd = (size_t)dst->L.capP * 4;
+  hipStream_t s = dst->stream;
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(dst->dev.x, pd, src->dev.x, ps, (size_t)N * 4, dst->n,
+                         hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(dst->dev.u, pd, src->dev.u, ps, (size_t)N * 4, dst->m,
+                         hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.parent, src->dev.parent, (size_t)N * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.cell, src->dev.cell, (size_t)N * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.flag, src->dev.flag, (size_t)N, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.birth, src->dev.birth, (size_t)N * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.sample, src->dev.sample, (size_t)N, hipMemcpyDeviceToDevice, s);
+  const size_t R = (size_t)dst->R;
+  if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.nv, src->dev.nv, R * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.ni, src->dev.ni, R * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.visited, src->dev.visited, R * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst->dev.avail, src->dev.avail, R, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.thr, src->dev.thr, R * 8, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(dst, e, "tree transfer");
+  dst->ctl_fresh = false;
+  e = launch_set_ctl(dst->env_dev, N, it, s);
+  if (e != hipSuccess) return hip_fail(dst, e, "control load");
+  st = do_frontier(dst, N);
+  if (st != KP_OK) return st;
+  dst->stage = 0;
+  return sync_ctl(dst);
+}
+
 kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, int32_t* len) {
   if (!h || !len) return KP_E_ARG;
   kp_status st = sync_ctl(h);

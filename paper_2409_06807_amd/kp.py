@@ -34,6 +34,7 @@ EXPORTED = [
     "kp_mlp_adam", "kp_mlp_train", "kp_set_proposal", "kp_log_path",
     "kp_batch_workspace_bytes", "kp_batch_create", "kp_batch_set_config", "kp_batch_get_config",
     "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error", "kp_batch_reset",
+    "kp_transfer_tree",
 ]
 
 
@@ -164,6 +165,8 @@ def load_library():
     L.kp_batch_plan.argtypes = [P, P, C.POINTER(C.c_double)]
     L.kp_batch_destroy.argtypes = [P]
     L.kp_batch_reset.argtypes = [P, P]
+    L.kp_transfer_tree.argtypes = [P, P]
+    L.kp_transfer_tree.restype = C.c_int
     for name in ("kp_batch_create", "kp_batch_set_config", "kp_batch_get_config", "kp_batch_plan",
                  "kp_batch_destroy", "kp_batch_reset"):
         getattr(L, name).restype = C.c_int
@@ -395,6 +398,10 @@ class Planner:
                                          C.byref(n)))
         return n.value
 
+    def transfer_from(self, other: "Planner"):
+        """Take over `other`'s tree (same problem and seed, capacity >= its |T|)."""
+        self._check(self.lib.kp_transfer_tree(other.h, self.h))
+
     def path(self, node: int):
         n = C.c_int32(0)
         ids = np.zeros(1 << 16, np.int32)
@@ -558,3 +565,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def plan_adaptive(p: dict, growth: int = 2, cap_max: int = 1 << 26, device="cuda:0"):
+    """Remark 1's adaptive tree capacity: plan, and whenever eq. (6) stops
+    the query on a full tree, move the tree into a planner `growth` times
+    larger and go on.  Returns (final result, planner, list of
+    (capacity, transfer ms))."""
+    import time
+    import torch
+    G = Planner(p, device=device)
+    r = G.plan()
+    resizes = []
+    cap = int(p["node_cap"])
+    while r["status"] == TREE_FULL and cap * growth <= cap_max:
+        cap *= growth
+        H = Planner(dict(p, node_cap=cap), device=device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.transfer_from(G)
+        resizes.append((cap, (time.perf_counter() - t0) * 1e3))
+        G.close()
+        G = H
+        r = G.plan()
+    return r, G, resizes

@@ -338,3 +338,53 @@ def test_c2_random_duration_solution_replays_in_fp64():
     assert len(set(ks)) > 1
     valid, reached, worst = replay_path_edgewise(p, g, path, ks)
     assert valid and reached and worst <= 1e-5, (valid, reached, worst)
+
+
+def test_transfer_tree_equals_host_load_and_continues_identically():
+    # Remark 1's capacity growth: moving a full tree device to device into a
+    # larger handle is the same as loading its host copy there, and both
+    # continue identically
+    from paper_2409_06807_amd import Planner
+    _say("transfer tree")
+    p = problem_small_di(seed=3, cap=1500)
+    G = planner(p)
+    r = G.plan()
+    assert r["status"] == oracle.TREE_FULL, r
+    big = dict(p, node_cap=6000)
+    A = Planner(big)
+    A.transfer_from(G)
+    B = Planner(big)
+    B.load_tree(G.copy_tree())
+    sa, sb = A.stats(), B.stats()
+    for k in ("n_nodes", "n_frontier", "lam", "iteration", "done_code"):
+        assert sa[k] == sb[k], k
+    assert sa["lam"] > 0
+    ta, tb = A.copy_tree(), B.copy_tree()
+    for k in ("x", "u", "parent", "cell", "flag", "birth", "sample", "nv", "ni", "visited", "thr"):
+        assert np.array_equal(ta[k], tb[k]), k
+    ra, rb = A.plan(), B.plan()
+    for k in ("status", "goal_id", "iterations", "n_nodes"):
+        assert ra[k] == rb[k], k
+    ta, tb = A.copy_tree(), B.copy_tree()
+    assert np.array_equal(ta["parent"], tb["parent"]) and np.array_equal(ta["x"], tb["x"])
+    # a handle of another problem is refused
+    C = Planner(dict(p, seed=4, node_cap=6000))
+    from paper_2409_06807_amd import KPError
+    with pytest.raises(KPError):
+        C.transfer_from(G)
+
+
+def test_plan_adaptive_capacity():
+    from paper_2409_06807_amd import plan_adaptive
+    _say("adaptive capacity")
+    p = problem_small_di(seed=3, cap=1500)
+    r, G, resizes = plan_adaptive(p, growth=2, cap_max=48000)
+    assert len(resizes) >= 1 and resizes[0][0] == 3000
+    g = G.copy_tree()
+    N = g["N"]
+    assert N == r["n_nodes"] or r["status"] != oracle.SOLVED
+    assert g["parent"][0] == -1 and np.all(g["parent"][1:N] < np.arange(1, N))
+    if r["status"] == oracle.SOLVED:
+        path = G.path(r["goal_id"])
+        valid, reached, worst = replay_path_edgewise(p, g, path)
+        assert valid and reached and worst <= 1e-5
