@@ -339,6 +339,11 @@ def sweep(workload, seeds, caps, eps_delta):
         p["node_cap"] = int(cap)
         print(json.dumps({"mode": "t_e sweep", "workload": p["name"], "node_cap": int(cap),
                           "seeds": len(seeds), **run(p)}), flush=True)
+    # Alg. 2's random segment duration (k uniform in 1..K steps) at the workload's capacity
+    p = gpu_workload(workload, 0)
+    p["duration_mode"] = 1
+    print(json.dumps({"mode": "random segment duration", "workload": p["name"],
+                      "node_cap": int(p["node_cap"]), "seeds": len(seeds), **run(p)}), flush=True)
     # Remark 1: start small and grow the capacity by 2x whenever the tree fills
     from paper_2409_06807_amd import plan_adaptive
     p0 = gpu_workload(workload, 0)
