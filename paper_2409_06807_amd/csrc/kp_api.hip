@@ -170,6 +170,43 @@ kp_status hip_fail(kp_problem* h, hipError_t e, const char* what) {
   return fail(h, KP_E_DEVICE, msg);
 }
 
+// True when every state an RK4 or Euler stage of a quadcopter step can
+// reach keeps |roll|, |pitch| and the yaw increment of a stage within the
+// range of the tilt polynomials (1.8 rad, 1.75 used), given that the step
+// starts inside the state box (every expanded node and every state that
+// passed its step's check does):
+//   body rates: |w'_a| <= (|tau_a| + |I_b - I_c| |w_b| |w_c|) / I_a; the bound
+//     W = w_box + h w'(W) (fixed point) holds at every stage point;
+//   pitch: |theta'| = |q cos phi - r sin phi| <= W_y + W_z;
+//   roll: |phi'| <= W_x + (W_y + W_z) tan(theta_max);
+//   yaw: |psi'| <= (W_y + W_z) / cos(theta_max), times h for a stage increment.
+bool tilt_range_ok(const kp_problem_desc& d) {
+  if (d.dynamics != KP_DYN_QUAD12) return false;
+  auto amax = [&](int i) { return std::fmax(std::fabs((double)d.x_lo[i]), std::fabs((double)d.x_hi[i])); };
+  const double h = d.h, lim = 1.75;
+  const double I[3] = {d.dyn_params[2], d.dyn_params[3], d.dyn_params[4]};
+  double tau[3], w[3], W[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(I[a] > 0.0)) return false;
+    tau[a] = std::fmax(std::fabs((double)d.u_lo[1 + a]), std::fabs((double)d.u_hi[1 + a]));
+    w[a] = W[a] = amax(9 + a);
+  }
+  for (int it = 0; it < 32; ++it) {
+    const double dw0 = (tau[0] + std::fabs(I[1] - I[2]) * W[1] * W[2]) / I[0];
+    const double dw1 = (tau[1] + std::fabs(I[2] - I[0]) * W[2] * W[0]) / I[1];
+    const double dw2 = (tau[2] + std::fabs(I[0] - I[1]) * W[0] * W[1]) / I[2];
+    W[0] = w[0] + h * dw0;
+    W[1] = w[1] + h * dw1;
+    W[2] = w[2] + h * dw2;
+  }
+  for (int a = 0; a < 3; ++a) W[a] *= 1.01;  // the fixed point, rounded up
+  const double th = amax(4) + h * (W[1] + W[2]);
+  if (!(th < 1.45)) return false;
+  const double ph = amax(3) + h * (W[0] + (W[1] + W[2]) * std::tan(th));
+  const double dy = h * (W[1] + W[2]) / std::cos(th);
+  return std::isfinite(ph) && ph <= lim && th <= lim && dy <= lim;
+}
+
 void fill_params(kp_problem* h) {
   const kp_problem_desc& d = h->desc;
   Params& p = h->prm;
@@ -213,6 +250,7 @@ void fill_params(kp_problem* h) {
   p.dIzx = p.Izz - p.Ixx;
   p.dIxy = p.Ixx - p.Iyy;
   p.dur_mode = d.duration_mode;
+  p.tilt_fast = tilt_range_ok(d) ? 1 : 0;
   p.key0 = (uint32_t)d.seed;
   p.key1 = (uint32_t)(d.seed >> 32);
   p.delta = d.delta;
@@ -367,7 +405,7 @@ kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool 
   long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
   int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
   if (grid < 1) grid = 1;
-  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->env_dev,
+  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm.tilt_fast, h->env_dev,
                                   h->desc.n_obstacles, trace, grid, h->stream,
                                   prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
@@ -527,7 +565,7 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
     return KP_E_DEVICE;
   }
   int bp = 1, bn = 1, bc = 1;
-  occupancy_propagate(desc->dynamics, desc->integrator, desc->n_obstacles, &bp);
+  occupancy_propagate(desc->dynamics, desc->integrator, h->prm.tilt_fast, desc->n_obstacles, &bp);
   occupancy_nodes(&bn);
   occupancy_commit(&bc);
   h->grid_prop_max = bp * h->cu_count;
@@ -1037,6 +1075,7 @@ struct kp_batch {
   hipStream_t stream = nullptr;       // the batch's own stream
   hipStream_t user_stream = nullptr;  // the problems' stream
   int dyn = 0, integ = 0, n_obs_max = 0;
+  int fast = 1;                       // every problem takes the fast tilt path
   int prop_max = 1, node_max = 1;     // single-problem grid maxima
   kp_batch_config cfg{};
   hipGraph_t graph = nullptr;
@@ -1072,7 +1111,7 @@ hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_
   const int nc = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
   t = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
   const int nn = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
-  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->table, n, b->n_obs_max,
+  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->fast, b->table, n, b->n_obs_max,
                                         gp < 1 ? 1 : gp, b->stream);
   if (e == hipSuccess) e = launch_post_batch(b->table, n, nc, nn, b->stream);
   return e;
@@ -1144,11 +1183,12 @@ kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_work
   for (int i = 0; i < n; ++i) {
     const kp_problem* h = problems[i];
     if (h->desc.n_obstacles > b->n_obs_max) b->n_obs_max = h->desc.n_obstacles;
+    if (!h->prm.tilt_fast) b->fast = 0;
     if (h->grid_node_max > node_max) node_max = h->grid_node_max;
     if (h->grid_commit_max > node_max) node_max = h->grid_commit_max;
   }
   int bp = 1;
-  occupancy_propagate(b->dyn, b->integ, b->n_obs_max, &bp);
+  occupancy_propagate(b->dyn, b->integ, b->fast, b->n_obs_max, &bp);
   prop_max = bp * problems[0]->cu_count;
   b->prop_max = prop_max;
   b->node_max = node_max;

@@ -65,7 +65,8 @@ static_assert(sizeof(Ctl) <= 4096, "control block size");
 struct Params {
   int32_t n, m, K, cap;
   int32_t lambda_max, n_obs, S, R;
-  int32_t dur_mode, pad_;   // 1: segment of 1 + (w * K >> 32) steps, w = word 1 of tag 1
+  int32_t dur_mode;         // 1: segment of 1 + (w * K >> 32) steps, w = word 1 of tag 1
+  int32_t tilt_fast;        // the state box keeps every RK4 stage's tilt within the polynomial range
   int32_t G[3];
   int32_t na[3];        // fine cells per axis = G * S
   float h, margin, goal_r2, rc;
@@ -153,8 +154,8 @@ struct Timing {
 hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s);
 hipError_t launch_root(const Env* env, Vec12 x_init, hipStream_t s);
 hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t);
-hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
-                            int grid, hipStream_t s, Timing t);
+hipError_t launch_propagate(int dyn, int integ, int fast, const Env* env, int n_obs,
+                            TraceRec* trace, int grid, hipStream_t s, Timing t);
 hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
                          hipStream_t s, Timing t);
 hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
@@ -167,8 +168,8 @@ struct BatchStatus {
   int32_t done, N, nF, lanes, iters_done, goal_id, err, pad;
   unsigned long long lanes_total, valid_total;
 };
-hipError_t launch_propagate_batch(int dyn, int integ, const Env* const* envs, int n, int n_obs_max,
-                                  int grid, hipStream_t s);
+hipError_t launch_propagate_batch(int dyn, int integ, int fast, const Env* const* envs, int n,
+                                  int n_obs_max, int grid, hipStream_t s);
 hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
                              hipStream_t s);
 hipError_t launch_batch_status(const Env* const* envs, int n, BatchStatus* out, hipStream_t s);
@@ -195,7 +196,7 @@ hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* par
                            float inv_bc1, float inv_bc2, hipStream_t s);
 hipError_t launch_log_path(const Env* env, float* x, float* t, int32_t cap_rows, int32_t row0,
                            hipStream_t s);
-int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu);
+int occupancy_propagate(int dyn, int integ, int fast, int n_obs, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
 int occupancy_commit(int* blocks_per_cu);
 size_t propagate_lds_bytes(int n_obs);

@@ -237,41 +237,45 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
   *c = __uint_as_float(__float_as_uint(cv) ^ (((uint32_t)(q + 1) & 2u) << 30));
 }
 
-// sin and cos of a tilt angle (roll, pitch).  For |x| <= 1.6 (the tilts a
-// state box admits, with room for the RK4 stage states) near-minimax
-// polynomials on [-1.6, 1.6] of degree 9 (sin, odd) and 10 (cos, even)
-// apply with no reduction: measured against FP64 sin/cos in FP32 Horner
-// form, sin is within 2.2 ulp and cos within 8.6e-8 absolute.  A wave with
-// any larger angle also runs the full reduction for those lanes.
+// sin and cos of a tilt angle (roll, pitch) or of an RK4 stage's yaw
+// increment.  For |x| <= 1.8, near-minimax polynomials on [-1.8, 1.8] of
+// degree 9 (sin, odd) and 10 (cos, even) apply with no reduction: measured
+// in FP32 Horner form against FP64 sin / cos on 2e6 points, sin is within
+// 2.6 ulp and cos within 1.1e-7 absolute.  FAST: the caller guarantees
+// |x| <= 1.8 (see tilt_range_ok on the host), so no check.  Otherwise a wave
+// with any larger angle also runs the full reduction for those lanes.
+template <bool FAST>
 __device__ __forceinline__ void sincos_tilt(float x, float* s, float* c) {
   const float t = x * x;
-  float ps = __builtin_fmaf(t, 0x1.61f3d4p-19f, -0x1.9fccc6p-13f);
-  ps = __builtin_fmaf(t, ps, 0x1.111106p-7f);
-  ps = __builtin_fmaf(t, ps, -0x1.555556p-3f);
+  float ps = __builtin_fmaf(t, 0x1.5880bep-19f, -0x1.9f1b8cp-13f);
+  ps = __builtin_fmaf(t, ps, 0x1.110dcep-7f);
+  ps = __builtin_fmaf(t, ps, -0x1.555554p-3f);
   float sv = __builtin_fmaf(x * t, ps, x);
-  float pc = __builtin_fmaf(t, -0x1.1ae382p-22f, 0x1.9fb708p-16f);
-  pc = __builtin_fmaf(t, pc, -0x1.6c15cap-10f);
-  pc = __builtin_fmaf(t, pc, 0x1.555554p-5f);
+  float pc = __builtin_fmaf(t, -0x1.13d974p-22f, 0x1.9f1102p-16f);
+  pc = __builtin_fmaf(t, pc, -0x1.6c10e4p-10f);
+  pc = __builtin_fmaf(t, pc, 0x1.55553ep-5f);
   pc = __builtin_fmaf(t, pc, -0.5f);
   float cv = __builtin_fmaf(t, pc, 1.0f);
-  const bool big = !(__builtin_fabsf(x) <= 1.6f);  // NaN too
-  if (__builtin_expect(__ballot(big) != 0ull, 0)) {
-    float s2, c2;
-    sincos_rr(x, &s2, &c2);
-    sv = big ? s2 : sv;
-    cv = big ? c2 : cv;
+  if constexpr (!FAST) {
+    const bool big = !(__builtin_fabsf(x) <= 1.8f);  // NaN too
+    if (__builtin_expect(__ballot(big) != 0ull, 0)) {
+      float s2, c2;
+      sincos_rr(x, &s2, &c2);
+      sv = big ? s2 : sv;
+      cv = big ? c2 : cv;
+    }
   }
   *s = sv;
   *c = cv;
 }
 
 // rigid-body quadcopter, ZYX Euler angles, inertial velocity, body rates
-template <class PP>
+template <bool FAST, class PP>
 __device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const float* u,
                                            float* dx) {
   float sf, cf, st, ct, sp, cp;
-  sincos_tilt(x[3], &sf, &cf);
-  sincos_tilt(x[4], &st, &ct);
+  sincos_tilt<FAST>(x[3], &sf, &cf);
+  sincos_tilt<FAST>(x[4], &st, &ct);
   sincos_rr(x[5], &sp, &cp);
   const float ict = __builtin_amdgcn_rcpf(ct);  // 1 ulp; |theta| stays far from pi/2
   const float P = x[9], Q = x[10], R = x[11];
@@ -293,12 +297,12 @@ __device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const fl
 }
 
 // the quadcopter derivative with sin / cos of the yaw angle supplied
-template <class PP>
+template <bool FAST, class PP>
 __device__ __forceinline__ void deriv_quad_y(const PP& p, const float* x, const float* u, float sp,
                                              float cp, float* dx) {
   float sf, cf, st, ct;
-  sincos_tilt(x[3], &sf, &cf);
-  sincos_tilt(x[4], &st, &ct);
+  sincos_tilt<FAST>(x[3], &sf, &cf);
+  sincos_tilt<FAST>(x[4], &st, &ct);
   const float ict = __builtin_amdgcn_rcpf(ct);
   const float P = x[9], Q = x[10], R = x[11];
   const float a = __builtin_fmaf(Q, sf, R * cf);
@@ -320,26 +324,27 @@ __device__ __forceinline__ void deriv_quad_y(const PP& p, const float* x, const 
 
 // sin / cos of psi0 + d from those of psi0 (angle addition); d is an RK4
 // stage's yaw increment, so sin d and cos d take the short polynomials
+template <bool FAST>
 __device__ __forceinline__ void sincos_shift(float s0, float c0, float d, float* s, float* c) {
   float sd, cd;
-  sincos_tilt(d, &sd, &cd);
+  sincos_tilt<FAST>(d, &sd, &cd);
   *s = __builtin_fmaf(s0, cd, c0 * sd);
   *c = __builtin_fmaf(c0, cd, -(s0 * sd));
 }
 
-template <int DYN, class PP>
+template <int DYN, bool FAST, class PP>
 __device__ __forceinline__ void deriv(const PP& p, const float* x, const float* u, float* dx) {
   if constexpr (DYN == KP_DYN_DI6) deriv_di(p, x, u, dx);
-  else deriv_quad(p, x, u, dx);
+  else deriv_quad<FAST>(p, x, u, dx);
 }
 
-template <int DYN, int INTEG, class PP>
+template <int DYN, int INTEG, bool FAST, class PP>
 __device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u) {
   constexpr int n = Dim<DYN>::n;
   const float h = p.h;
   if constexpr (INTEG == KP_INT_EULER) {
     float k1[n];
-    deriv<DYN>(p, x, u, k1);
+    deriv<DYN, FAST>(p, x, u, k1);
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h, k1[i], x[i]);
   } else if constexpr (DYN == KP_DYN_QUAD12) {
@@ -349,54 +354,54 @@ __device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u
     float sp0, cp0, sp, cp;
     sincos_rr(x[5], &sp0, &cp0);
     float t[n], k[n], acc[n];
-    deriv_quad_y(p, x, u, sp0, cp0, k);
+    deriv_quad_y<FAST>(p, x, u, sp0, cp0, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = k[i];
       t[i] = __builtin_fmaf(hh, k[i], x[i]);
     }
-    sincos_shift(sp0, cp0, hh * k[5], &sp, &cp);
-    deriv_quad_y(p, t, u, sp, cp, k);
+    sincos_shift<FAST>(sp0, cp0, hh * k[5], &sp, &cp);
+    deriv_quad_y<FAST>(p, t, u, sp, cp, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(hh, k[i], x[i]);
     }
-    sincos_shift(sp0, cp0, hh * k[5], &sp, &cp);
-    deriv_quad_y(p, t, u, sp, cp, k);
+    sincos_shift<FAST>(sp0, cp0, hh * k[5], &sp, &cp);
+    deriv_quad_y<FAST>(p, t, u, sp, cp, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(h, k[i], x[i]);
     }
-    sincos_shift(sp0, cp0, h * k[5], &sp, &cp);
-    deriv_quad_y(p, t, u, sp, cp, k);
+    sincos_shift<FAST>(sp0, cp0, h * k[5], &sp, &cp);
+    deriv_quad_y<FAST>(p, t, u, sp, cp, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
   } else {
     const float hh = 0.5f * h;
     const float h6 = h * (1.0f / 6.0f);
     float k1[n];
-    deriv<DYN>(p, x, u, k1);
+    deriv<DYN, FAST>(p, x, u, k1);
     float t[n], k[n], acc[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = k1[i];
       t[i] = __builtin_fmaf(hh, k1[i], x[i]);
     }
-    deriv<DYN>(p, t, u, k);
+    deriv<DYN, FAST>(p, t, u, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(hh, k[i], x[i]);
     }
-    deriv<DYN>(p, t, u, k);
+    deriv<DYN, FAST>(p, t, u, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(h, k[i], x[i]);
     }
-    deriv<DYN>(p, t, u, k);
+    deriv<DYN, FAST>(p, t, u, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
   }
@@ -679,7 +684,7 @@ __device__ __forceinline__ float box_separation(float lx, float ly, float lz, fl
   return fmaxf(s0, s1);
 }
 
-template <int DYN, int INTEG>
+template <int DYN, int INTEG, bool FAST>
 __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, TraceRec* trace) {
   const Params& p = env->p;
   const Dev& d = env->d;
@@ -901,7 +906,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       if (__ballot(alive) == 0ull) break;
       if (alive) {
         const float px = x[0], py = x[1], pz = x[2];
-        integ_step<DYN, INTEG>(sc, x, u);
+        integ_step<DYN, INTEG, FAST>(sc, x, u);
         steps = j + 1;
         bool ok = state_ok_lds<DYN>(bnd, x);
         if (ok) {
@@ -1578,15 +1583,15 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
 // batched launch over a table of problems; the work of each problem is the
 // same either way.
-template <int DYN, int INTEG>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(
+template <int DYN, int INTEG, bool FAST>
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate(
     const Env* __restrict__ env, TraceRec* trace) {
-  propagate_body<DYN, INTEG>(env, trace);
+  propagate_body<DYN, INTEG, FAST>(env, trace);
 }
-template <int DYN, int INTEG>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate_batch(
+template <int DYN, int INTEG, bool FAST>
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate_batch(
     const Env* const* __restrict__ envs) {
-  propagate_body<DYN, INTEG>(envs[blockIdx.y], nullptr);
+  propagate_body<DYN, INTEG, FAST>(envs[blockIdx.y], nullptr);
 }
 
 __global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
@@ -1669,23 +1674,27 @@ hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t) {
   return hipGetLastError();
 }
 
-template <int DYN, int INTEG>
+template <int DYN, int INTEG, bool FAST>
 static hipError_t launch_prop_t(const Env* env, int n_obs, TraceRec* trace, int grid,
                                 hipStream_t s, Timing t) {
-  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG>), dim3(grid), dim3(kPropBlock),
+  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG, FAST>), dim3(grid), dim3(kPropBlock),
                         (uint32_t)propagate_lds_bytes(n_obs), s, t.start, t.stop, 0, env, trace);
   return hipGetLastError();
 }
 
-hipError_t launch_propagate(int dyn, int integ, const Env* env, int n_obs, TraceRec* trace,
-                            int grid, hipStream_t s, Timing t) {
+// fast: the problem's state box keeps every tilt angle the quadcopter's RK4
+// stages can reach inside the polynomial range (no per-call range check)
+hipError_t launch_propagate(int dyn, int integ, int fast, const Env* env, int n_obs,
+                            TraceRec* trace, int grid, hipStream_t s, Timing t) {
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER>(env, n_obs, trace, grid, s, t);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(env, n_obs, trace, grid, s, t);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4>(env, n_obs, trace, grid, s, t);
-  if (dyn == KP_DYN_QUAD12 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(env, n_obs, trace, grid, s, t);
-  return launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(env, n_obs, trace, grid, s, t);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(env, n_obs, trace, grid, s, t);
+  if (integ == KP_INT_EULER)
+    return fast ? launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(env, n_obs, trace, grid, s, t)
+                : launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(env, n_obs, trace, grid, s, t);
+  return fast ? launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(env, n_obs, trace, grid, s, t)
+              : launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(env, n_obs, trace, grid, s, t);
 }
 
 hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
@@ -1715,24 +1724,26 @@ hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t) {
   return hipGetLastError();
 }
 
-template <int DYN, int INTEG>
+template <int DYN, int INTEG, bool FAST>
 static hipError_t launch_prop_batch_t(const Env* const* envs, int n, int n_obs_max, int grid,
                                       hipStream_t s) {
-  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG>), dim3(grid, n), dim3(kPropBlock),
+  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG, FAST>), dim3(grid, n), dim3(kPropBlock),
                      (uint32_t)propagate_lds_bytes(n_obs_max), s, envs);
   return hipGetLastError();
 }
 
-hipError_t launch_propagate_batch(int dyn, int integ, const Env* const* envs, int n, int n_obs_max,
-                                  int grid, hipStream_t s) {
+hipError_t launch_propagate_batch(int dyn, int integ, int fast, const Env* const* envs, int n,
+                                  int n_obs_max, int grid, hipStream_t s) {
   if (grid < 1) grid = 1;
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_EULER>(envs, n, n_obs_max, grid, s);
+    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_EULER, false>(envs, n, n_obs_max, grid, s);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
-    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_RK4>(envs, n, n_obs_max, grid, s);
-  if (dyn == KP_DYN_QUAD12 && integ == KP_INT_EULER)
-    return launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER>(envs, n, n_obs_max, grid, s);
-  return launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4>(envs, n, n_obs_max, grid, s);
+    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_RK4, false>(envs, n, n_obs_max, grid, s);
+  if (integ == KP_INT_EULER)
+    return fast ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, true>(envs, n, n_obs_max, grid, s)
+                : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, false>(envs, n, n_obs_max, grid, s);
+  return fast ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, true>(envs, n, n_obs_max, grid, s)
+              : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, false>(envs, n, n_obs_max, grid, s);
 }
 
 hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
@@ -1759,21 +1770,27 @@ hipError_t launch_path(const Env* env, int32_t node, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int DYN, int INTEG>
+template <int DYN, int INTEG, bool FAST>
 static int occ_prop_t(int n_obs) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG>, kPropBlock,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG, FAST>, kPropBlock,
                                                     propagate_lds_bytes(n_obs)) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-int occupancy_propagate(int dyn, int integ, int n_obs, int* blocks_per_cu) {
+int occupancy_propagate(int dyn, int integ, int fast, int n_obs, int* blocks_per_cu) {
   int nb;
-  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER) nb = occ_prop_t<KP_DYN_DI6, KP_INT_EULER>(n_obs);
-  else if (dyn == KP_DYN_DI6) nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4>(n_obs);
-  else if (integ == KP_INT_EULER) nb = occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER>(n_obs);
-  else nb = occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4>(n_obs);
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
+    nb = occ_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(n_obs);
+  else if (dyn == KP_DYN_DI6)
+    nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(n_obs);
+  else if (integ == KP_INT_EULER)
+    nb = fast ? occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(n_obs)
+              : occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(n_obs);
+  else
+    nb = fast ? occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(n_obs)
+              : occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(n_obs);
   *blocks_per_cu = nb;
   return nb;
 }
