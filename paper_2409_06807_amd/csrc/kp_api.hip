@@ -1076,6 +1076,7 @@ struct kp_batch {
   hipStream_t user_stream = nullptr;  // the problems' stream
   int dyn = 0, integ = 0, n_obs_max = 0;
   int fast = 1;                       // every problem takes the fast tilt path
+  int learned = 0;                    // some problem has a learned proposal (set per plan)
   int prop_max = 1, node_max = 1;     // single-problem grid maxima
   kp_batch_config cfg{};
   hipGraph_t graph = nullptr;
@@ -1105,6 +1106,14 @@ void drop_graph(kp_batch* b) {
 // one iteration for every problem: grids from per-problem bounds (capped)
 hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_ub) {
   const int n = (int)b->P.size();
+  if (b->learned) {
+    // the proposal network of every problem that has one, before its expansion
+    const long long rpb = mlp_head_rows_per_block();
+    long long hb = (lanes_ub + rpb - 1) / rpb;
+    const int cap = mlp_head_grid_max(b->P[0]->cu_count);
+    hipError_t e = launch_mlp_head_batch(b->table, n, (int)(hb < cap ? hb : cap), b->stream);
+    if (e != hipSuccess) return e;
+  }
   long long t = (lanes_ub + kPropBlock - 1) / kPropBlock;
   const int gp = (int)(t < b->cfg.prop_blocks ? t : b->cfg.prop_blocks);
   t = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
@@ -1248,7 +1257,15 @@ kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms) 
   // order after the work already queued on the problems' stream
   hipError_t e = hipStreamSynchronize(b->user_stream);
   if (e != hipSuccess) return bhip(b, e, "problem stream");
-  for (int i = 0; i < n; ++i) b->P[i]->ctl_fresh = false;
+  int learned = 0;
+  for (int i = 0; i < n; ++i) {
+    b->P[i]->ctl_fresh = false;
+    if (b->P[i]->prm.mix_thr != 0ull) learned = 1;
+  }
+  if (learned != b->learned) {
+    b->learned = learned;
+    drop_graph(b);  // the captured iterations gain or lose the network pass
+  }
   kp_status st = batch_status(b);
   if (st != KP_OK) return st;
   std::vector<uint32_t> it0((size_t)n);

@@ -186,6 +186,7 @@ hipError_t launch_mlp_pack(const float* params, uint4* packed, hipStream_t s);
 hipError_t launch_mlp_forward(const uint4* packed, const float* x, int32_t rows, float* out,
                               hipStream_t s);
 hipError_t launch_mlp_head(const Env* env, int grid, hipStream_t s, Timing t);
+hipError_t launch_mlp_head_batch(const Env* const* envs, int n, int grid, hipStream_t s);
 int mlp_head_grid_max(int cu_count);
 int mlp_head_rows_per_block();
 hipError_t launch_mlp_grad(const uint4* packed, const float* x, const float* t, int32_t n_rows,

@@ -388,13 +388,13 @@ __global__ __launch_bounds__(kInfBlock) void k_mlp_forward(const u32x4* __restri
 
 // Per frontier entry e (the layout the expansion lanes index by e = lane /
 // lambda): Gaussian mean (4 floats) and standard deviation (4 floats).
-__global__ __launch_bounds__(kInfBlock) void k_mlp_head(const Env* __restrict__ env) {
+__device__ __forceinline__ void head_body(const Env* __restrict__ env) {
   __shared__ u32x4 sfrag[E_FWD];
   __shared__ float sbias[N_BIAS];
   const Params& p = env->p;
   const Dev& d = env->d;
   const Ctl* c = d.ctl;
-  if (c->done) return;
+  if (c->done || p.mix_thr == 0ull) return;
   const int32_t nF = c->nF, f_expl = c->f_expl, f_base = c->f_base;
   const int passes = (nF + kInfRows - 1) / kInfRows;
   if ((int)blockIdx.x * kInfWaves >= passes) return;
@@ -440,6 +440,14 @@ __global__ __launch_bounds__(kInfBlock) void k_mlp_head(const Env* __restrict__ 
       }
     }
   }
+}
+
+__global__ __launch_bounds__(kInfBlock) void k_mlp_head(const Env* __restrict__ env) {
+  head_body(env);
+}
+// one grid row per problem of a batch; problems without a proposal return at once
+__global__ __launch_bounds__(kInfBlock) void k_mlp_head_batch(const Env* const* __restrict__ envs) {
+  head_body(envs[blockIdx.y]);
 }
 
 // ---------------------------------------------------------------------------
@@ -732,6 +740,12 @@ int mlp_head_grid_max(int cu_count) { return cu_count; }
 hipError_t launch_mlp_head(const Env* env, int grid, hipStream_t s, Timing t) {
   if (grid < 1) grid = 1;
   hipExtLaunchKernelGGL(k_mlp_head, dim3(grid), dim3(kInfBlock), 0, s, t.start, t.stop, 0, env);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_head_batch(const Env* const* envs, int n, int grid, hipStream_t s) {
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_mlp_head_batch, dim3(grid, n), dim3(kInfBlock), 0, s, envs);
   return hipGetLastError();
 }
 

@@ -153,3 +153,35 @@ def test_autotuner_keeps_results(tmp_path):
     cfg, table = autotune.tune(B, reset, "test-sig", cache_path=str(tmp_path / "a.json"), space=space)
     assert cfg in space and len(table) == 3
     B.close()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_with_learned_proposals_equals_single(graph):
+    # problems with a learned proposal get their network pass inside the batch
+    import paper_2409_06807_amd as kp
+    from paper_2409_06807_amd import Planner, Batch
+    import torch
+    from workloads import mlp_inputs
+    _say(f"batch with learned proposals, graph={graph}")
+    ps = small_batch()[:4]
+    params = torch.tensor(mlp_inputs.params(31, scale=1.0, out_scale=1.0), dtype=torch.float32,
+                          device="cuda:0")
+    packed = kp.mlp_pack(params)
+    learned = [True, False, True, True]
+    ref = []
+    for p, l in zip(ps, learned):
+        G = Planner(p)
+        if l:
+            G.set_proposal(packed, 0.7)
+        r = G.plan()
+        ref.append((r, G.copy_tree()))
+        G.close()
+    planners = [Planner(p) for p in ps]
+    for G, l in zip(planners, learned):
+        if l:
+            G.set_proposal(packed, 0.7)
+    B = Batch(planners)
+    B.set_config(use_graph=graph)
+    res, _ = B.plan()
+    check_same(ref, planners, res)
+    B.close()
