@@ -292,7 +292,7 @@ def batched_leg(n_queries, batch_seed=3):
     run()
     default = dict(config=B.config(), **run())
     cfg, table = autotune.tune(B, reset, autotune.signature(ps, "mi355x"),
-                               cache_path=tempfile.mktemp(suffix=".json"))
+                               cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
     tuned = dict(config=cfg, **run())
     B.close()
     st = [r["status"] for r in seq]

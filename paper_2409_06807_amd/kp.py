@@ -392,6 +392,8 @@ class Planner:
         return self._proposal[1][:rows].cpu().numpy()
 
     def log_path(self, node: int, X, T, row0: int) -> int:
+        _need(X, MLP_INPUTS, "X")
+        _need(T, 4, "T", rows=int(X.shape[0]))
         n = C.c_int32(0)
         self._check(self.lib.kp_log_path(self.h, int(node), C.c_void_p(X.data_ptr()),
                                          C.c_void_p(T.data_ptr()), int(X.shape[0]), int(row0),
@@ -425,6 +427,17 @@ class Planner:
 # ---------------------------------------------------------------------------
 # learned proposal: network kernels without a planner handle
 # ---------------------------------------------------------------------------
+def _need(t, cols, name, rows=None):
+    """A contiguous FP32 CUDA tensor of shape (rows, cols): the kernels index
+    it by these sizes, so anything else is refused before any launch."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous() and t.dim() == 2 and t.shape[1] == cols
+            and (rows is None or t.shape[0] >= rows)):
+        raise KPError(E_ARG, f"{name}: need a contiguous float32 CUDA tensor of shape "
+                             f"({'>= ' + str(rows) if rows is not None else 'rows'}, {cols})")
+
+
 def _stream_ptr(t):
     import torch
     return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
@@ -438,6 +451,11 @@ def _mlp_check(st, what):
 def mlp_pack(params, packed=None):
     """FP32 parameters (device tensor of MLP_PARAMS floats) -> packed tensor."""
     import torch
+    if not (params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()
+            and params.numel() == MLP_PARAMS):
+        raise KPError(E_ARG, f"params: need {MLP_PARAMS} contiguous float32 CUDA values")
+    if packed is not None and packed.numel() * packed.element_size() < MLP_PACKED_BYTES:
+        raise KPError(E_ARG, "packed: too small")
     if packed is None:
         packed = torch.empty(MLP_PACKED_BYTES, dtype=torch.uint8, device=params.device)
     _mlp_check(load_library().kp_mlp_pack(C.c_void_p(params.data_ptr()), C.c_void_p(packed.data_ptr()),
@@ -448,6 +466,7 @@ def mlp_pack(params, packed=None):
 def mlp_forward(packed, X):
     """Raw outputs (rows x 8) of the rows of X (rows x 16, FP32 device tensor)."""
     import torch
+    _need(X, MLP_INPUTS, "X")
     rows = int(X.shape[0])
     out = torch.zeros((rows, MLP_OUTPUTS), dtype=torch.float32, device=X.device)
     _mlp_check(load_library().kp_mlp_forward(C.c_void_p(packed.data_ptr()), C.c_void_p(X.data_ptr()),
@@ -463,6 +482,8 @@ def mlp_partials(batch: int) -> int:
 def mlp_grad(packed, X, T, n_ctrl: int, batch: int, key: int = 0, step: int = 0):
     """Partial gradients (ceil(batch/64) x MLP_PARAMS) and partial losses."""
     import torch
+    _need(X, MLP_INPUTS, "X")
+    _need(T, 4, "T", rows=int(X.shape[0]))
     nb = mlp_partials(batch)
     partials = torch.empty((nb, MLP_PARAMS), dtype=torch.float32, device=X.device)
     loss = torch.empty(nb, dtype=torch.float32, device=X.device)
@@ -475,6 +496,10 @@ def mlp_grad(packed, X, T, n_ctrl: int, batch: int, key: int = 0, step: int = 0)
 
 def mlp_adam(params, m1, m2, partials, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam step on params, m1, m2 in place."""
+    _need(partials, MLP_PARAMS, "partials")
+    for t, name in ((params, "params"), (m1, "m1"), (m2, "m2")):
+        if not (t.is_cuda and t.is_contiguous() and t.numel() == MLP_PARAMS):
+            raise KPError(E_ARG, f"{name}: need {MLP_PARAMS} contiguous float32 CUDA values")
     _mlp_check(load_library().kp_mlp_adam(
         C.c_void_p(params.data_ptr()), C.c_void_p(m1.data_ptr()), C.c_void_p(m2.data_ptr()),
         C.c_void_p(partials.data_ptr()), int(partials.shape[0]), int(step), C.c_float(lr),
@@ -485,6 +510,11 @@ def mlp_train(params, m1, m2, packed, X, T, n_ctrl: int, batch: int, steps: int,
               key: int, step0: int = 0):
     """`steps` minibatch Adam steps; returns the per-step losses (device tensor)."""
     import torch
+    _need(X, MLP_INPUTS, "X")
+    _need(T, 4, "T", rows=int(X.shape[0]))
+    for t, name in ((params, "params"), (m1, "m1"), (m2, "m2")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == MLP_PARAMS):
+            raise KPError(E_ARG, f"{name}: need {MLP_PARAMS} contiguous float32 CUDA values")
     nb = mlp_partials(batch)
     partials = torch.empty((nb, MLP_PARAMS), dtype=torch.float32, device=X.device)
     loss = torch.empty((max(steps, 1), nb), dtype=torch.float32, device=X.device)

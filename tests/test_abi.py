@@ -126,3 +126,16 @@ def test_struct_layouts_match_header(lib):
     d.duration_mode = 1
     d.reserved = 5
     assert lib.kp_workspace_bytes(C.byref(d)) == 0
+
+
+def test_binding_refuses_bad_network_tensors():
+    # shapes, dtypes and devices are checked before anything reaches the library
+    import torch
+    import paper_2409_06807_amd as kp
+    X = torch.zeros((4, 16))
+    with pytest.raises(kp.KPError):
+        kp.mlp_forward(torch.zeros(kp.MLP_PACKED_BYTES, dtype=torch.uint8), X)
+    with pytest.raises(kp.KPError):
+        kp.mlp_pack(torch.zeros(kp.MLP_PARAMS))
+    with pytest.raises(kp.KPError):
+        kp.mlp_grad(None, X, torch.zeros((4, 4)), 4, 4)
