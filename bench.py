@@ -50,7 +50,8 @@ PEAK_FP32_TFLOPS = 157.3
 # the kernel sources still hash to what was profiled.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_propagate_traffic.json")
 KERNEL_SOURCES = ("paper_2409_06807_amd/csrc/kp_kernels.hip",
-                  "paper_2409_06807_amd/csrc/kp_internal.h")
+                  "paper_2409_06807_amd/csrc/kp_internal.h",
+                  "paper_2409_06807_amd/csrc/kp_device.h")
 
 
 def kernel_source_hash() -> str:
