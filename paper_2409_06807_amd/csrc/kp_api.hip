@@ -160,6 +160,23 @@ struct kp_problem {
 
 namespace {
 
+// the fields of two descriptions that shape a tree (all but capacity, budgets
+// and the obstacle pointer), compared one by one
+bool same_problem(const kp_problem_desc& a, const kp_problem_desc& b) {
+  auto eq = [](const void* x, const void* y, size_t n) { return std::memcmp(x, y, n) == 0; };
+  return a.dynamics == b.dynamics && a.integrator == b.integrator && a.steps == b.steps &&
+         eq(&a.h, &b.h, sizeof a.h) && eq(a.dyn_params, b.dyn_params, sizeof a.dyn_params) &&
+         eq(a.u_lo, b.u_lo, sizeof a.u_lo) && eq(a.u_hi, b.u_hi, sizeof a.u_hi) &&
+         eq(a.x_lo, b.x_lo, sizeof a.x_lo) && eq(a.x_hi, b.x_hi, sizeof a.x_hi) &&
+         a.n_obstacles == b.n_obstacles && eq(&a.margin, &b.margin, sizeof a.margin) &&
+         eq(a.x_init, b.x_init, sizeof a.x_init) &&
+         eq(a.goal_center, b.goal_center, sizeof a.goal_center) &&
+         eq(&a.goal_radius, &b.goal_radius, sizeof a.goal_radius) &&
+         eq(a.grid, b.grid, sizeof a.grid) && a.sub == b.sub && a.lambda_max == b.lambda_max &&
+         eq(&a.delta, &b.delta, sizeof a.delta) && eq(&a.epsilon, &b.epsilon, sizeof a.epsilon) &&
+         a.seed == b.seed && a.duration_mode == b.duration_mode;
+}
+
 kp_status fail(kp_problem* h, kp_status st, const std::string& msg) {
   if (h) h->err = msg;
   return st;
@@ -831,18 +848,16 @@ kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in) {
 
 kp_status kp_transfer_tree(kp_problem* src, kp_problem* dst) {
   if (!src || !dst || src == dst) return KP_E_ARG;
-  const kp_problem_desc& a = src->desc;
-  const kp_problem_desc& b = dst->desc;
-  if (a.dynamics != b.dynamics || a.integrator != b.integrator || a.steps != b.steps ||
-      a.grid[0] != b.grid[0] || a.grid[1] != b.grid[1] || a.grid[2] != b.grid[2] ||
-      a.sub != b.sub || a.seed != b.seed || a.duration_mode != b.duration_mode)
+  // every field that shapes the tree must agree; capacity and budgets may differ
+  if (!same_problem(src->desc, dst->desc) || src->obs != dst->obs)
     return fail(dst, KP_E_ARG, "kp_transfer_tree: problems differ beyond their capacity");
   if (src->stage != 0) return fail(dst, KP_E_ORDER, "kp_transfer_tree: source mid-iteration");
   kp_status st = sync_ctl(src);
   if (st != KP_OK) return fail(dst, st, src->err);
   const int32_t N = src->hctl->N;
   const int32_t it = src->hctl->it;
-  if (N > b.node_cap) return fail(dst, KP_E_ARG, "kp_transfer_tree: tree larger than the capacity");
+  if (N > dst->desc.node_cap)
+    return fail(dst, KP_E_ARG, "kp_transfer_tree: tree larger than the capacity");
   hipError_t e = hipStreamSynchronize(dst->stream);
   // device to device on the destination's stream; the source is idle (synchronised above)
   const size_t ps = (size_t)src->L.capP * 4, pd = (size_t)dst->L.capP * 4;

@@ -367,11 +367,14 @@ def test_transfer_tree_equals_host_load_and_continues_identically():
         assert ra[k] == rb[k], k
     ta, tb = A.copy_tree(), B.copy_tree()
     assert np.array_equal(ta["parent"], tb["parent"]) and np.array_equal(ta["x"], tb["x"])
-    # a handle of another problem is refused
-    C = Planner(dict(p, seed=4, node_cap=6000))
+    # a handle of another problem is refused: another seed, margin or obstacle set
     from paper_2409_06807_amd import KPError
-    with pytest.raises(KPError):
-        C.transfer_from(G)
+    for other in (dict(p, seed=4), dict(p, margin=np.float32(0.2)),
+                  dict(p, obstacles=p["obstacles"][:-1])):
+        C = Planner(dict(other, node_cap=6000))
+        with pytest.raises(KPError):
+            C.transfer_from(G)
+        C.close()
 
 
 def test_plan_adaptive_capacity():
