@@ -34,25 +34,94 @@ __device__ __forceinline__ unsigned long long lanes_below() {
   return (1ull << __lane_id()) - 1ull;
 }
 
+// Wave reductions on the DPP path.  A DPP move is an operand modifier of a
+// VALU instruction, so each step costs a few cycles instead of an LDS
+// permute round trip; on a lone wave (small frontiers) these latencies add
+// up to microseconds per tile.  The six steps: xor 1 and xor 2 inside each
+// quad, the half-row and row mirrors (8- and 16-lane results), then the
+// broadcasts of lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3.
+// Lane 63 then holds the result of all 64 lanes, and the callers read it
+// from there (wave-uniform).  Every lane of the wave must be active.
+constexpr int kDppQuadXor1 = 0xb1;   // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4e;   // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppBcast15 = 0x142;
+constexpr int kDppBcast31 = 0x143;
+
+// lanes of rows outside ROWS, and lanes without a source, get `old`
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_mov64(unsigned long long old,
+                                                        unsigned long long v) {
+  const uint32_t lo = dpp_mov<CTRL, ROWS>((uint32_t)old, (uint32_t)v);
+  const uint32_t hi = dpp_mov<CTRL, ROWS>((uint32_t)(old >> 32), (uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+template <class Op>
+__device__ __forceinline__ uint32_t dpp_reduce_u32(uint32_t v, uint32_t ident, Op op) {
+  v = op(v, dpp_mov<kDppQuadXor1, 0xf>(ident, v));
+  v = op(v, dpp_mov<kDppQuadXor2, 0xf>(ident, v));
+  v = op(v, dpp_mov<kDppHalfMirror, 0xf>(ident, v));
+  v = op(v, dpp_mov<kDppMirror, 0xf>(ident, v));
+  v = op(v, dpp_mov<kDppBcast15, 0xa>(ident, v));
+  v = op(v, dpp_mov<kDppBcast31, 0xc>(ident, v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+template <class Op>
+__device__ __forceinline__ unsigned long long dpp_reduce_u64(unsigned long long v,
+                                                             unsigned long long ident, Op op) {
+  v = op(v, dpp_mov64<kDppQuadXor1, 0xf>(ident, v));
+  v = op(v, dpp_mov64<kDppQuadXor2, 0xf>(ident, v));
+  v = op(v, dpp_mov64<kDppHalfMirror, 0xf>(ident, v));
+  v = op(v, dpp_mov64<kDppMirror, 0xf>(ident, v));
+  v = op(v, dpp_mov64<kDppBcast15, 0xa>(ident, v));
+  v = op(v, dpp_mov64<kDppBcast31, 0xc>(ident, v));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  return dpp_reduce_u32(v, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+}
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-  return v;
+  return __uint_as_float(dpp_reduce_u32(__float_as_uint(v), 0x7f800000u, [](uint32_t a, uint32_t b) {
+    return __float_as_uint(fminf(__uint_as_float(a), __uint_as_float(b)));
+  }));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+  return __uint_as_float(dpp_reduce_u32(__float_as_uint(v), 0xff800000u, [](uint32_t a, uint32_t b) {
+    return __float_as_uint(fmaxf(__uint_as_float(a), __uint_as_float(b)));
+  }));
 }
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  return dpp_reduce_u64(v, 0ull, [](unsigned long long a, unsigned long long b) { return a + b; });
+}
+__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v) {
+  return dpp_reduce_u64(v, 0ull, [](unsigned long long a, unsigned long long b) { return a | b; });
 }
 __device__ __forceinline__ double wave_max_f64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  return __longlong_as_double((long long)dpp_reduce_u64(
+      (unsigned long long)__double_as_longlong(v), 0xfff0000000000000ull,
+      [](unsigned long long a, unsigned long long b) {
+        return (unsigned long long)__double_as_longlong(
+            fmax(__longlong_as_double((long long)a), __longlong_as_double((long long)b)));
+      }));
+}
+
+// min / max over the four lanes of each quad, in every lane of the quad
+__device__ __forceinline__ float quad_min(float v) {
+  v = fminf(v, __uint_as_float(dpp_mov<kDppQuadXor1, 0xf>(0x7f800000u, __float_as_uint(v))));
+  return fminf(v, __uint_as_float(dpp_mov<kDppQuadXor2, 0xf>(0x7f800000u, __float_as_uint(v))));
+}
+__device__ __forceinline__ float quad_max(float v) {
+  v = fmaxf(v, __uint_as_float(dpp_mov<kDppQuadXor1, 0xf>(0xff800000u, __float_as_uint(v))));
+  return fmaxf(v, __uint_as_float(dpp_mov<kDppQuadXor2, 0xf>(0xff800000u, __float_as_uint(v))));
 }
 
 // Exclusive prefix of small per-lane counts (0..31) across the wave from five
@@ -665,11 +734,6 @@ constexpr size_t prop_lds_bytes(int n_obs) {
 static_assert(prop_lds_bytes(KP_MAX_OBSTACLES) <= 65536, "propagate LDS above 64 KiB");
 size_t propagate_lds_bytes(int n_obs) { return prop_lds_bytes(n_obs); }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-  return v;
-}
 
 // Separation of two closed boxes: the largest gap along any axis between a
 // face of one and the facing face of the other.  The boxes intersect
@@ -848,15 +912,13 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       float q0 = active ? x[0] - p.rc : big, q1 = active ? x[1] - p.rc : big;
       float q2 = active ? x[2] - p.rc : big, q3 = active ? x[0] + p.rc : -big;
       float q4 = active ? x[1] + p.rc : -big, q5 = active ? x[2] + p.rc : -big;
-#pragma unroll
-      for (int o = 1; o < kLaneGroup; o <<= 1) {
-        q0 = fminf(q0, __shfl_xor(q0, o));
-        q1 = fminf(q1, __shfl_xor(q1, o));
-        q2 = fminf(q2, __shfl_xor(q2, o));
-        q3 = fmaxf(q3, __shfl_xor(q3, o));
-        q4 = fmaxf(q4, __shfl_xor(q4, o));
-        q5 = fmaxf(q5, __shfl_xor(q5, o));
-      }
+      static_assert(kLaneGroup == 4, "group boxes are reduced inside quads");
+      q0 = quad_min(q0);
+      q1 = quad_min(q1);
+      q2 = quad_min(q2);
+      q3 = quad_max(q3);
+      q4 = quad_max(q4);
+      q5 = quad_max(q5);
       // in the passes below lane l serves group l % 16 and union entries
       // c0 + l / 16, so one pass tests four entries against all 16 groups
       const uint32_t gq = lane & (kGroupsPerWave - 1);
@@ -890,7 +952,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       }
     }
     // every list is read to the same even length; pad with the sentinel
-    const uint32_t kmax = (__builtin_amdgcn_readfirstlane(wave_max_u32(mycnt)) + 1u) & ~1u;
+    const uint32_t kmax = (wave_max_u32(mycnt) + 1u) & ~1u;
     for (uint32_t k = mycnt + (lane & (kLaneGroup - 1)); k < kmax; k += kLaneGroup)
       const_cast<uint16_t*>(my)[k] = (uint16_t)n_obs;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -961,7 +1023,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       unsigned long long pending = __ballot(active);
       while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
-        const uint32_t k0 = (uint32_t)__shfl((int)key, leader);
+        const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const unsigned long long match = __ballot(key == k0);
         if ((int)__lane_id() == leader) {
           unsigned long long* ctr = (k0 & 1u) ? d.nv : d.ni;
@@ -1472,11 +1534,9 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
       unsigned long long pending = __ballot(lane < cnt);
       while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
-        const uint32_t r0 = (uint32_t)__shfl((int)key, leader);
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const unsigned long long match = __ballot(key == r0);
-        unsigned long long bits = (key == r0) ? (1ull << (cl & 63u)) : 0ull;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
+        const unsigned long long bits = wave_or_u64((key == r0) ? (1ull << (cl & 63u)) : 0ull);
         if ((int)lane == leader) {
           atomicOr(&d.visited[r0], bits);
           d.avail[r0] = 1;
