@@ -19,6 +19,11 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # packed FP32 instructions stay off (toolchain correctness on this target)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # with packed FP32 off, the SLP vectorizer only packs booleans into
+    # 16-bit lanes (compare, select 0/1, shift, bit-op) where a compare
+    # into a lane mask and a scalar AND would do; off, the propagate kernel
+    # needs fewer instructions and registers
+    "-fno-slp-vectorize",
     "-Wall", "-Wno-unused-function",
 ]
 
