@@ -47,11 +47,12 @@ PEAK_FP32_TFLOPS = 157.3
 
 # HBM bytes per propagate launch from two rocprofv3 counter passes (FETCH_SIZE,
 # WRITE_SIZE), already scaled by the copy-kernel calibration; only used while
-# the kernel sources still hash to what was profiled.
+# the kernel sources and the build flags still hash to what was profiled.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_propagate_traffic.json")
 KERNEL_SOURCES = ("paper_2409_06807_amd/csrc/kp_kernels.hip",
                   "paper_2409_06807_amd/csrc/kp_internal.h",
-                  "paper_2409_06807_amd/csrc/kp_device.h")
+                  "paper_2409_06807_amd/csrc/kp_device.h",
+                  "paper_2409_06807_amd/build.py")
 
 
 def kernel_source_hash() -> str:

@@ -1642,9 +1642,11 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
 
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
 // batched launch over a table of problems; the work of each problem is the
-// same either way.
+// same either way.  Waves per SIMD: the branch-free quadcopter kernel fits
+// 96 registers without spills and runs 5; the variant with the tilt range
+// check and the batched quadcopter kernel would spill there and keep 4.
 template <int DYN, int INTEG, bool FAST>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate(
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : (FAST ? 5 : 4)))) void k_propagate(
     const Env* __restrict__ env, TraceRec* trace) {
   propagate_body<DYN, INTEG, FAST>(env, trace);
 }
