@@ -197,8 +197,12 @@ kp_status hip_fail(kp_problem* h, hipError_t e, const char* what) {
 //   pitch: |theta'| = |q cos phi - r sin phi| <= W_y + W_z;
 //   roll: |phi'| <= W_x + (W_y + W_z) tan(theta_max);
 //   yaw: |psi'| <= (W_y + W_z) / cos(theta_max), times h for a stage increment.
-bool tilt_range_ok(const kp_problem_desc& d) {
+// The same variant also tests the state box as |x| <= hi outside position,
+// so it further needs lo = -hi exactly in those coordinates.
+bool quad_fast_ok(const kp_problem_desc& d) {
   if (d.dynamics != KP_DYN_QUAD12) return false;
+  for (int i = 3; i < 12; ++i)
+    if (!(d.x_lo[i] == -d.x_hi[i])) return false;
   auto amax = [&](int i) { return std::fmax(std::fabs((double)d.x_lo[i]), std::fabs((double)d.x_hi[i])); };
   const double h = d.h, lim = 1.75;
   const double I[3] = {d.dyn_params[2], d.dyn_params[3], d.dyn_params[4]};
@@ -267,7 +271,7 @@ void fill_params(kp_problem* h) {
   p.dIzx = p.Izz - p.Ixx;
   p.dIxy = p.Ixx - p.Iyy;
   p.dur_mode = d.duration_mode;
-  p.tilt_fast = tilt_range_ok(d) ? 1 : 0;
+  p.tilt_fast = quad_fast_ok(d) ? 1 : 0;
   p.key0 = (uint32_t)d.seed;
   p.key1 = (uint32_t)(d.seed >> 32);
   p.delta = d.delta;

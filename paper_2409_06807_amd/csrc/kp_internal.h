@@ -67,6 +67,7 @@ struct Params {
   int32_t lambda_max, n_obs, S, R;
   int32_t dur_mode;         // 1: segment of 1 + (w * K >> 32) steps, w = word 1 of tag 1
   int32_t tilt_fast;        // the state box keeps every RK4 stage's tilt within the polynomial range
+                            // and is symmetric about zero outside position
   int32_t G[3];
   int32_t na[3];        // fine cells per axis = G * S
   float h, margin, goal_r2, rc;

@@ -311,7 +311,7 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
 // degree 9 (sin, odd) and 10 (cos, even) apply with no reduction: measured
 // in FP32 Horner form against FP64 sin / cos on 2e6 points, sin is within
 // 2.6 ulp and cos within 1.1e-7 absolute.  FAST: the caller guarantees
-// |x| <= 1.8 (see tilt_range_ok on the host), so no check.  Otherwise a wave
+// |x| <= 1.8 (see quad_fast_ok on the host), so no check.  Otherwise a wave
 // with any larger angle also runs the full reduction for those lanes.
 template <bool FAST>
 __device__ __forceinline__ void sincos_tilt(float x, float* s, float* c) {
@@ -509,6 +509,22 @@ __device__ __forceinline__ bool state_ok_lds(const float* __restrict__ b, const 
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < n; ++i) ok &= (x[i] >= bb[i]) & (x[i] <= bb[12 + i]);
+  return ok;
+}
+
+// The quadcopter test when the box is symmetric about zero in every
+// coordinate but position (lo = -hi, checked on the host): lo <= x <= hi is
+// then exactly |x| <= hi (negation is exact, and a NaN fails), one compare
+// with a free absolute-value modifier instead of two; position keeps both.
+__device__ __forceinline__ bool state_ok_lds_sym(const float* __restrict__ b, const float* x) {
+  const float4* b4 = reinterpret_cast<const float4*>(b);
+  const float4 lo = b4[0], h0 = b4[3], h1 = b4[4], h2 = b4[5];
+  const float hi[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
+  bool ok = (x[0] >= lo.x) & (x[1] >= lo.y) & (x[2] >= lo.z);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ok &= x[i] <= hi[i];
+#pragma unroll
+  for (int i = 3; i < 12; ++i) ok &= __builtin_fabsf(x[i]) <= hi[i];
   return ok;
 }
 
@@ -970,7 +986,9 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
         const float px = x[0], py = x[1], pz = x[2];
         integ_step<DYN, INTEG, FAST>(sc, x, u);
         steps = j + 1;
-        bool ok = state_ok_lds<DYN>(bnd, x);
+        bool ok;
+        if constexpr (DYN == KP_DYN_QUAD12 && FAST) ok = state_ok_lds_sym(bnd, x);
+        else ok = state_ok_lds<DYN>(bnd, x);
         if (ok) {
           const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
           const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;

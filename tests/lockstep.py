@@ -284,6 +284,13 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
             tr = G.trace(trace, W.num_lanes())
             check_proposal(p, W, G, tr, proposal, rep, it)
             recs = W.expand_all(controls=np.pad(tr["u"][:, :W.m], ((0, 0), (0, 4 - W.m))))
+        # the kernel's own wave-summed counters agree with its per-lane trace
+        gs1 = G.stats()
+        got = (gs1["lanes_total"] - gs["lanes_total"], gs1["valid_total"] - gs["valid_total"],
+               gs1["steps_total"] - gs["steps_total"])
+        want = (len(tr), int(np.count_nonzero(tr["valid"])), int(tr["steps"].astype(np.int64).sum()))
+        if got != want:
+            rep.fail(f"it{it}: lanes / valid / steps counters {got}, trace {want}")
         merged = compare_expansion(p, W, recs, tr, rep, it, gpu_prev)
         W.apply(merged)
         g = G.copy_tree()

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import problem_small_di, problem_small_quad, problem_c5, RK4
+from workloads import problem_small_di, problem_small_quad, problem_c5, EULER, RK4
 
 import lockstep
 
@@ -19,6 +19,14 @@ def _announce(name, p):
     print(f"[gpu-case] {name}: cap={p['node_cap']} obs={len(p['obstacles'])} "
           f"lam={p['lambda_max']} grid={p['grid']} sub={p['sub']} seed={p['seed']}", flush=True)
     sys.stdout.flush()
+
+
+def _with_box(p, bounds):
+    """The problem with some state-box coordinates replaced: {index: (lo, hi)}."""
+    lo, hi = np.array(p["x_lo"], np.float32), np.array(p["x_hi"], np.float32)
+    for i, (a, b) in bounds.items():
+        lo[i], hi[i] = a, b
+    return dict(p, x_lo=lo, x_hi=hi)
 
 
 CASES = {
@@ -34,6 +42,14 @@ CASES = {
     # Alg. 2's random segment duration (k uniform in 1..K steps)
     "di-duration": lambda: problem_small_di(seed=8, cap=4096, n_obs=12, duration_mode=1),
     "quad-duration": lambda: problem_small_quad(seed=4, cap=8192, n_obs=60, duration_mode=1),
+    "quad-euler": lambda: problem_small_quad(seed=7, cap=8192, n_obs=60, integrator=EULER),
+    # the kernel variant with the tilt range check and the two-sided state-box
+    # test: a tilt bound too wide for the branch-free polynomials, and a box
+    # that is not symmetric about zero
+    "quad-wide-tilt": lambda: _with_box(problem_small_quad(seed=5, cap=8192, n_obs=60),
+                                        {3: (-1.3, 1.3), 4: (-1.3, 1.3)}),
+    "quad-asym-box": lambda: _with_box(problem_small_quad(seed=6, cap=8192, n_obs=60),
+                                       {6: (-10.0, 8.0), 11: (-4.0, 5.0)}),
 }
 
 
