@@ -50,6 +50,10 @@ CASES = {
                                         {3: (-1.3, 1.3), 4: (-1.3, 1.3)}),
     "quad-asym-box": lambda: _with_box(problem_small_quad(seed=6, cap=8192, n_obs=60),
                                        {6: (-10.0, 8.0), 11: (-4.0, 5.0)}),
+    # a velocity box not symmetric about zero: the double integrator's
+    # two-sided state-box test
+    "di-asym-box": lambda: _with_box(problem_small_di(seed=9, cap=4096, n_obs=12),
+                                     {3: (-10.0, 9.0), 5: (-8.0, 10.0)}),
 }
 
 
