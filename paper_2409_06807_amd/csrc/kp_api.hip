@@ -689,7 +689,7 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
   const uint32_t it0 = h->hctl->iters_done;
   // Default: 8 iterations between status reads.  Every kernel reads its
   // sizes from the device and an oversized grid costs no atomics, so the
-  // host round trip (about 25 us) is paid once per 8 iterations instead of
+  // host round trip (about 13 us) is paid once per 8 iterations instead of
   // once per iteration; after a stop the rest of a batch is empty launches.
   const int per_sync = h->desc.iters_per_sync > 0 ? h->desc.iters_per_sync : 8;
   const long long cap = h->desc.node_cap;
