@@ -27,7 +27,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t ctl, env, x, u, parent, cell, flag, birth, sample, F;
   size_t nv, ni, visited, thr, avail, obs, st_front, st_nodes, path;
-  size_t sx, su, scell, slane, scount, ssum;
+  size_t sx, su, scell, slane, spar, scount, ssum;
   size_t total;
   int capP, tiles_node, nchunk;
 };
@@ -109,6 +109,7 @@ Layout make_layout(const kp_problem_desc* d) {
   L.su = take(capP * m * 4);
   L.scell = take(capP * 4);
   L.slane = take(capP * 4);
+  L.spar = take(capP * 4);
   L.scount = take(((size_t)d->node_cap / 64 + 2) * 4);  // one count per 64-lane wave tile
   L.ssum = take((size_t)L.nchunk * 2 * 4);
   L.total = off;
@@ -343,6 +344,7 @@ void carve(kp_problem* h, void* ws) {
   v.su = reinterpret_cast<float*>(b + L.su);
   v.scell = reinterpret_cast<uint32_t*>(b + L.scell);
   v.slane = reinterpret_cast<uint32_t*>(b + L.slane);
+  v.spar = reinterpret_cast<int32_t*>(b + L.spar);
   v.scount = reinterpret_cast<uint32_t*>(b + L.scount);
   v.ssum = reinterpret_cast<uint32_t*>(b + L.ssum);
   v.capP = L.capP;

@@ -55,7 +55,7 @@ struct alignas(256) Ctl {
   uint32_t goal_hit;      // an accepted sample of this query reached X_goal
   // the iteration as k_propagate found it, read by k_post (whose finaliser
   // rewrites the fields above while other blocks may still start)
-  int32_t slanes, slam, sfexpl, sfbase;
+  int32_t slanes, slam;
   TotLine tot[kGroups];  // propagate totals per group; the host adds the groups
   TkLine tkp[kGroups];   // propagate tile tickets per group; cleared by k_commit / k_post
 };
@@ -113,6 +113,8 @@ struct Dev {
   float* su;           // [m][capP]
   uint32_t* scell;     // [capP]
   uint32_t* slane;     // [capP] lane index << 1 | goal bit
+  int32_t* spar;       // [capP] parent id (the commit never reads F, which the
+                       // node-set pass of the same launch rewrites)
   uint32_t* scount;    // [node_cap / 64 + 2] accepted samples per 64-lane wave tile
   uint32_t* ssum;      // [2][nchunk] accepted samples per kChunkTiles consecutive wave
                        // tiles; iteration it uses half it & 1

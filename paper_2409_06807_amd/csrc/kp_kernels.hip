@@ -788,8 +788,6 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     c->sepoch = c->epoch;
     c->slanes = lanes;
     c->slam = lam;
-    c->sfexpl = f_expl;
-    c->sfbase = f_base;
   }
   uint32_t* ssum_it = d.ssum + (size_t)(it & 1u) * (size_t)d.nchunk;
   // tiles are single waves: each wave takes 64 lanes at a time from the ticket
@@ -1064,6 +1062,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       for (int j = 0; j < m; ++j) d.su[(size_t)j * d.capP + slot] = u[j];
       d.scell[slot] = cl;
       d.slane[slot] = ((uint32_t)g << 1) | (goal ? 1u : 0u);
+      d.spar[slot] = f;
     }
     if (__lane_id() == 0) {
       const uint32_t na = (uint32_t)__popcll(ab);
@@ -1126,7 +1125,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
 // staged sample gets id |T| + (accepted samples of all earlier tiles) +
 // (rank inside its tile) and its tree entries.
 struct CommitCtx {
-  int32_t N, lanes, lam, f_expl, f_base;
+  int32_t N, lanes, lam;
   uint32_t it, nwt;
 };
 __device__ __forceinline__ void commit_tiles(const Params& p, const Dev& d, Ctl* c,
@@ -1152,7 +1151,7 @@ __device__ __forceinline__ void commit_tiles(const Params& p, const Dev& d, Ctl*
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         if (q < p.m) us[q] = d.su[(size_t)q * d.capP + slot];
-      par = frontier_node(d.F, (int32_t)(sl >> 1) / k.lam, k.f_expl, k.f_base);
+      par = d.spar[slot];
     }
     const uint32_t ch = wt / kChunkTiles;
     unsigned long long part = 0;
@@ -1238,8 +1237,6 @@ __global__ __launch_bounds__(kCommitBlock) void k_commit(const Env* __restrict__
   k.N = N;
   k.lanes = lanes;
   k.lam = lam;
-  k.f_expl = c->f_expl;
-  k.f_base = c->f_base;
   k.it = it;
   k.nwt = nwt;
   commit_tiles(p, d, c, k, blockIdx.x * wpb + wave, nblk * wpb, trace);
@@ -1471,6 +1468,8 @@ __global__ __launch_bounds__(kNodeBlock) void k_nodesets(const Env* __restrict__
 // on look-backs ordered as in k_nodesets.  Every block reads the sizes from
 // the copy k_propagate made, so the finaliser may run while late blocks
 // start.  Same results as k_commit, k_region and k_nodesets in sequence.
+// The commit takes each sample's parent from its staged record, never from
+// F, which the node-set blocks rewrite in the same launch.
 // Thread 0 polls with relaxed device-scope loads.  No acquire fence follows
 // (on this GPU it would invalidate the cache of every wave of every waiting
 // block): the thresholds are then read with device-scope atomic loads, which
@@ -1525,22 +1524,21 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
     return;
   }
   if (blockIdx.x <= (uint32_t)nc) {
+    const uint32_t ci = blockIdx.x - 1u;
     // ---- V_U ----
     CommitCtx k;
     k.N = N;
     k.lanes = lanes;
     k.lam = lam;
-    k.f_expl = c->sfexpl;
-    k.f_base = c->sfbase;
     k.it = it;
     k.nwt = nwt;
-    const uint32_t first = (blockIdx.x - 1u) * wpb + wave, stride = (uint32_t)nc * wpb;
+    const uint32_t first = ci * wpb + wave, stride = (uint32_t)nc * wpb;
     commit_tiles(p, d, c, k, first, stride, nullptr);
     // visited bits of the block's samples, once the estimates have read the
     // old ones: one atomic per distinct region among a tile's samples.  A
     // block with no accepted sample does not wait.
     bool any = false;
-    for (uint32_t wt = (blockIdx.x - 1u) * wpb; wt < nwt && !any; wt += stride)
+    for (uint32_t wt = ci * wpb; wt < nwt && !any; wt += stride)
       for (uint32_t w = 0; w < wpb && wt + w < nwt; ++w) any |= d.scount[wt + w] != 0u;
     if (!any) return;
     wait_region(c, epoch);
