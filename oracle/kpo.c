@@ -18,7 +18,8 @@
  *   eq. 6   lambda = min(lambda_max, floor((t_e - |T|) / |V_E|)).
  * Readings of points the paper leaves open are stated where they are used.
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared kpo.c -lm
+ * Build: gcc -O2 -std=gnu99 -ffp-contract=off -fopenmp -fPIC -shared kpo.c -lm
+ * (without -fopenmp the lanes run on one thread; the results are the same).
  */
 #include "kpo.h"
 
@@ -26,6 +27,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
@@ -219,7 +223,9 @@ uint32_t kpo_cell_of(const kpo_problem* pb, const double* p) {
   return region * 64u + local;
 }
 
-static int near_cell_plane(const kpo_problem* pb, const double* p, double tol) {
+/* Whether position p lies within tol of an interior plane of the fine-cell
+ * grid (a plane between two cells, not the clamped outer faces of W). */
+int kpo_near_cell_plane(const kpo_problem* pb, const double* p, double tol) {
   for (int a = 0; a < 3; ++a) {
     const int na = pb->grid[a] * pb->sub;
     const double w = (pb->x_hi[a] - pb->x_lo[a]) / (double)na;
@@ -501,13 +507,26 @@ int32_t kpo_frontier(kpo_planner* P) {
 
 int64_t kpo_num_lanes(const kpo_planner* P) { return (int64_t)P->nF * P->lambda; }
 
-/* Alg. 2, one thread's work: sample u (dt is the fixed segment of K steps),
- * x' = PropagateODE(x, u), map x' to its sub-region, check validity.
- * The segment is integrated step by step and checked at every step; x' is
- * the end of the segment, or the state at the first step that fails.
- * A non-finite x' is mapped to its parent's cell. */
+/* Alg. 2, one thread's work, in its order: sample u (dt is the segment of K
+ * steps), x' = PropagateODE(x, u, dt) over the whole segment, map x' to its
+ * sub-region, then decide validity.  The validity test is taken step by
+ * step along the integrated trajectory (every step's state and swept box);
+ * it does not move x'.  A non-finite x' is mapped to its parent's cell. */
 void kpo_expand_one(const kpo_planner* P, int32_t f, int32_t s, kpo_record* rec, double* traj_out) {
   kpo_expand_one_u(P, f, s, NULL, rec, traj_out);
+}
+
+/* Whether the FP64 value of a state is a stable reference for a
+ * lower-precision computation of the same trajectory: finite, and for the
+ * quadcopter a pitch away from the Euler-angle singularity at |theta| = pi/2,
+ * where the rate matrix W(phi, theta) has 1 / cos(theta) entries and nearby
+ * trajectories separate without bound.  Used only to classify decisions in
+ * the parity protocol; it changes no planner result. */
+static int well_conditioned(const kpo_problem* pb, const double* x, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(x[i])) return 0;
+  if (pb->dyn == KPO_QUAD12 && fabs(x[4]) > pb->cond_tilt) return 0;
+  return 1;
 }
 
 /* The same expansion with the control given by the caller (u_given: m FP32
@@ -533,22 +552,32 @@ void kpo_expand_one_u(const kpo_planner* P, int32_t f, int32_t s, const float* u
   rec->k_seg = Kl;
   double u[4] = {0, 0, 0, 0};
   for (int j = 0; j < m; ++j) u[j] = (double)rec->u[j];
+  /* x' = PropagateODE(x, u, dt) */
   memcpy(traj, P->x + (size_t)f * n, sizeof(double) * n);
   for (int j = 1; j <= Kl; ++j) kpo_step(pb, traj + (size_t)(j - 1) * n, u, traj + (size_t)j * n);
-  const double tol = pb->amb_tol;
-  const int fail = first_fail(pb, traj, n, Kl, 0.0);
-  rec->fail_strict = first_fail(pb, traj, n, Kl, -tol);
-  rec->fail_loose = first_fail(pb, traj, n, Kl, +tol);
-  rec->valid = (fail == Kl + 1);
-  rec->steps = rec->valid ? Kl : fail;
-  const double* xe = traj + (size_t)rec->steps * n;
+  rec->steps = Kl;
+  const double* xe = traj + (size_t)Kl * n;
   memcpy(rec->x, xe, sizeof(double) * n);
+  /* map x' to its sub-region R_i^k */
+  const double tol = pb->amb_tol;
   if (isfinite(xe[0]) && isfinite(xe[1]) && isfinite(xe[2])) {
     rec->cell = kpo_cell_of(pb, xe);
-    rec->amb_cell = near_cell_plane(pb, xe, tol);
+    rec->amb_cell = kpo_near_cell_plane(pb, xe, tol);
   } else {
     rec->cell = P->cell[f];
     rec->amb_cell = 0;
+  }
+  /* validity of the trajectory from x to x' */
+  rec->fail = first_fail(pb, traj, n, Kl, 0.0);
+  rec->fail_strict = first_fail(pb, traj, n, Kl, -tol);
+  rec->fail_loose = first_fail(pb, traj, n, Kl, +tol);
+  rec->valid = (rec->fail == Kl + 1);
+  rec->cond_step = Kl + 1;
+  for (int j = 1; j <= Kl; ++j) {
+    if (!well_conditioned(pb, traj + (size_t)j * n, n)) {
+      rec->cond_step = j;
+      break;
+    }
   }
   const double gd = goal_dist(pb, xe);
   rec->goal = rec->valid && gd <= pb->goal_r;
@@ -556,20 +585,43 @@ void kpo_expand_one_u(const kpo_planner* P, int32_t f, int32_t s, const float* u
   free(heap);
 }
 
+/* Every lane of Alg. 2, lane k = (frontier position e, sample s) with
+ * k = e * lambda + s.  Lanes are independent of each other (each reads only
+ * the tree as it was when the iteration started), so with OpenMP they may
+ * run on several threads; every record is the same either way. */
 int64_t kpo_expand_all(const kpo_planner* P, kpo_record* recs) {
-  int64_t k = 0;
-  for (int32_t e = 0; e < P->nF; ++e)
-    for (int32_t s = 0; s < P->lambda; ++s) kpo_expand_one(P, P->F[e], s, &recs[k++], NULL);
-  return k;
+  return kpo_expand_all_u(P, NULL, recs);
 }
 
-/* All lanes with given controls: U holds 4 floats per lane, lane order. */
+/* All lanes with given controls: U holds 4 floats per lane, lane order
+ * (NULL: the controls are drawn). */
 int64_t kpo_expand_all_u(const kpo_planner* P, const float* U, kpo_record* recs) {
-  int64_t k = 0;
-  for (int32_t e = 0; e < P->nF; ++e)
-    for (int32_t s = 0; s < P->lambda; ++s, ++k)
-      kpo_expand_one_u(P, P->F[e], s, U + 4 * k, &recs[k], NULL);
-  return k;
+  const int64_t lanes = (int64_t)P->nF * P->lambda;
+  const int32_t lam = P->lambda;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) if (lanes > 256)
+#endif
+  for (int64_t k = 0; k < lanes; ++k) {
+    const int32_t e = (int32_t)(k / lam), s = (int32_t)(k - (int64_t)e * lam);
+    kpo_expand_one_u(P, P->F[e], s, U ? U + 4 * k : NULL, &recs[k], NULL);
+  }
+  return lanes;
+}
+
+void kpo_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int32_t kpo_get_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* Alg. 2 bookkeeping, in lane order (frontier order, then sample index):

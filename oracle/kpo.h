@@ -53,6 +53,7 @@ typedef struct {
   double amb_tol;       /* ambiguity band for decisions taken on FP values */
   int32_t dur_mode;     /* 0: every segment takes `steps` steps; 1: k ~ U{1..steps} per expansion */
   int32_t pad_;
+  double cond_tilt;     /* quadcopter: |pitch| above this marks a trajectory as ill-conditioned */
 } kpo_problem;
 
 /* One expansion (parent f, sample s) of Alg. 2, before any bookkeeping. */
@@ -60,8 +61,8 @@ typedef struct {
   int32_t parent;
   int32_t sample;
   float u[4];           /* sampled control (FP32 values) */
-  double x[12];         /* x': end of the segment, or the first failing step */
-  int32_t steps;        /* steps integrated to reach x' */
+  double x[12];         /* x' = PropagateODE(x, u, dt): the end of the segment */
+  int32_t steps;        /* steps integrated to reach x' (the segment's steps) */
   int32_t valid;        /* segment valid */
   uint32_t cell;        /* fine cell of x' (region << 6 | sub-cell) */
   int32_t goal;         /* valid and x' in X_goal */
@@ -71,6 +72,8 @@ typedef struct {
   int32_t amb_cell;     /* x' within amb_tol of an interior cell plane */
   int32_t amb_goal;     /* x' within amb_tol of the goal sphere */
   int32_t k_seg;        /* integration steps of this segment (its duration / h) */
+  int32_t fail;         /* first failing step (k_seg + 1: the segment is valid) */
+  int32_t cond_step;    /* first step whose state is ill-conditioned (k_seg + 1: none) */
 } kpo_record;
 
 typedef struct kpo_planner kpo_planner;
@@ -83,6 +86,7 @@ void kpo_step(const kpo_problem* pb, const double* x, const double* u, double* x
 int kpo_state_ok(const kpo_problem* pb, const double* x, double relax);
 int kpo_swept_hit(const kpo_problem* pb, const double* p0, const double* p1, double inflate);
 uint32_t kpo_cell_of(const kpo_problem* pb, const double* p);
+int kpo_near_cell_plane(const kpo_problem* pb, const double* p, double tol);
 double kpo_region_score(double delta, uint64_t nv, uint64_t ni, int cov);
 void kpo_estimates(int R, const uint8_t* avail, const uint64_t* nv, const uint64_t* ni,
                    const uint64_t* visited, double delta, double eps,
@@ -103,6 +107,9 @@ int64_t kpo_expand_all(const kpo_planner* P, kpo_record* recs); /* Alg. 2, per-l
 void kpo_expand_one_u(const kpo_planner* P, int32_t f, int32_t s, const float* u_given,
                       kpo_record* rec, double* traj);               /* given control */
 int64_t kpo_expand_all_u(const kpo_planner* P, const float* U, kpo_record* recs);
+/* Threads of the expansion loop (OpenMP builds; results do not depend on it). */
+void kpo_set_threads(int32_t n);
+int32_t kpo_get_threads(void);
 void kpo_apply(kpo_planner* P, const kpo_record* recs, int64_t n); /* Alg. 2 bookkeeping */
 void kpo_update_estimates(kpo_planner* P);                     /* Alg. 3 */
 int32_t kpo_update_node_sets(kpo_planner* P);                  /* Alg. 4; goal id or -1 */

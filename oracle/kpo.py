@@ -16,6 +16,10 @@ OK, SOLVED, TIMEOUT, TREE_FULL, FRONTIER_EMPTY = 0, 1, 2, 3, 4
 E_ARG, E_START_INVALID, E_GOAL_INVALID = -1, -4, -5
 
 AMB_TOL = 1e-4  # ambiguity band for FP-decided outcomes (workspace / state units)
+# Quadcopter states with |pitch| above this are too close to the Euler-angle
+# singularity (|pitch| = pi/2) for their FP64 values to serve as a reference
+# of a lower-precision trajectory; see kpo.c well_conditioned.
+COND_TILT = 1.45
 
 
 def build(force: bool = True) -> str:
@@ -23,8 +27,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-             "-shared", SRC, "-o", tmp, "-lm"], cwd=HERE)
+            ["gcc", "-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+             "-fPIC", "-shared", SRC, "-o", tmp, "-lm"], cwd=HERE)
         os.replace(tmp, LIB)
     return LIB
 
@@ -40,7 +44,7 @@ class Problem(C.Structure):
         ("grid", C.c_int32 * 3), ("sub", C.c_int32), ("cap", C.c_int32),
         ("lambda_max", C.c_int32), ("delta", C.c_double), ("eps", C.c_double),
         ("seed", C.c_uint64), ("amb_tol", C.c_double), ("dur_mode", C.c_int32),
-        ("pad_", C.c_int32),
+        ("pad_", C.c_int32), ("cond_tilt", C.c_double),
     ]
 
 
@@ -61,11 +65,12 @@ class View(C.Structure):
 
 RECORD_DTYPE = np.dtype({
     "names": ["parent", "sample", "u", "x", "steps", "valid", "cell", "goal", "w_acc",
-              "fail_strict", "fail_loose", "amb_cell", "amb_goal", "k_seg"],
+              "fail_strict", "fail_loose", "amb_cell", "amb_goal", "k_seg", "fail", "cond_step"],
     "formats": [np.int32, np.int32, (np.float32, 4), (np.float64, 12), np.int32, np.int32,
-                np.uint32, np.int32, np.uint32, np.int32, np.int32, np.int32, np.int32, np.int32],
-    "offsets": [0, 4, 8, 24, 120, 124, 128, 132, 136, 140, 144, 148, 152, 156],
-    "itemsize": 160,
+                np.uint32, np.int32, np.uint32, np.int32, np.int32, np.int32, np.int32, np.int32,
+                np.int32, np.int32],
+    "offsets": [0, 4, 8, 24, 120, 124, 128, 132, 136, 140, 144, 148, 152, 156, 160, 164],
+    "itemsize": 168,
 })
 
 _lib = None
@@ -88,6 +93,10 @@ def lib():
         L.kpo_swept_hit.argtypes = [C.POINTER(Problem), vp, vp, C.c_double]
         L.kpo_cell_of.argtypes = [C.POINTER(Problem), vp]
         L.kpo_cell_of.restype = C.c_uint32
+        L.kpo_near_cell_plane.argtypes = [C.POINTER(Problem), vp, C.c_double]
+        L.kpo_near_cell_plane.restype = C.c_int
+        L.kpo_set_threads.argtypes = [C.c_int32]
+        L.kpo_get_threads.restype = C.c_int32
         L.kpo_region_score.argtypes = [C.c_double, C.c_uint64, C.c_uint64, C.c_int]
         L.kpo_region_score.restype = C.c_double
         L.kpo_estimates.argtypes = [C.c_int, vp, vp, vp, vp, C.c_double, C.c_double, vp, vp, vp, vp]
@@ -136,7 +145,7 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def problem_struct(p: dict, amb_tol: float = AMB_TOL):
+def problem_struct(p: dict, amb_tol: float = AMB_TOL, cond_tilt: float = COND_TILT):
     """Build the oracle's problem struct from a workload dict.  Returns
     (struct, keepalive) -- keep the second item alive as long as the first."""
     s = Problem()
@@ -172,6 +181,7 @@ def problem_struct(p: dict, amb_tol: float = AMB_TOL):
     s.seed = int(p["seed"]) & ((1 << 64) - 1)
     s.amb_tol = float(amb_tol)
     s.dur_mode = int(p.get("duration_mode", 0))
+    s.cond_tilt = float(cond_tilt)
     return s, obs
 
 
@@ -184,6 +194,15 @@ def philox4x32_10(ctr, key):
     out = np.zeros(4, np.uint32)
     lib().kpo_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's expansion loop (OpenMP; results do not depend on it)."""
+    lib().kpo_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().kpo_get_threads())
 
 
 def segment_steps(p, it, f, s):
@@ -241,6 +260,12 @@ def cell_of(p, pos):
     pb = _PB(p)
     a = np.ascontiguousarray(np.asarray(pos, np.float64))
     return int(lib().kpo_cell_of(C.byref(pb.s), _ptr(a)))
+
+
+def near_cell_plane(p, pos, tol=AMB_TOL):
+    pb = _PB(p)
+    a = np.ascontiguousarray(np.asarray(pos, np.float64))
+    return bool(lib().kpo_near_cell_plane(C.byref(pb.s), _ptr(a), float(tol)))
 
 
 def region_score(delta, nv, ni, cov):

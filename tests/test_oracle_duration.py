@@ -45,13 +45,12 @@ def test_expansion_integrates_k_steps_closed_form():
         k = int(r["k_seg"])
         assert k == oracle.segment_steps(p, 0, int(r["parent"]), int(r["sample"]))
         u = r["u"][:3].astype(np.float64)
-        if r["valid"]:
-            assert r["steps"] == k
-            v = x0[3:] + k * h * u
-            pos = x0[:3] + k * h * x0[3:] + h * h * u * k * (k - 1) / 2
-            assert np.allclose(r["x"][:6], np.concatenate([pos, v]), rtol=0, atol=1e-11)
-        else:
-            assert 1 <= r["steps"] <= k
+        # x' is the end of the whole k-step segment, valid or not (Alg. 2)
+        assert r["steps"] == k
+        v = x0[3:] + k * h * u
+        pos = x0[:3] + k * h * x0[3:] + h * h * u * k * (k - 1) / 2
+        assert np.allclose(r["x"][:6], np.concatenate([pos, v]), rtol=0, atol=1e-11)
+        assert 1 <= r["fail"] <= k + 1 and (r["fail"] == k + 1) == bool(r["valid"])
 
 
 def edge_steps(p, s, path):
@@ -86,7 +85,8 @@ def test_random_duration_quad_runs():
         if W.frontier() != oracle.OK:
             break
         recs = W.expand_all()
-        assert np.all((recs["steps"] >= 1) & (recs["steps"] <= recs["k_seg"]))
+        assert np.array_equal(recs["steps"], recs["k_seg"])
+        assert np.all((recs["fail"] >= 1) & (recs["fail"] <= recs["k_seg"] + 1))
         W.apply(recs)
         W.update_estimates()
         W.update_node_sets()

@@ -223,8 +223,10 @@ def test_ambiguity_band_ordering():
     P.frontier()
     recs = P.expand_all()
     K = int(p["steps"])
-    fail = np.where(recs["valid"] == 1, K + 1, recs["steps"])
+    fail = recs["fail"]
+    assert np.array_equal(recs["valid"] == 1, fail == K + 1)
     assert np.all(recs["fail_strict"] <= fail) and np.all(fail <= recs["fail_loose"])
+    assert np.all(recs["steps"] == K)
 
 
 def near_goal_problem(seed=0):
@@ -263,3 +265,31 @@ def test_found_path_replays_in_fp64(seed):
         for o in obs:
             assert not np.any(np.all((pts >= o[:3]) & (pts <= o[3:]), axis=1))
         x = np.concatenate([x[:3] + x[3:] * K * h + 0.5 * u * (K * h) ** 2, x[3:] + u * K * h])
+
+
+def test_threads_do_not_change_results():
+    """The expansion loop may run on several OpenMP threads: every record, and
+    so the whole planning run, is the same as on one thread."""
+    p = problem_small_quad(seed=3, cap=6000)
+    runs = []
+    old = oracle.get_threads()
+    try:
+        for t in (1, 4):
+            oracle.set_threads(t)
+            W = oracle.OraclePlanner(p)
+            recs = []
+            for _ in range(4):
+                if W.frontier() != oracle.OK:
+                    break
+                r = W.expand_all()
+                recs.append(r.tobytes())
+                W.apply(r)
+                W.update_estimates()
+                W.update_node_sets()
+            s = W.state()
+            runs.append((recs, {k: np.asarray(v).tobytes() for k, v in s.items()
+                                if isinstance(v, np.ndarray)}))
+    finally:
+        oracle.set_threads(old)
+    assert runs[0][0] == runs[1][0]
+    assert runs[0][1] == runs[1][1]
