@@ -30,18 +30,31 @@ METRIC = "median time-to-solution (ms) + valid expansions/s; learned vs uniform 
 
 # Algorithmic work model of the propagation kernel (counted from the
 # formulas, not from the compiled code): FP32 operations per integration step
-# (a fused multiply-add counts 2, a sin or cos 1, a compare 1), per swept-box
-# test against one obstacle, and integer operations per Philox4x32-10 block.
-STEP_OPS = {
-    # quadcopter RK4: 4 derivatives x 43 + stage/combination 156 + state box 24 + swept box 12
-    (1, 1): 4 * 43 + 156 + 24 + 12,
-    # double integrator Euler: 6 FMA (12) + state box 12 + swept box 12
-    (0, 0): 12 + 12 + 12,
-    # double integrator RK4: 3 stages x 12 + 12 x 2 accum + 12 x 3 final + 12 + 12
-    (0, 1): 36 + 24 + 36 + 12 + 12,
-    (1, 0): 43 + 24 + 24 + 12,
+# (a fused multiply-add counts 2, a sin or cos 1, a compare 1), per checked
+# step (the state-box test and the swept box; a lane checks its steps up to
+# its first failing one and integrates on to the end of its segment), per
+# swept-box test against one obstacle, and integer operations per
+# Philox4x32-10 block.
+INTEG_OPS = {
+    (1, 1): 4 * 43 + 156,     # quadcopter RK4: 4 derivatives x 43 + stages / combination 156
+    (0, 0): 12,               # double integrator Euler: 6 FMA
+    (0, 1): 36 + 24 + 36,     # double integrator RK4: 3 stages x 12 + 12 x 2 accum + 12 x 3 final
+    (1, 0): 43 + 24,          # quadcopter Euler
+}
+CHECK_OPS = {
+    (1, 1): 24 + 12,          # state box 12 x 2 compares + swept box 6 min/max + 6 margin adds
+    (0, 0): 12 + 12,
+    (0, 1): 12 + 12,
+    (1, 0): 24 + 12,
 }
 BOX_TEST_OPS = 6
+
+
+def prop_ops(dyn, integ, steps, checked, boxes, lanes):
+    """Algorithmic operations of a set of propagate launches."""
+    philox_per_lane = 2 if dyn == 1 else 1
+    return (steps * INTEG_OPS[(dyn, integ)] + checked * CHECK_OPS[(dyn, integ)] +
+            boxes * BOX_TEST_OPS + lanes * philox_per_lane * PHILOX_OPS)
 PHILOX_OPS = 100
 PEAK_FP32_TFLOPS = 157.3
 
@@ -80,14 +93,22 @@ def gpu_workload(name: str, seed: int = 0):
     return {"c1": problem_c1, "c2": problem_c2, "c5": problem_c5}[name](seed=seed)
 
 
-def run_cpu_baseline(name: str, budget_s: float):
-    """The CPU oracle as it stands, single-threaded, on the leading iterations
-    of seed 0 of the same workload: it stops before the first iteration whose
-    predicted time (its expansion count times the time per expansion so far)
-    would overrun the budget."""
+def host_cores() -> int:
+    """Threads the oracle may use: the CPUs this process may run on, bounded
+    by OMP_NUM_THREADS when it is set (the GPU machine sets it to its CPU share)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def oracle_throughput(P, budget_s: float):
+    """The oracle's valid expansions per second on the leading iterations of
+    the planner P: it stops before the first iteration whose predicted time
+    (its expansion count times the time per expansion so far) would overrun
+    the budget."""
     import oracle
-    p = gpu_workload(name, 0)
-    P = oracle.OraclePlanner(p)
     t0 = time.perf_counter()
     done = 0
     while True:
@@ -105,12 +126,71 @@ def run_cpu_baseline(name: str, budget_s: float):
             break
     dt = time.perf_counter() - t0
     s = P.state(copy=False)
-    nv = int(s["nv"].sum())
-    return {
-        "value": nv / dt, "unit": "valid expansions/s", "cores": 1, "kind": "oracle",
-        "sample": f"{p['name']} seed 0, first {done} iterations: {s['sum_lanes']} expansions, "
-                  f"{nv} valid, |T| = {s['N']}, {dt:.1f} s",
+    return done, int(s["sum_lanes"]), int(s["nv"].sum()), int(s["N"]), dt
+
+
+def oracle_leg(name: str, budget_s: float, tts_seeds: int, tts_budget_s: float, replays):
+    """The CPU oracle (FP64, plain C, unchanged for this) on the host cores:
+      * single-threaded throughput on the leading iterations of seed 0;
+      * planning queries of seeds 0, 1, ... to their end on every host core
+        (OpenMP over the expansion loop; the results are those of one
+        thread), until tts_seeds queries or the budget: its time-to-solution;
+      * FP64 replay of every trajectory the GPU legs returned, edge by edge
+        from each stored parent, against the obstacles without the margin.
+    replays: {leg: [(problem, trajectory), ...]}.  Returns the cpu_baseline
+    entry and {leg: replay summary}."""
+    import oracle
+    cores = host_cores()
+    oracle.set_threads(1)
+    p = gpu_workload(name, 0)
+    done, lanes1, nv1, n1, dt1 = oracle_throughput(oracle.OraclePlanner(p), budget_s)
+    single = {"value": nv1 / dt1, "unit": "valid expansions/s", "cores": 1,
+              "sample": f"{p['name']} seed 0, first {done} iterations: {lanes1} expansions, "
+                        f"{nv1} valid, |T| = {n1}, {dt1:.1f} s"}
+    oracle.set_threads(cores)
+    tts, runs = [], []
+    t_all = time.perf_counter()
+    nv_all = lanes_all = 0
+    for s in range(tts_seeds):
+        if s > 0 and time.perf_counter() - t_all > tts_budget_s:
+            break
+        P = oracle.OraclePlanner(gpu_workload(name, s))
+        a = time.perf_counter()
+        st, g, it = P.plan(max_iters=100000, t_max_ms=60000.0)
+        ms = (time.perf_counter() - a) * 1e3
+        v = P.state(copy=False)
+        nv_all += int(v["nv"].sum())
+        lanes_all += int(v["sum_lanes"])
+        runs.append({"seed": s, "status": int(st), "ms": ms, "iterations": int(it), "nodes": int(v["N"])})
+        if st == oracle.SOLVED:
+            tts.append(ms)
+        del P
+    wall = time.perf_counter() - t_all
+    oracle.set_threads(1)
+    entry = {
+        "value": nv_all / wall if wall > 0 else 0.0, "unit": "valid expansions/s", "cores": cores,
+        "kind": "oracle",
+        "sample": f"{p['name']} seeds 0..{len(runs) - 1} planned to their end on {cores} threads "
+                  f"(OpenMP over the expansion loop): {lanes_all} expansions, {nv_all} valid, "
+                  f"{wall:.1f} s",
+        "single_thread": single,
+        "median_tts_ms": statistics.median(tts) if tts else None,
+        "mean_tts_ms": statistics.mean(tts) if tts else None,
+        "success_rate": len(tts) / len(runs) if runs else None,
+        "queries": runs,
     }
+    rep = {}
+    for leg, items in replays.items():
+        ok = reached = 0
+        worst = 0.0
+        for prob, tr in items:
+            r = oracle.replay_trajectory(prob, tr)
+            ok += int(r["valid"] and r["reached"])
+            reached += int(r["reached"])
+            worst = max(worst, r["worst"])
+        rep[leg] = {"replay_valid_rate": ok / len(items) if items else None,
+                    "replayed_paths": len(items), "worst_edge_rel_dev": worst}
+    return entry, rep
 
 
 def percentile(v, q):
@@ -145,7 +225,7 @@ def expand_only(G, p, dyn, integ, reps):
         G.update_tree()
     lanes, tree = best
     times = []
-    steps = boxes = 0
+    steps = boxes = checked = 0
     for _ in range(reps):
         G.load_tree(tree)
         s0 = G.stats()
@@ -157,19 +237,20 @@ def expand_only(G, p, dyn, integ, reps):
         s1 = G.stats()
         times.append(kt["propagate"][1])
         steps = s1["steps_total"] - s0["steps_total"]
+        checked = s1["checked_steps_total"] - s0["checked_steps_total"]
         boxes = s1["box_tests_total"] - s0["box_tests_total"]
         G.update_regions()
         G.update_tree()
     ms = statistics.median(times)
-    philox_per_lane = 2 if dyn == 1 else 1
-    ops = steps * STEP_OPS[(dyn, integ)] + boxes * BOX_TEST_OPS + lanes * philox_per_lane * PHILOX_OPS
+    ops = prop_ops(dyn, integ, steps, checked, boxes, lanes)
     tf = ops / (ms * 1e-3) / 1e12
     print(json.dumps({
         "mode": "expand-only", "workload": p["name"], "iteration": int(tree["it"]),
         "tree_nodes": int(tree["N"]), "lanes": int(lanes), "repetitions": reps,
         "propagate_ms_median": ms, "propagate_ms_all": times,
         "lanes_per_us": lanes / (ms * 1e3), "steps_per_lane": steps / lanes,
-        "box_tests_per_step": boxes / steps if steps else None,
+        "checked_steps_per_lane": checked / lanes,
+        "box_tests_per_checked_step": boxes / checked if checked else None,
         "algorithmic_tflops": tf, "peak_tflops": PEAK_FP32_TFLOPS,
         "frac": tf / PEAK_FP32_TFLOPS}))
 
@@ -223,15 +304,18 @@ def learned_leg(G, p, steps, warmup, n_paths, train_steps, batch, lr, mix):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     G.set_profiling(True)
+    paths = []
     for s in range(steps):
         G.reset(s)
-        G.plan()
+        r = G.plan()
+        if r["status"] == SOLVED:
+            paths.append((dict(p, seed=s), G.trajectory(r["goal_id"])))
     kt = G.kernel_times()
     G.set_profiling(False)
     G.set_proposal(None)
     solved = [ms for ms, r in zip(per_ms, results) if r["status"] == SOLVED]
     n_head, head_ms = kt["proposal"]
-    return {
+    return paths, {
         "mix": mix,
         "median_tts_ms": statistics.median(solved) if solved else None,
         "mean_tts_ms": statistics.mean(solved) if solved else None,
@@ -297,10 +381,12 @@ def batched_leg(n_queries, batch_seed=3):
                                cache_path=os.path.join(tempfile.mkdtemp(), "autotune.json"))
     tuned = dict(config=cfg, **run())
     B.close()
+    paths = [(pq, G.trajectory(r["goal_id"])) for pq, G, r in zip(ps, planners, seq)
+             if r["status"] == SOLVED]
     st = [r["status"] for r in seq]
-    return {
+    return paths, {
         "workload": f"c3-batch-di6: {n_queries} double-integrator queries, boxes log-uniform in "
-                    "[10, 1536], caps log-uniform in [16k, 1M], start/goal >= 50 apart",
+                    "[10, 2000], caps log-uniform in [16k, 1M], start/goal >= 50 apart",
         "queries": n_queries, "solved": st.count(SOLVED), "tree_full": st.count(TREE_FULL),
         "sequential": {"total_ms": seq_total, "median_query_ms": statistics.median(seq_ms),
                        "queries_per_s": n_queries / (seq_total * 1e-3)},
@@ -382,7 +468,12 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--profile-steps", type=int, default=-1,
                     help="queries in the HIP-event pass (default: the same seeds as the timed steps)")
-    ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--cpu-budget-s", type=float, default=10.0,
+                    help="single-threaded oracle sample (s)")
+    ap.add_argument("--cpu-tts-seeds", type=int, default=5,
+                    help="queries the oracle plans to their end on all host cores")
+    ap.add_argument("--cpu-tts-budget-s", type=float, default=60.0,
+                    help="no further oracle query starts after this many seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters-per-sync", type=int, default=0)
     ap.add_argument("--expand-only", action="store_true",
@@ -459,21 +550,23 @@ def main():
 
     # per-kernel HIP-event durations on the planner's stream (separate pass)
     G.set_profiling(True)
-    steps_tot = box_tot = lanes_prof = 0
+    steps_tot = box_tot = lanes_prof = checked_tot = 0
     profile_steps = args.steps if args.profile_steps < 0 else args.profile_steps
+    paths = []
     for s in range(profile_steps):
         G.reset(s)
-        G.plan()
+        r = G.plan()
+        if r["status"] == SOLVED:
+            paths.append((gpu_workload(args.workload, s), G.trajectory(r["goal_id"])))
         st = G.stats()
         steps_tot += st["steps_total"]
+        checked_tot += st["checked_steps_total"]
         box_tot += st["box_tests_total"]
         lanes_prof += st["lanes_total"]
     kt = G.kernel_times()
     G.set_profiling(False)
     n_launch, prop_ms = kt["propagate"]
-    philox_per_lane = 2 if dyn == 1 else 1
-    ops = steps_tot * STEP_OPS[(dyn, integ)] + box_tot * BOX_TEST_OPS + \
-        lanes_prof * philox_per_lane * PHILOX_OPS
+    ops = prop_ops(dyn, integ, steps_tot, checked_tot, box_tot, lanes_prof)
     achieved = ops / (prop_ms * 1e-3) / 1e12 if prop_ms > 0 else 0.0
 
     line = {
@@ -518,22 +611,35 @@ def main():
             "avg_launch_ms": prop_ms / n_launch if n_launch else None,
             "ops_per_launch": ops / n_launch if n_launch else None,
             "steps_per_lane": steps_tot / lanes_prof if lanes_prof else None,
-            "box_tests_per_step": box_tot / steps_tot if steps_tot else None,
+            "checked_steps_per_lane": checked_tot / lanes_prof if lanes_prof else None,
+            "box_tests_per_checked_step": box_tot / checked_tot if checked_tot else None,
         },
         "grid": {"propagate": G.stats()["grid_propagate"], "nodes": G.stats()["grid_nodes"]},
         "kernel_ms": {k: v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},
     }
+    replays = {"uniform": paths}
     if not args.no_learned:
-        lrn = learned_leg(G, p, args.steps, args.warmup, args.learned_paths,
-                          args.learned_train_steps, 512, 3e-3, args.learned_mix)
+        lpaths, lrn = learned_leg(G, p, args.steps, args.warmup, args.learned_paths,
+                                  args.learned_train_steps, 512, 3e-3, args.learned_mix)
+        replays["learned"] = lpaths
         um, lm = line["median_tts_ms"], lrn["median_tts_ms"]
         lrn["median_tts_ratio_learned_over_uniform"] = lm / um if (um and lm) else None
         line["learned"] = lrn
     if not args.no_batched:
-        line["batched"] = batched_leg(args.batch_queries)
+        bpaths, line["batched"] = batched_leg(args.batch_queries)
+        replays["batched"] = bpaths
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = run_cpu_baseline(args.workload, args.cpu_budget_s)
+        # the oracle leg: CPU baseline timings, then the FP64 replay of every
+        # trajectory the legs above returned (outside every timed region)
+        entry, rep = oracle_leg(args.workload, args.cpu_budget_s, args.cpu_tts_seeds,
+                                args.cpu_tts_budget_s, replays)
+        line["cpu_baseline"] = entry
+        line.update(rep["uniform"])
+        if "learned" in rep:
+            line["learned"].update(rep["learned"])
+        if "batched" in rep:
+            line["batched"].update(rep["batched"])
     print(json.dumps(line))
 
 

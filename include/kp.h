@@ -30,10 +30,11 @@
 extern "C" {
 #endif
 
-#define KP_ABI_VERSION 2u
+#define KP_ABI_VERSION 3u
 #define KP_MAX_STATE 12
 #define KP_MAX_CONTROL 4
-#define KP_MAX_OBSTACLES 1536  /* per-block LDS (obstacle table + candidate lists) stays under 64 KiB */
+#define KP_MAX_OBSTACLES 2048  /* the obstacle table and candidate lists of a propagate block fit
+                                   gfx950's LDS (69 KB per 256-lane block at 2048) */
 
 typedef enum {
   KP_OK = 0,
@@ -136,8 +137,10 @@ typedef struct {
   int32_t n_new;           /* |V_U| of the last expansion */
   int32_t device_error;    /* nonzero if a kernel hit an internal limit */
   uint64_t lanes_total, valid_total, invalid_total;
-  uint64_t steps_total;    /* integration steps executed */
+  uint64_t steps_total;    /* integration steps executed (every lane runs its whole segment) */
   uint64_t box_tests_total;/* swept-box vs obstacle tests executed */
+  uint64_t checked_steps_total; /* steps whose state and swept box were tested: each lane
+                                   tests up to and including its first failing step */
   int32_t grid_propagate;  /* workgroups of a full-size propagate launch */
   int32_t grid_nodes;      /* workgroups of a full-size node-pass launch */
 } kp_iter_stats;
@@ -172,15 +175,16 @@ typedef struct {
 
 /*
  * One record per expansion lane of kp_expand, written when a trace buffer is
- * passed (lane = frontier position * lambda + sample).  96 bytes, device
+ * passed (lane = frontier position * lambda + sample).  100 bytes, device
  * memory of at least kp_trace_bytes() bytes.
  */
 typedef struct {
   int32_t parent;          /* tree node expanded */
   int32_t sample;          /* 0 .. lambda-1 */
   float u[4];              /* sampled control */
-  float x[12];             /* x': segment end, or the state at the first failing step */
-  int32_t steps;           /* integration steps taken */
+  float x[12];             /* x' = PropagateODE(x, u, dt), the end of the segment (Alg. 2) */
+  int32_t steps;           /* integration steps of the segment */
+  int32_t fail_step;       /* first step whose state or swept box fails; steps + 1 if valid */
   int32_t valid;
   uint32_t cell;           /* sub-region of x' (region * 64 + index) */
   int32_t goal;            /* valid, accepted and in X_goal */
@@ -258,10 +262,22 @@ kp_status kp_load_tree(kp_problem* h, const kp_tree_host* in);
  * and eq. (6) recomputed with its capacity).  Synchronous. */
 kp_status kp_transfer_tree(kp_problem* src, kp_problem* dst);
 
-/* Node ids from the root to `node` ("return trajectory x_init to x",
- * the goal test of Alg. 4).  ids: host array of cap entries; *len receives the path
- * length.  KP_E_ARG if node is out of range or the path exceeds cap. */
+/* Node ids from the root to `node`: the parent walk behind the trajectory
+ * that Alg. 4 returns when its goal test succeeds.  ids: host array of cap
+ * entries; *len receives the path length.  KP_E_ARG if node is out of range
+ * or the path exceeds cap. */
 kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, int32_t* len);
+
+/* The trajectory from the root to `node` (Alg. 4 returns it for the goal
+ * node): for each of the *len nodes of the path, row i of x holds its state
+ * (n floats), row i of u the control of the edge into it (m floats, zero for
+ * the root) and steps[i] that edge's integration steps (0 for the root; the
+ * segment duration is steps[i] * h).  Host buffers of cap rows; any of x, u,
+ * steps may be NULL (all NULL: only *len).  KP_E_ORDER in the middle of an
+ * iteration; KP_E_ARG if node is out of range or the path exceeds cap.
+ * Synchronous. */
+kp_status kp_get_trajectory(kp_problem* h, int32_t node, float* x, float* u, int32_t* steps,
+                            int32_t cap, int32_t* len);
 
 /* Per-kernel timing with HIP events on the handle's stream (0 = off).  While
  * on, every launch carries two events stamped with its dispatch's begin and end; totals accumulate until
@@ -272,6 +288,23 @@ kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, in
  * count and the summed duration in milliseconds.  Synchronises. */
 kp_status kp_set_profiling(kp_problem* h, int32_t on);
 kp_status kp_kernel_times(kp_problem* h, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Per-lane records of the expansions that kp_plan and kp_batch_plan run
+ * (Alg. 2 inside Alg. 1's loop): with dev_trace set, every propagate launch
+ * of the planning loop writes one kp_trace_record per lane of this problem,
+ * as kp_expand does, overwriting the previous iteration's records (new_id
+ * stays -1: ids are given in the fused pass after it).  dev_trace: NULL (off) or device memory of kp_trace_bytes()
+ * bytes, 4-byte aligned, borrowed until replaced.  Used to compare the planning
+ * loop lane by lane with a reference, one iteration per kp_plan call
+ * (max_iters = 1). */
+kp_status kp_set_trace(kp_problem* h, void* dev_trace);
+
+/* Caps on the workgroups of every launch of the handle: prop_blocks for the
+ * expansion, node_blocks for the V_U commit and the node passes (0 = the
+ * occupancy maximum, the default).  Kernels take their work from ticket
+ * counters and read their sizes from device memory, so the results do not
+ * depend on these caps; small caps make one block serve many tiles. */
+kp_status kp_set_launch_limits(kp_problem* h, int32_t prop_blocks, int32_t node_blocks);
 
 const char* kp_status_str(kp_status s);
 const char* kp_last_error(const kp_problem* h);
@@ -358,8 +391,10 @@ kp_status kp_mlp_train(float* dev_params, float* dev_m1, float* dev_m2, void* de
                        float* dev_partials, float* dev_loss, void* hip_stream);
 
 /* Use the packed network dev_packed for the handle's expansions from the next
- * kp_expand / kp_plan on, mixed with the uniform draw at rate mix in [0, 1]
- * (dev_packed = NULL or mix = 0: uniform only).  dev_head: device scratch of
+ * kp_expand / kp_plan on, mixed with the uniform draw at rate mix in [0, 1):
+ * the uniform share 1 - mix must stay positive (KP_E_ARG otherwise), since it
+ * is what keeps every control reachable (dev_packed = NULL or mix = 0:
+ * uniform only).  dev_head: device scratch of
  * head_rows x 8 floats, head_rows >= node_cap.  Both buffers are borrowed
  * until the proposal is replaced.  KP_E_ORDER in the middle of an iteration.
  * Synchronises. */
@@ -373,6 +408,15 @@ kp_status kp_set_proposal(kp_problem* h, const void* dev_packed, float* dev_head
  * Synchronises. */
 kp_status kp_log_path(kp_problem* h, int32_t node, float* dev_x, float* dev_t, int32_t cap_rows,
                       int32_t row0, int32_t* n_rows);
+
+/* Training rows from every edge of the tree whose child lies strictly closer
+ * to the goal centre than its parent (valid expansions that made progress),
+ * in node id order: row row0 + k holds the parent's input features (dev_x)
+ * and the edge's control in normalised units (dev_t), as kp_log_path writes
+ * them, for rows below cap_rows.  *n_rows receives the rows written.  Must be
+ * called between iterations (KP_E_ORDER otherwise).  Synchronises. */
+kp_status kp_log_tree_edges(kp_problem* h, float* dev_x, float* dev_t, int32_t cap_rows,
+                            int32_t row0, int32_t* n_rows);
 
 /* ---------------------------------------------------------------------------
  * Batched planning

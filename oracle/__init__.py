@@ -9,4 +9,5 @@ from .kpo import (  # noqa: F401
     RECORD_DTYPE, OraclePlanner, build, lib, philox4x32_10, control_map, deriv, step,
     state_ok, swept_hit, cell_of, region_score, estimates, replay, problem_struct, integrate_batch,
     segment_steps, near_cell_plane, set_threads, get_threads, AMB_TOL, COND_TILT,
+    replay_trajectory,
 )

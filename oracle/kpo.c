@@ -793,6 +793,48 @@ int32_t kpo_replay_k(const kpo_problem* pb, const double* x0, int32_t n_edges, c
   return valid;
 }
 
+/* FP64 replay of a stored trajectory one edge at a time.  Edge e starts
+ * from its parent's stored state xs[e] (n FP32 values, widened), holds the
+ * stored control us[e] for steps[e] steps, and must keep every step inside
+ * the state box relaxed by tol and every swept box clear of the obstacles
+ * grown by margin - tol (margin 0 replays against the obstacles themselves);
+ * its end is compared with the stored child xs[e + 1].  A replay from the
+ * root alone would compound the FP32 rounding of the stored states along the
+ * path (the quadcopter is open-loop unstable), so each edge is checked from
+ * the state the planner integrated it from.  Returns 1 if every edge is
+ * valid; *worst gets the largest |end - child| / max(1, |end|) over all
+ * components, *first_bad the first invalid edge (-1: none), and end the FP64
+ * end state of the last edge. */
+int32_t kpo_replay_edges(const kpo_problem* pb, int32_t n_edges, const float* xs, const float* us,
+                         const int32_t* steps, double margin, double tol, double* worst,
+                         int32_t* first_bad, double* end) {
+  const int n = state_dim(pb->dyn), m = ctrl_dim(pb->dyn);
+  kpo_problem q = *pb;
+  q.margin = margin;
+  double x[12], xn[12], u[4] = {0, 0, 0, 0};
+  *worst = 0.0;
+  *first_bad = -1;
+  for (int i = 0; i < n; ++i) x[i] = (double)xs[i];
+  for (int32_t e = 0; e < n_edges; ++e) {
+    for (int i = 0; i < n; ++i) x[i] = (double)xs[(size_t)e * n + i];
+    for (int j = 0; j < m; ++j) u[j] = (double)us[(size_t)(e + 1) * m + j];
+    int ok = 1;
+    for (int k = 0; k < steps[e + 1]; ++k) {
+      kpo_step(&q, x, u, xn);
+      if (!kpo_state_ok(&q, xn, tol) || kpo_swept_hit(&q, x, xn, margin - tol)) ok = 0;
+      memcpy(x, xn, sizeof(double) * n);
+    }
+    if (!ok && *first_bad < 0) *first_bad = e;
+    for (int i = 0; i < n; ++i) {
+      const double ref = fabs(x[i]) > 1.0 ? fabs(x[i]) : 1.0;
+      const double d = fabs((double)xs[(size_t)(e + 1) * n + i] - x[i]) / ref;
+      if (!(d <= *worst)) *worst = d;  /* NaN propagates */
+    }
+  }
+  if (end) memcpy(end, x, sizeof(double) * n);
+  return *first_bad < 0;
+}
+
 /* Integrate n_seg segments in FP64: segment i starts at x0[i] (n values),
  * holds control u[i] (m FP32 values) and runs steps[i] integration steps;
  * the end state goes to out[i].  A plain primitive used to re-check edges. */

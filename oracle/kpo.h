@@ -128,6 +128,13 @@ int32_t kpo_replay_k(const kpo_problem* pb, const double* x0, int32_t n_edges, c
                      const int32_t* edge_steps, double margin, double* end_states,
                      int32_t* reached_goal);
 
+/* Edge-by-edge FP64 replay of a stored trajectory of n_edges + 1 nodes:
+ * xs [n_edges + 1][n] states, us [n_edges + 1][m] controls of the edge into
+ * each node (row 0 unused), steps [n_edges + 1] steps of that edge. */
+int32_t kpo_replay_edges(const kpo_problem* pb, int32_t n_edges, const float* xs, const float* us,
+                         const int32_t* steps, double margin, double tol, double* worst,
+                         int32_t* first_bad, double* end);
+
 void kpo_integrate_batch(const kpo_problem* pb, int64_t n_seg, const double* x0, const float* u,
                          const int32_t* steps, double* out);
 

@@ -134,6 +134,10 @@ def lib():
         L.kpo_replay_k.argtypes = [C.POINTER(Problem), vp, C.c_int32, vp, vp, C.c_double, vp,
                                    C.POINTER(C.c_int32)]
         L.kpo_replay_k.restype = C.c_int32
+        L.kpo_replay_edges.argtypes = [C.POINTER(Problem), C.c_int32, vp, vp, vp, C.c_double,
+                                        C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                        vp]
+        L.kpo_replay_edges.restype = C.c_int32
         L.kpo_integrate_batch.argtypes = [C.POINTER(Problem), C.c_int64, vp, vp, vp, vp]
         L.kpo_get_view.argtypes = [P, C.POINTER(View)]
         L.kpo_set_counters.argtypes = [P, C.c_int32, C.c_int32]
@@ -311,6 +315,34 @@ def replay(p, x0, controls, margin=0.0, edge_steps=None):
                            _ptr(ks) if ks is not None else None, float(margin), _ptr(ends),
                            C.byref(g))
     return bool(v), bool(g.value), ends[:len(ctl)]
+
+
+def replay_trajectory(p, traj, margin=0.0, tol=AMB_TOL, rel_tol=1e-5):
+    """FP64 replay of a returned trajectory (dict of x [L][n], u [L][m] and
+    steps [L] for the L nodes from the root, as the GPU library returns it),
+    edge by edge from each stored parent, against the un-inflated obstacles
+    less the ambiguity band.  Returns dict(valid, reached, worst, first_bad):
+    valid = every edge stays valid and ends within rel_tol of its stored child;
+    reached = the last edge's FP64 end lies in the goal ball (within tol)."""
+    pb = _PB(p)
+    x = np.ascontiguousarray(np.asarray(traj["x"], np.float32).reshape(-1, pb.n))
+    u = np.ascontiguousarray(np.asarray(traj["u"], np.float32).reshape(-1, pb.m))
+    k = np.ascontiguousarray(np.asarray(traj["steps"], np.int32))
+    L = len(x)
+    worst = C.c_double(0.0)
+    bad = C.c_int32(-1)
+    end = np.zeros(pb.n)
+    if L < 2:
+        end[:] = x[0] if L else 0.0
+        ok = True
+    else:
+        ok = bool(lib().kpo_replay_edges(C.byref(pb.s), L - 1, _ptr(x), _ptr(u), _ptr(k),
+                                         float(margin), float(tol), C.byref(worst), C.byref(bad),
+                                         _ptr(end)))
+    c = np.asarray(p["goal_center"], np.float32).astype(np.float64)
+    reached = float(np.sqrt(np.sum((end[:3] - c) ** 2))) <= float(np.float32(p["goal_radius"])) + tol
+    valid = ok and worst.value <= rel_tol
+    return dict(valid=valid, reached=reached, worst=float(worst.value), first_bad=int(bad.value))
 
 
 # ---------------------------------------------------------------------------

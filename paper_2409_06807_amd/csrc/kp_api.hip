@@ -145,6 +145,8 @@ struct kp_problem {
   int grid_node_max;
   int grid_commit_max;
   int grid_head_max;
+  int lim_prop = 0, lim_node = 0;  // kp_set_launch_limits caps (0: none)
+  TraceRec* plan_trace = nullptr;  // kp_set_trace: per-lane records of kp_plan's expansions
   int stage;  // 0: next is kp_expand; 1: next is kp_update_regions; 2: next is kp_update_tree
   bool ctl_fresh = false;  // hctl holds the device control block (no launch since the last read)
   Ctl* hctl;  // pinned host mirror of the control block
@@ -188,45 +190,14 @@ kp_status hip_fail(kp_problem* h, hipError_t e, const char* what) {
   return fail(h, KP_E_DEVICE, msg);
 }
 
-// True when every state an RK4 or Euler stage of a quadcopter step can
-// reach keeps |roll|, |pitch| and the yaw increment of a stage within the
-// range of the tilt polynomials (1.8 rad, 1.75 used), given that the step
-// starts inside the state box (every expanded node and every state that
-// passed its step's check does):
-//   body rates: |w'_a| <= (|tau_a| + |I_b - I_c| |w_b| |w_c|) / I_a; the bound
-//     W = w_box + h w'(W) (fixed point) holds at every stage point;
-//   pitch: |theta'| = |q cos phi - r sin phi| <= W_y + W_z;
-//   roll: |phi'| <= W_x + (W_y + W_z) tan(theta_max);
-//   yaw: |psi'| <= (W_y + W_z) / cos(theta_max), times h for a stage increment.
-// The same variant also tests the state box as |x| <= hi outside position,
-// so it further needs lo = -hi exactly in those coordinates.
-bool quad_fast_ok(const kp_problem_desc& d) {
+// True when the quadcopter's state box is symmetric about zero in every
+// coordinate but position (lo = -hi exactly): the kernel then tests those
+// coordinates as |x| <= hi, one compare instead of two.
+bool quad_box_symmetric(const kp_problem_desc& d) {
   if (d.dynamics != KP_DYN_QUAD12) return false;
   for (int i = 3; i < 12; ++i)
     if (!(d.x_lo[i] == -d.x_hi[i])) return false;
-  auto amax = [&](int i) { return std::fmax(std::fabs((double)d.x_lo[i]), std::fabs((double)d.x_hi[i])); };
-  const double h = d.h, lim = 1.75;
-  const double I[3] = {d.dyn_params[2], d.dyn_params[3], d.dyn_params[4]};
-  double tau[3], w[3], W[3];
-  for (int a = 0; a < 3; ++a) {
-    if (!(I[a] > 0.0)) return false;
-    tau[a] = std::fmax(std::fabs((double)d.u_lo[1 + a]), std::fabs((double)d.u_hi[1 + a]));
-    w[a] = W[a] = amax(9 + a);
-  }
-  for (int it = 0; it < 32; ++it) {
-    const double dw0 = (tau[0] + std::fabs(I[1] - I[2]) * W[1] * W[2]) / I[0];
-    const double dw1 = (tau[1] + std::fabs(I[2] - I[0]) * W[2] * W[0]) / I[1];
-    const double dw2 = (tau[2] + std::fabs(I[0] - I[1]) * W[0] * W[1]) / I[2];
-    W[0] = w[0] + h * dw0;
-    W[1] = w[1] + h * dw1;
-    W[2] = w[2] + h * dw2;
-  }
-  for (int a = 0; a < 3; ++a) W[a] *= 1.01;  // the fixed point, rounded up
-  const double th = amax(4) + h * (W[1] + W[2]);
-  if (!(th < 1.45)) return false;
-  const double ph = amax(3) + h * (W[0] + (W[1] + W[2]) * std::tan(th));
-  const double dy = h * (W[1] + W[2]) / std::cos(th);
-  return std::isfinite(ph) && ph <= lim && th <= lim && dy <= lim;
+  return true;
 }
 
 void fill_params(kp_problem* h) {
@@ -272,7 +243,7 @@ void fill_params(kp_problem* h) {
   p.dIzx = p.Izz - p.Ixx;
   p.dIxy = p.Ixx - p.Iyy;
   p.dur_mode = d.duration_mode;
-  p.tilt_fast = quad_fast_ok(d) ? 1 : 0;
+  p.box_sym = quad_box_symmetric(d) ? 1 : 0;
   p.key0 = (uint32_t)d.seed;
   p.key1 = (uint32_t)(d.seed >> 32);
   p.delta = d.delta;
@@ -371,7 +342,7 @@ kp_status sync_ctl(kp_problem* h) {
 
 // propagate totals, kept per counter group on the device
 struct Totals {
-  unsigned long long lanes = 0, valid = 0, steps = 0, box = 0;
+  unsigned long long lanes = 0, valid = 0, steps = 0, box = 0, checked = 0;
 };
 Totals totals(const Ctl& c) {
   Totals t;
@@ -380,6 +351,7 @@ Totals totals(const Ctl& c) {
     t.valid += c.tot[g].valid;
     t.steps += c.tot[g].steps;
     t.box += c.tot[g].box;
+    t.checked += c.tot[g].checked;
   }
   return t;
 }
@@ -408,11 +380,24 @@ void prof_collect(kp_problem* h) {
   h->ev_used = 0;
 }
 
+// workgroup caps of a launch: the occupancy maxima, lowered by
+// kp_set_launch_limits (results do not depend on them)
+int cap_prop(const kp_problem* h) {
+  return (h->lim_prop > 0 && h->lim_prop < h->grid_prop_max) ? h->lim_prop : h->grid_prop_max;
+}
+int cap_node(const kp_problem* h) {
+  return (h->lim_node > 0 && h->lim_node < h->grid_node_max) ? h->lim_node : h->grid_node_max;
+}
+int cap_commit(const kp_problem* h) {
+  return (h->lim_node > 0 && h->lim_node < h->grid_commit_max) ? h->lim_node : h->grid_commit_max;
+}
+
 // n_nodes: |T| as the host knows it (exact: reset or a loaded tree)
 kp_status do_frontier(kp_problem* h, long long n_nodes) {
   h->ctl_fresh = false;
   const long long tiles = (n_nodes + kNodeTile - 1) / kNodeTile;
-  int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
+  const int gmax = cap_node(h);
+  int grid = (int)(tiles < gmax ? tiles : gmax);
   if (grid < 1) grid = 1;
   hipError_t e = launch_frontier(h->env_dev, grid, h->stream, prof_slot(h, 3));
   if (e != hipSuccess) return hip_fail(h, e, "frontier launch");
@@ -426,15 +411,17 @@ kp_status do_frontier(kp_problem* h, long long n_nodes) {
 kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_commit) {
   h->ctl_fresh = false;
   long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
-  int grid = (int)(tiles < h->grid_prop_max ? tiles : h->grid_prop_max);
+  const int gmax = cap_prop(h);
+  int grid = (int)(tiles < gmax ? tiles : gmax);
   if (grid < 1) grid = 1;
-  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm.tilt_fast, h->env_dev,
+  hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm.box_sym, h->env_dev,
                                   h->desc.n_obstacles, trace, grid, h->stream,
                                   prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
   if (!with_commit) return KP_OK;
   const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
-  int cgrid = (int)(ctiles < h->grid_commit_max ? ctiles : h->grid_commit_max);
+  const int cmax = cap_commit(h);
+  int cgrid = (int)(ctiles < cmax ? ctiles : cmax);
   if (cgrid < 1) cgrid = 1;
   e = launch_commit(h->env_dev, trace, cgrid, 0, h->stream, prof_slot(h, 4));
   if (e != hipSuccess) return hip_fail(h, e, "commit launch");
@@ -447,8 +434,9 @@ kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
   h->ctl_fresh = false;
   const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   const long long ntiles = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
-  const int nc = (int)(ctiles < h->grid_commit_max ? ctiles : h->grid_commit_max);
-  const int nn = (int)(ntiles < h->grid_node_max ? ntiles : h->grid_node_max);
+  const int cmax = cap_commit(h), nmax = cap_node(h);
+  const int nc = (int)(ctiles < cmax ? ctiles : cmax);
+  const int nn = (int)(ntiles < nmax ? ntiles : nmax);
   hipError_t e = launch_post(h->env_dev, nc, nn, h->stream, prof_slot(h, 5));
   if (e != hipSuccess) return hip_fail(h, e, "post launch");
   return KP_OK;
@@ -478,7 +466,8 @@ kp_status do_region(kp_problem* h) {
 kp_status do_nodesets(kp_problem* h, long long nodes_ub) {
   h->ctl_fresh = false;
   long long tiles = (nodes_ub + kNodeTile - 1) / kNodeTile;
-  int grid = (int)(tiles < h->grid_node_max ? tiles : h->grid_node_max);
+  const int gmax = cap_node(h);
+  int grid = (int)(tiles < gmax ? tiles : gmax);
   if (grid < 1) grid = 1;
   hipError_t e = launch_nodesets(h->env_dev, grid, h->stream, prof_slot(h, 2));
   if (e != hipSuccess) return hip_fail(h, e, "node sets launch");
@@ -588,7 +577,7 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
     return KP_E_DEVICE;
   }
   int bp = 1, bn = 1, bc = 1;
-  occupancy_propagate(desc->dynamics, desc->integrator, h->prm.tilt_fast, desc->n_obstacles, &bp);
+  occupancy_propagate(desc->dynamics, desc->integrator, h->prm.box_sym, desc->n_obstacles, &bp);
   occupancy_nodes(&bn);
   occupancy_commit(&bc);
   h->grid_prop_max = bp * h->cu_count;
@@ -713,7 +702,7 @@ kp_status kp_plan(kp_problem* h, kp_plan_result* out) {
       const long long lanes_ub = (b == 0) ? c.lanes : cap - c.N;
       const long long old_nodes_ub = (b == 0) ? (long long)c.N : cap;
       if ((st = do_head(h, (b == 0) ? (long long)c.nF : cap)) != KP_OK) return st;
-      if ((st = do_propagate(h, nullptr, lanes_ub, false)) != KP_OK) return st;
+      if ((st = do_propagate(h, h->plan_trace, lanes_ub, false)) != KP_OK) return st;
       if ((st = do_post(h, lanes_ub, old_nodes_ub)) != KP_OK) return st;
     }
     if ((st = sync_ctl(h)) != KP_OK) return st;
@@ -757,6 +746,7 @@ kp_status kp_get_stats(kp_problem* h, kp_iter_stats* out) {
   out->invalid_total = t.lanes - t.valid;
   out->steps_total = t.steps;
   out->box_tests_total = t.box;
+  out->checked_steps_total = t.checked;
   out->grid_propagate = h->grid_prop_max;
   out->grid_nodes = h->grid_node_max;
   return KP_OK;
@@ -923,6 +913,37 @@ kp_status kp_get_path(kp_problem* h, int32_t node, int32_t* ids, int32_t cap, in
   return KP_OK;
 }
 
+kp_status kp_get_trajectory(kp_problem* h, int32_t node, float* x, float* u, int32_t* steps,
+                            int32_t cap, int32_t* len) {
+  if (!h || !len) return KP_E_ARG;
+  if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_get_trajectory in the middle of an iteration");
+  int32_t n = 0;
+  kp_status st = kp_get_path(h, node, nullptr, 0, &n);
+  if (st != KP_OK) return st;
+  *len = n;
+  if (!x && !u && !steps) return KP_OK;
+  if (n > cap) return fail(h, KP_E_ARG, "kp_get_trajectory: buffers too small");
+  // the rows are gathered into the V_U staging area, unused between iterations
+  if ((size_t)n * kTrajRowWords > (size_t)h->dev.capP * (size_t)h->n)
+    return fail(h, KP_E_ARG, "kp_get_trajectory: path longer than the staging area holds");
+  hipError_t e = launch_path_gather(h->env_dev, n, h->dev.sx, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "path gather launch");
+  std::vector<float> rows((size_t)n * kTrajRowWords);
+  e = hipMemcpyAsync(rows.data(), h->dev.sx, rows.size() * sizeof(float), hipMemcpyDeviceToHost,
+                     h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "trajectory copy");
+  for (int32_t i = 0; i < n; ++i) {
+    const float* r = rows.data() + (size_t)i * kTrajRowWords;
+    if (x)
+      for (int k = 0; k < h->n; ++k) x[(size_t)i * h->n + k] = r[k];
+    if (u)
+      for (int j = 0; j < h->m; ++j) u[(size_t)i * h->m + j] = r[12 + j];
+    if (steps) std::memcpy(&steps[i], &r[16], 4);
+  }
+  return KP_OK;
+}
+
 kp_status kp_set_profiling(kp_problem* h, int32_t on) {
   if (!h) return KP_E_ARG;
   prof_collect(h);
@@ -940,6 +961,27 @@ kp_status kp_set_profiling(kp_problem* h, int32_t on) {
     }
   }
   h->prof = on != 0;
+  return KP_OK;
+}
+
+kp_status kp_set_trace(kp_problem* h, void* dev_trace) {
+  if (!h) return KP_E_ARG;
+  if (dev_trace && (reinterpret_cast<uintptr_t>(dev_trace) & 3u))
+    return fail(h, KP_E_ARG, "kp_set_trace: buffer not 4-byte aligned");
+  h->plan_trace = static_cast<TraceRec*>(dev_trace);
+  h->dev.trace = h->plan_trace;  // batched launches read it from the device environment
+  hipError_t e = upload_env(h);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "environment upload");
+  return KP_OK;
+}
+
+kp_status kp_set_launch_limits(kp_problem* h, int32_t prop_blocks, int32_t node_blocks) {
+  if (!h) return KP_E_ARG;
+  if (prop_blocks < 0 || node_blocks < 0)
+    return fail(h, KP_E_ARG, "kp_set_launch_limits: negative workgroup count");
+  h->lim_prop = prop_blocks;
+  h->lim_node = node_blocks;
   return KP_OK;
 }
 
@@ -1052,7 +1094,9 @@ kp_status kp_set_proposal(kp_problem* h, const void* dev_packed, float* dev_head
                           float mix) {
   if (!h) return KP_E_ARG;
   if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_set_proposal in the middle of an iteration");
-  if (!(mix >= 0.0f && mix <= 1.0f)) return fail(h, KP_E_ARG, "mix must be in [0, 1]");
+  // a uniform share 1 - mix > 0 keeps a positive density on all of U, which
+  // the completeness argument (Sec. V, Theorem 1) needs
+  if (!(mix >= 0.0f && mix < 1.0f)) return fail(h, KP_E_ARG, "mix must be in [0, 1)");
   const bool on = dev_packed != nullptr && mix > 0.0f;
   if (on) {
     if (!dev_head || head_rows < h->desc.node_cap || !aligned16(dev_packed) || !aligned16(dev_head))
@@ -1083,6 +1127,34 @@ kp_status kp_log_path(kp_problem* h, int32_t node, float* dev_x, float* dev_t, i
   return KP_OK;
 }
 
+kp_status kp_log_tree_edges(kp_problem* h, float* dev_x, float* dev_t, int32_t cap_rows,
+                            int32_t row0, int32_t* n_rows) {
+  if (!h || !n_rows || !dev_x || !dev_t || cap_rows < 0 || row0 < 0) return KP_E_ARG;
+  *n_rows = 0;
+  if (h->stage != 0) return fail(h, KP_E_ORDER, "kp_log_tree_edges in the middle of an iteration");
+  kp_status st = sync_ctl(h);
+  if (st != KP_OK) return st;
+  const int tiles = edge_tiles(h->hctl->N);
+  // per-tile counts in the per-wave-tile count array of the V_U staging,
+  // unused between iterations (it holds node_cap / 64 + 2 entries)
+  if ((long long)tiles > (long long)h->desc.node_cap / 64 + 2)
+    return fail(h, KP_E_ARG, "kp_log_tree_edges: tree too large for the count array");
+  uint32_t* tcount = h->dev.scount;
+  hipError_t e = launch_edge_count(h->env_dev, tiles, tcount, h->stream);
+  if (e == hipSuccess)
+    e = launch_edge_write(h->env_dev, tiles, tcount, dev_x, dev_t, cap_rows, row0, h->stream);
+  std::vector<uint32_t> counts((size_t)tiles);
+  if (e == hipSuccess && tiles > 0)
+    e = hipMemcpyAsync(counts.data(), tcount, counts.size() * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "tree edge logging");
+  long long total = 0;
+  for (uint32_t v : counts) total += v;
+  const long long room = (long long)cap_rows - row0;
+  *n_rows = (int32_t)(total < room ? total : (room > 0 ? room : 0));
+  return KP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batched planning
 // ---------------------------------------------------------------------------
@@ -1096,7 +1168,7 @@ struct kp_batch {
   hipStream_t stream = nullptr;       // the batch's own stream
   hipStream_t user_stream = nullptr;  // the problems' stream
   int dyn = 0, integ = 0, n_obs_max = 0;
-  int fast = 1;                       // every problem takes the fast tilt path
+  int sym = 1;                        // every problem's state box is symmetric
   int learned = 0;                    // some problem has a learned proposal (set per plan)
   int prop_max = 1, node_max = 1;     // single-problem grid maxima
   kp_batch_config cfg{};
@@ -1141,7 +1213,7 @@ hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_
   const int nc = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
   t = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
   const int nn = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
-  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->fast, b->table, n, b->n_obs_max,
+  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->sym, b->table, n, b->n_obs_max,
                                         gp < 1 ? 1 : gp, b->stream);
   if (e == hipSuccess) e = launch_post_batch(b->table, n, nc, nn, b->stream);
   return e;
@@ -1213,12 +1285,12 @@ kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_work
   for (int i = 0; i < n; ++i) {
     const kp_problem* h = problems[i];
     if (h->desc.n_obstacles > b->n_obs_max) b->n_obs_max = h->desc.n_obstacles;
-    if (!h->prm.tilt_fast) b->fast = 0;
+    if (!h->prm.box_sym) b->sym = 0;
     if (h->grid_node_max > node_max) node_max = h->grid_node_max;
     if (h->grid_commit_max > node_max) node_max = h->grid_commit_max;
   }
   int bp = 1;
-  occupancy_propagate(b->dyn, b->integ, b->fast, b->n_obs_max, &bp);
+  occupancy_propagate(b->dyn, b->integ, b->sym, b->n_obs_max, &bp);
   prop_max = bp * problems[0]->cu_count;
   b->prop_max = prop_max;
   b->node_max = node_max;

@@ -25,7 +25,10 @@ constexpr int32_t kNoGoal = 0x7fffffff;
 // chip serialise, about 11 ns each, so one shared line would throttle them.
 constexpr int kGroups = 8;
 struct alignas(128) TotLine {
-  unsigned long long lanes, valid, steps, box;
+  // lanes, valid lanes, integration steps, swept-box tests, and the steps
+  // whose state and swept box were tested (a lane stops testing at its first
+  // failing step but integrates on to the end of its segment)
+  unsigned long long lanes, valid, steps, box, checked;
 };
 struct alignas(128) TkLine {
   uint32_t v;
@@ -66,8 +69,7 @@ struct Params {
   int32_t n, m, K, cap;
   int32_t lambda_max, n_obs, S, R;
   int32_t dur_mode;         // 1: segment of 1 + (w * K >> 32) steps, w = word 1 of tag 1
-  int32_t tilt_fast;        // the state box keeps every RK4 stage's tilt within the polynomial range
-                            // and is symmetric about zero outside position
+  int32_t box_sym;          // quadcopter state box symmetric about zero outside position
   int32_t G[3];
   int32_t na[3];        // fine cells per axis = G * S
   float h, margin, goal_r2, rc;
@@ -88,6 +90,16 @@ struct Params {
   unsigned long long mix_thr;
   float fc[16], fs[16];
 };
+
+struct TraceRec {
+  int32_t parent, sample;
+  float u[4];
+  float x[12];
+  int32_t steps, fail_step, valid;
+  uint32_t cell;
+  int32_t goal, accept, new_id;
+};
+static_assert(sizeof(TraceRec) == 100, "trace record layout");
 
 // Device pointers carved from the caller's workspace.
 struct Dev {
@@ -121,21 +133,13 @@ struct Dev {
   int32_t* path;       // [kMaxPath + 1]
   const uint4* mlp;    // packed network (kp_mlp_pack layout), borrowed; null if uniform
   float* head;         // [rows][8] Gaussian mean (4) and std (4) per frontier entry, borrowed
+  TraceRec* trace;     // per-lane records of the planning loop's expansions (kp_set_trace), or null
   int32_t capP;        // padded node capacity (multiple of kNodeTile)
   int32_t tiles_node;  // entries of st_front / st_nodes
   int32_t nchunk;      // entries of ssum
   int32_t pad;
 };
 
-struct TraceRec {
-  int32_t parent, sample;
-  float u[4];
-  float x[12];
-  int32_t steps, valid;
-  uint32_t cell;
-  int32_t goal, accept, new_id;
-};
-static_assert(sizeof(TraceRec) == 96, "trace record layout");
 
 // Everything a kernel needs besides per-launch arguments; lives in device
 // memory (start of the workspace) so kernels read it through one pointer
@@ -157,7 +161,7 @@ struct Timing {
 hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s);
 hipError_t launch_root(const Env* env, Vec12 x_init, hipStream_t s);
 hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t);
-hipError_t launch_propagate(int dyn, int integ, int fast, const Env* env, int n_obs,
+hipError_t launch_propagate(int dyn, int integ, int sym, const Env* env, int n_obs,
                             TraceRec* trace, int grid, hipStream_t s, Timing t);
 hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
                          hipStream_t s, Timing t);
@@ -165,13 +169,16 @@ hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
 hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s, Timing t);
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
+// rows of kTrajWords words (state, control, steps) of the path k_path wrote
+constexpr int kTrajRowWords = 17;
+hipError_t launch_path_gather(const Env* env, int32_t len, float* out, hipStream_t s);
 
 // batched planning: one grid row (blockIdx.y) per problem of an Env* table
 struct BatchStatus {
   int32_t done, N, nF, lanes, iters_done, goal_id, err, pad;
   unsigned long long lanes_total, valid_total;
 };
-hipError_t launch_propagate_batch(int dyn, int integ, int fast, const Env* const* envs, int n,
+hipError_t launch_propagate_batch(int dyn, int integ, int sym, const Env* const* envs, int n,
                                   int n_obs_max, int grid, hipStream_t s);
 hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
                              hipStream_t s);
@@ -200,7 +207,11 @@ hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* par
                            float inv_bc1, float inv_bc2, hipStream_t s);
 hipError_t launch_log_path(const Env* env, float* x, float* t, int32_t cap_rows, int32_t row0,
                            hipStream_t s);
-int occupancy_propagate(int dyn, int integ, int fast, int n_obs, int* blocks_per_cu);
+int edge_tiles(int32_t n_nodes);
+hipError_t launch_edge_count(const Env* env, int tiles, uint32_t* tcount, hipStream_t s);
+hipError_t launch_edge_write(const Env* env, int tiles, const uint32_t* tcount, float* x, float* t,
+                             int32_t cap_rows, int32_t row0, hipStream_t s);
+int occupancy_propagate(int dyn, int integ, int sym, int n_obs, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
 int occupancy_commit(int* blocks_per_cu);
 size_t propagate_lds_bytes(int n_obs);

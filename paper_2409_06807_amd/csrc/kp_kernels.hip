@@ -310,10 +310,11 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
 // increment.  For |x| <= 1.8, near-minimax polynomials on [-1.8, 1.8] of
 // degree 9 (sin, odd) and 10 (cos, even) apply with no reduction: measured
 // in FP32 Horner form against FP64 sin / cos on 2e6 points, sin is within
-// 2.6 ulp and cos within 1.1e-7 absolute.  FAST: the caller guarantees
-// |x| <= 1.8 (see quad_fast_ok on the host), so no check.  Otherwise a wave
-// with any larger angle also runs the full reduction for those lanes.
-template <bool FAST>
+// 2.6 ulp and cos within 1.1e-7 absolute.  A state inside the valid box keeps
+// every stage's angles in that range, but a segment that has left the box
+// is still integrated to its end (x' of Alg. 2), and its angles can grow
+// without bound; a wave with any larger angle also runs the full reduction
+// for those lanes.
 __device__ __forceinline__ void sincos_tilt(float x, float* s, float* c) {
   const float t = x * x;
   float ps = __builtin_fmaf(t, 0x1.5880bep-19f, -0x1.9f1b8cp-13f);
@@ -325,26 +326,24 @@ __device__ __forceinline__ void sincos_tilt(float x, float* s, float* c) {
   pc = __builtin_fmaf(t, pc, 0x1.55553ep-5f);
   pc = __builtin_fmaf(t, pc, -0.5f);
   float cv = __builtin_fmaf(t, pc, 1.0f);
-  if constexpr (!FAST) {
-    const bool big = !(__builtin_fabsf(x) <= 1.8f);  // NaN too
-    if (__builtin_expect(__ballot(big) != 0ull, 0)) {
-      float s2, c2;
-      sincos_rr(x, &s2, &c2);
-      sv = big ? s2 : sv;
-      cv = big ? c2 : cv;
-    }
+  const bool big = !(__builtin_fabsf(x) <= 1.8f);  // NaN too
+  if (__builtin_expect(__ballot(big) != 0ull, 0)) {
+    float s2, c2;
+    sincos_rr(x, &s2, &c2);
+    sv = big ? s2 : sv;
+    cv = big ? c2 : cv;
   }
   *s = sv;
   *c = cv;
 }
 
 // rigid-body quadcopter, ZYX Euler angles, inertial velocity, body rates
-template <bool FAST, class PP>
+template <class PP>
 __device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const float* u,
                                            float* dx) {
   float sf, cf, st, ct, sp, cp;
-  sincos_tilt<FAST>(x[3], &sf, &cf);
-  sincos_tilt<FAST>(x[4], &st, &ct);
+  sincos_tilt(x[3], &sf, &cf);
+  sincos_tilt(x[4], &st, &ct);
   sincos_rr(x[5], &sp, &cp);
   const float ict = __builtin_amdgcn_rcpf(ct);  // 1 ulp; |theta| stays far from pi/2
   const float P = x[9], Q = x[10], R = x[11];
@@ -366,12 +365,12 @@ __device__ __forceinline__ void deriv_quad(const PP& p, const float* x, const fl
 }
 
 // the quadcopter derivative with sin / cos of the yaw angle supplied
-template <bool FAST, class PP>
+template <class PP>
 __device__ __forceinline__ void deriv_quad_y(const PP& p, const float* x, const float* u, float sp,
                                              float cp, float* dx) {
   float sf, cf, st, ct;
-  sincos_tilt<FAST>(x[3], &sf, &cf);
-  sincos_tilt<FAST>(x[4], &st, &ct);
+  sincos_tilt(x[3], &sf, &cf);
+  sincos_tilt(x[4], &st, &ct);
   const float ict = __builtin_amdgcn_rcpf(ct);
   const float P = x[9], Q = x[10], R = x[11];
   const float a = __builtin_fmaf(Q, sf, R * cf);
@@ -393,84 +392,108 @@ __device__ __forceinline__ void deriv_quad_y(const PP& p, const float* x, const 
 
 // sin / cos of psi0 + d from those of psi0 (angle addition); d is an RK4
 // stage's yaw increment, so sin d and cos d take the short polynomials
-template <bool FAST>
 __device__ __forceinline__ void sincos_shift(float s0, float c0, float d, float* s, float* c) {
   float sd, cd;
-  sincos_tilt<FAST>(d, &sd, &cd);
+  sincos_tilt(d, &sd, &cd);
   *s = __builtin_fmaf(s0, cd, c0 * sd);
   *c = __builtin_fmaf(c0, cd, -(s0 * sd));
 }
 
-template <int DYN, bool FAST, class PP>
+template <int DYN, class PP>
 __device__ __forceinline__ void deriv(const PP& p, const float* x, const float* u, float* dx) {
   if constexpr (DYN == KP_DYN_DI6) deriv_di(p, x, u, dx);
-  else deriv_quad<FAST>(p, x, u, dx);
+  else deriv_quad(p, x, u, dx);
 }
 
-template <int DYN, int INTEG, bool FAST, class PP>
-__device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u) {
+// Yaw frame of a quadcopter segment.  The yaw is unbounded (the state box
+// allows hundreds of radians), and an FP32 angle near 16 rad is stored to
+// about 1e-6 rad, an error that the thrust direction turns into velocity
+// errors of ~1e-5 over a segment when it accumulates step by step.  So a
+// segment keeps its start angle psi0 (its parent's stored value, an exact
+// input) with that angle's sine and cosine, and integrates the offset
+// d = psi - psi0, which stays small; sin / cos of psi0 + d follow by angle
+// addition, and the state's yaw is psi0 + d rounded once.
+struct YawFrame {
+  float s0, c0, psi0, d;
+};
+
+template <int DYN, int INTEG, class PP>
+__device__ __forceinline__ void integ_step(const PP& p, float* x, const float* u, YawFrame& y) {
   constexpr int n = Dim<DYN>::n;
   const float h = p.h;
-  if constexpr (INTEG == KP_INT_EULER) {
+  if constexpr (DYN == KP_DYN_QUAD12 && INTEG == KP_INT_EULER) {
+    float sp, cp, k1[n];
+    sincos_shift(y.s0, y.c0, y.d, &sp, &cp);
+    deriv_quad_y(p, x, u, sp, cp, k1);
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+      if (i != 5) x[i] = __builtin_fmaf(h, k1[i], x[i]);
+    y.d = __builtin_fmaf(h, k1[5], y.d);
+    x[5] = y.psi0 + y.d;
+  } else if constexpr (INTEG == KP_INT_EULER) {
     float k1[n];
-    deriv<DYN, FAST>(p, x, u, k1);
+    deriv<DYN>(p, x, u, k1);
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h, k1[i], x[i]);
   } else if constexpr (DYN == KP_DYN_QUAD12) {
-    // yaw: one full reduction per step; the stages shift it by their increments
+    // the step's yaw from the segment frame; the stages shift it by their
+    // increments
     const float hh = 0.5f * h;
     const float h6 = h * (1.0f / 6.0f);
     float sp0, cp0, sp, cp;
-    sincos_rr(x[5], &sp0, &cp0);
+    sincos_shift(y.s0, y.c0, y.d, &sp0, &cp0);
     float t[n], k[n], acc[n];
-    deriv_quad_y<FAST>(p, x, u, sp0, cp0, k);
+    deriv_quad_y(p, x, u, sp0, cp0, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = k[i];
       t[i] = __builtin_fmaf(hh, k[i], x[i]);
     }
-    sincos_shift<FAST>(sp0, cp0, hh * k[5], &sp, &cp);
-    deriv_quad_y<FAST>(p, t, u, sp, cp, k);
+    sincos_shift(sp0, cp0, hh * k[5], &sp, &cp);
+    deriv_quad_y(p, t, u, sp, cp, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(hh, k[i], x[i]);
     }
-    sincos_shift<FAST>(sp0, cp0, hh * k[5], &sp, &cp);
-    deriv_quad_y<FAST>(p, t, u, sp, cp, k);
+    sincos_shift(sp0, cp0, hh * k[5], &sp, &cp);
+    deriv_quad_y(p, t, u, sp, cp, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(h, k[i], x[i]);
     }
-    sincos_shift<FAST>(sp0, cp0, h * k[5], &sp, &cp);
-    deriv_quad_y<FAST>(p, t, u, sp, cp, k);
+    sincos_shift(sp0, cp0, h * k[5], &sp, &cp);
+    deriv_quad_y(p, t, u, sp, cp, k);
 #pragma unroll
-    for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
+    for (int i = 0; i < n; ++i)
+      if (i != 5) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
+    y.d = __builtin_fmaf(h6, acc[5] + k[5], y.d);
+    x[5] = y.psi0 + y.d;
   } else {
     const float hh = 0.5f * h;
     const float h6 = h * (1.0f / 6.0f);
     float k1[n];
-    deriv<DYN, FAST>(p, x, u, k1);
+    deriv<DYN>(p, x, u, k1);
     float t[n], k[n], acc[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = k1[i];
       t[i] = __builtin_fmaf(hh, k1[i], x[i]);
     }
-    deriv<DYN, FAST>(p, t, u, k);
+    deriv<DYN>(p, t, u, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(hh, k[i], x[i]);
     }
-    deriv<DYN, FAST>(p, t, u, k);
+    deriv<DYN>(p, t, u, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       acc[i] = __builtin_fmaf(2.0f, k[i], acc[i]);
       t[i] = __builtin_fmaf(h, k[i], x[i]);
     }
-    deriv<DYN, FAST>(p, t, u, k);
+    deriv<DYN>(p, t, u, k);
 #pragma unroll
     for (int i = 0; i < n; ++i) x[i] = __builtin_fmaf(h6, acc[i] + k[i], x[i]);
   }
@@ -574,6 +597,7 @@ __device__ void clear_counters(Ctl* c) {
   c->goal_hit = 0u;
   for (int g = 0; g < kGroups; ++g) {
     c->tot[g].lanes = c->tot[g].valid = c->tot[g].steps = c->tot[g].box = 0ull;
+    c->tot[g].checked = 0ull;
     c->tkp[g].v = 0u;
   }
 }
@@ -747,7 +771,8 @@ constexpr size_t prop_lds_bytes(int n_obs) {
   return kBoundsFloats * sizeof(float) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
          (size_t)(kPropBlock / 64) * wave_lds_bytes(n_obs);
 }
-static_assert(prop_lds_bytes(KP_MAX_OBSTACLES) <= 65536, "propagate LDS above 64 KiB");
+// gfx950 gives a workgroup up to 160 KiB of LDS
+static_assert(prop_lds_bytes(KP_MAX_OBSTACLES) <= 160 * 1024, "propagate LDS above 160 KiB");
 size_t propagate_lds_bytes(int n_obs) { return prop_lds_bytes(n_obs); }
 
 
@@ -764,7 +789,7 @@ __device__ __forceinline__ float box_separation(float lx, float ly, float lz, fl
   return fmaxf(s0, s1);
 }
 
-template <int DYN, int INTEG, bool FAST>
+template <int DYN, int INTEG, bool SYM>
 __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, TraceRec* trace) {
   const Params& p = env->p;
   const Dev& d = env->d;
@@ -807,7 +832,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   uint16_t* glist = cand + union_stride(n_obs);
   uint32_t* gcnt = reinterpret_cast<uint32_t*>(glist + kGroupsPerWave * kGroupStride);
   // per-wave running totals (wave-uniform), flushed once per block
-  unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0;
+  unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0, t_checked = 0;
 
   // A wave's first tile is its index in the grid.  Later tiles come from
   // per-group ticket counters: group q (block index mod ng) hands out tiles
@@ -972,48 +997,58 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 
-    // Segment integration with per-step validity; x' is the segment end or
-    // the first failing state.
+    // x' = PropagateODE(x, u, dt): every lane integrates its whole segment.
+    // Validity is decided step by step along the way (state box, then the
+    // swept box against the candidate obstacles); a lane that fails keeps
+    // integrating to its end without further tests, since x' of an invalid
+    // sample still decides which region's n_invalid it counts in (Alg. 2).
+    YawFrame yf{0.0f, 1.0f, 0.0f, 0.0f};
+    if constexpr (DYN == KP_DYN_QUAD12) {
+      yf.psi0 = x[5];
+      sincos_rr(x[5], &yf.s0, &yf.c0);
+    }
     bool alive = active;
     bool valid = active;
     int32_t steps = 0;
+    int32_t fstep = 0;   // first failing step (0 while none)
     uint32_t box_tests = 0;
     for (int j = 0; j < K; ++j) {
       if (__ballot(alive) == 0ull) break;
       if (alive) {
         const float px = x[0], py = x[1], pz = x[2];
-        integ_step<DYN, INTEG, FAST>(sc, x, u);
+        integ_step<DYN, INTEG>(sc, x, u, yf);
         steps = j + 1;
-        bool ok;
-        if constexpr (DYN == KP_DYN_QUAD12 && FAST) ok = state_ok_lds_sym(bnd, x);
-        else ok = state_ok_lds<DYN>(bnd, x);
-        if (ok) {
-          const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
-          const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;
-          const float lz = fminf(pz, x[2]) - margin, hz = fmaxf(pz, x[2]) + margin;
-          // six comparisons per candidate (closed boxes: touching is a hit);
-          // measured faster here than the separation form used for culling.
-          // Two candidates per trip (one 32-bit read of their indices) so
-          // that their LDS reads overlap.
-          bool hit = false;
-          for (uint32_t q = 0; q < kmax; q += 2) {
-            const uint32_t ij = *reinterpret_cast<const uint32_t*>(my + q);
-            const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
-            const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
-            hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
-                   (o[2] <= hz);
-            hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
-                   (r[2] <= hz);
+        if (valid) {
+          bool ok;
+          if constexpr (DYN == KP_DYN_QUAD12 && SYM) ok = state_ok_lds_sym(bnd, x);
+          else ok = state_ok_lds<DYN>(bnd, x);
+          if (ok) {
+            const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
+            const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;
+            const float lz = fminf(pz, x[2]) - margin, hz = fmaxf(pz, x[2]) + margin;
+            // six comparisons per candidate (closed boxes: touching is a hit);
+            // measured faster here than the separation form used for culling.
+            // Two candidates per trip (one 32-bit read of their indices) so
+            // that their LDS reads overlap.
+            bool hit = false;
+            for (uint32_t q = 0; q < kmax; q += 2) {
+              const uint32_t ij = *reinterpret_cast<const uint32_t*>(my + q);
+              const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
+              const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
+              hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
+                     (o[2] <= hz);
+              hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
+                     (r[2] <= hz);
+            }
+            box_tests += mycnt;
+            ok = !hit;
           }
-          box_tests += mycnt;
-          ok = !hit;
+          if (!ok) {
+            valid = false;
+            fstep = j + 1;
+          }
         }
-        if (!ok) {
-          alive = false;
-          valid = false;
-        } else if (j + 1 == kl) {
-          alive = false;  // the segment's duration is over
-        }
+        if (j + 1 == kl) alive = false;  // the segment's duration is over
       }
     }
 
@@ -1079,6 +1114,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
 #pragma unroll
       for (int k = 0; k < 12; ++k) t->x[k] = (k < n) ? x[k] : 0.0f;
       t->steps = steps;
+      t->fail_step = valid ? steps + 1 : fstep;
       t->valid = valid ? 1 : 0;
       t->cell = cl;
       t->goal = goal ? 1 : 0;
@@ -1093,27 +1129,30 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     t_lanes += (unsigned long long)__popcll(__ballot(active));
     t_valid += (unsigned long long)__popcll(__ballot(active && valid));
     t_steps += wave_sum_u64((unsigned long long)steps);
+    t_checked += wave_sum_u64((unsigned long long)(valid ? steps : fstep));
     t_box += wave_sum_u64((unsigned long long)box_tests);
   }
 
-  __shared__ unsigned long long s_tot[kPropBlock / 64][4];
+  __shared__ unsigned long long s_tot[kPropBlock / 64][5];
   if (__lane_id() == 0) {
     s_tot[wave][0] = t_lanes;
     s_tot[wave][1] = t_valid;
     s_tot[wave][2] = t_steps;
     s_tot[wave][3] = t_box;
+    s_tot[wave][4] = t_checked;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long a[4] = {0, 0, 0, 0};
+    unsigned long long a[5] = {0, 0, 0, 0, 0};
     for (int w = 0; w < kPropBlock / 64; ++w)
-      for (int q = 0; q < 4; ++q) a[q] += s_tot[w][q];
+      for (int q = 0; q < 5; ++q) a[q] += s_tot[w][q];
     if (a[0]) {
       TotLine* t = &c->tot[blockIdx.x % kGroups];
       atomicAdd(&t->lanes, a[0]);
       atomicAdd(&t->valid, a[1]);
       atomicAdd(&t->steps, a[2]);
       atomicAdd(&t->box, a[3]);
+      atomicAdd(&t->checked, a[4]);
     }
   }
 }
@@ -1658,18 +1697,20 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
 
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
 // batched launch over a table of problems; the work of each problem is the
-// same either way.  Waves per SIMD: the branch-free quadcopter kernel fits
-// 96 registers without spills and runs 5; the variant with the tilt range
-// check and the batched quadcopter kernel would spill there and keep 4.
-template <int DYN, int INTEG, bool FAST>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : (FAST ? 5 : 4)))) void k_propagate(
+// same either way.  Waves per SIMD: the double-integrator kernels fit 96
+// registers and run 5; the quadcopter kernels need more than 96 (the tilt
+// sin / cos keep their range-checked reduction for segments that have left
+// the state box) and run 4.
+template <int DYN, int INTEG, bool SYM>
+__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate(
     const Env* __restrict__ env, TraceRec* trace) {
-  propagate_body<DYN, INTEG, FAST>(env, trace);
+  propagate_body<DYN, INTEG, SYM>(env, trace);
 }
-template <int DYN, int INTEG, bool FAST>
+template <int DYN, int INTEG, bool SYM>
 __global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate_batch(
     const Env* const* __restrict__ envs) {
-  propagate_body<DYN, INTEG, FAST>(envs[blockIdx.y], nullptr);
+  const Env* env = envs[blockIdx.y];
+  propagate_body<DYN, INTEG, SYM>(env, env->d.trace);
 }
 
 __global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
@@ -1723,6 +1764,32 @@ __global__ void k_path(const Env* __restrict__ env, int32_t node) {
   for (int32_t v = node; v >= 0; v = d.parent[v]) d.path[k--] = v;
 }
 
+// Rows of the trajectory along the path k_path wrote: row i holds the state
+// of path node i (12 floats), the control of the edge into it (4 floats) and
+// that edge's integration steps (as an int), 17 words, in `out`.
+constexpr int kTrajWords = 17;
+__global__ void k_path_gather(const Env* __restrict__ env, int32_t len, float* __restrict__ out) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const int32_t v = d.path[1 + i];
+  float* r = out + (size_t)i * kTrajWords;
+  for (int k = 0; k < 12; ++k) r[k] = (k < p.n) ? d.x[(size_t)k * d.capP + v] : 0.0f;
+  for (int j = 0; j < 4; ++j) r[12 + j] = (j < p.m) ? d.u[(size_t)j * d.capP + v] : 0.0f;
+  int32_t ks = 0;
+  const int32_t par = d.parent[v];
+  if (par >= 0) {
+    ks = p.K;
+    if (p.dur_mode) {
+      const U4 w1 = philox((uint32_t)d.birth[v], (uint32_t)par, (uint32_t)d.sample[v], 1u, p.key0,
+                           p.key1);
+      ks = 1 + (int32_t)__umulhi(w1.w[1], (uint32_t)p.K);
+    }
+  }
+  r[16] = __int_as_float(ks);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1752,26 +1819,26 @@ hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t) {
   return hipGetLastError();
 }
 
-template <int DYN, int INTEG, bool FAST>
+template <int DYN, int INTEG, bool SYM>
 static hipError_t launch_prop_t(const Env* env, int n_obs, TraceRec* trace, int grid,
                                 hipStream_t s, Timing t) {
-  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG, FAST>), dim3(grid), dim3(kPropBlock),
+  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG, SYM>), dim3(grid), dim3(kPropBlock),
                         (uint32_t)propagate_lds_bytes(n_obs), s, t.start, t.stop, 0, env, trace);
   return hipGetLastError();
 }
 
-// fast: the problem's state box keeps every tilt angle the quadcopter's RK4
-// stages can reach inside the polynomial range (no per-call range check)
-hipError_t launch_propagate(int dyn, int integ, int fast, const Env* env, int n_obs,
+// sym: the quadcopter's state box is symmetric about zero outside position,
+// so its test is |x| <= hi there
+hipError_t launch_propagate(int dyn, int integ, int sym, const Env* env, int n_obs,
                             TraceRec* trace, int grid, hipStream_t s, Timing t) {
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
     return launch_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(env, n_obs, trace, grid, s, t);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
     return launch_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(env, n_obs, trace, grid, s, t);
   if (integ == KP_INT_EULER)
-    return fast ? launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(env, n_obs, trace, grid, s, t)
+    return sym ? launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(env, n_obs, trace, grid, s, t)
                 : launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(env, n_obs, trace, grid, s, t);
-  return fast ? launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(env, n_obs, trace, grid, s, t)
+  return sym ? launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(env, n_obs, trace, grid, s, t)
               : launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(env, n_obs, trace, grid, s, t);
 }
 
@@ -1802,15 +1869,15 @@ hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t) {
   return hipGetLastError();
 }
 
-template <int DYN, int INTEG, bool FAST>
+template <int DYN, int INTEG, bool SYM>
 static hipError_t launch_prop_batch_t(const Env* const* envs, int n, int n_obs_max, int grid,
                                       hipStream_t s) {
-  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG, FAST>), dim3(grid, n), dim3(kPropBlock),
+  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG, SYM>), dim3(grid, n), dim3(kPropBlock),
                      (uint32_t)propagate_lds_bytes(n_obs_max), s, envs);
   return hipGetLastError();
 }
 
-hipError_t launch_propagate_batch(int dyn, int integ, int fast, const Env* const* envs, int n,
+hipError_t launch_propagate_batch(int dyn, int integ, int sym, const Env* const* envs, int n,
                                   int n_obs_max, int grid, hipStream_t s) {
   if (grid < 1) grid = 1;
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
@@ -1818,9 +1885,9 @@ hipError_t launch_propagate_batch(int dyn, int integ, int fast, const Env* const
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
     return launch_prop_batch_t<KP_DYN_DI6, KP_INT_RK4, false>(envs, n, n_obs_max, grid, s);
   if (integ == KP_INT_EULER)
-    return fast ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, true>(envs, n, n_obs_max, grid, s)
+    return sym ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, true>(envs, n, n_obs_max, grid, s)
                 : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, false>(envs, n, n_obs_max, grid, s);
-  return fast ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, true>(envs, n, n_obs_max, grid, s)
+  return sym ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, true>(envs, n, n_obs_max, grid, s)
               : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, false>(envs, n, n_obs_max, grid, s);
 }
 
@@ -1843,31 +1910,66 @@ hipError_t launch_set_done(const Env* env, int32_t code, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_path_gather(const Env* env, int32_t len, float* out, hipStream_t s) {
+  if (len < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_path_gather, dim3((len + 255) / 256), dim3(256), 0, s, env, len, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s) {
   hipLaunchKernelGGL(k_path, dim3(1), dim3(64), 0, s, env, node);
   return hipGetLastError();
 }
 
-template <int DYN, int INTEG, bool FAST>
+// Dynamic LDS above 64 KiB (obstacle tables of more than ~1500 boxes) needs
+// each propagate kernel's limit raised once; gfx950 gives a workgroup up to
+// 160 KiB.  Done before the first occupancy query (at problem creation), so
+// never inside a captured graph.
+template <int DYN, int INTEG, bool SYM>
+static hipError_t allow_lds_t() {
+  const int bytes = (int)prop_lds_bytes(KP_MAX_OBSTACLES);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<DYN, INTEG, SYM>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate_batch<DYN, INTEG, SYM>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+static hipError_t allow_lds_all() {
+  static const hipError_t once = [] {
+    hipError_t e = allow_lds_t<KP_DYN_DI6, KP_INT_EULER, false>();
+    if (e == hipSuccess) e = allow_lds_t<KP_DYN_DI6, KP_INT_RK4, false>();
+    if (e == hipSuccess) e = allow_lds_t<KP_DYN_QUAD12, KP_INT_EULER, false>();
+    if (e == hipSuccess) e = allow_lds_t<KP_DYN_QUAD12, KP_INT_EULER, true>();
+    if (e == hipSuccess) e = allow_lds_t<KP_DYN_QUAD12, KP_INT_RK4, false>();
+    if (e == hipSuccess) e = allow_lds_t<KP_DYN_QUAD12, KP_INT_RK4, true>();
+    return e;
+  }();
+  return once;
+}
+
+template <int DYN, int INTEG, bool SYM>
 static int occ_prop_t(int n_obs) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG, FAST>, kPropBlock,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG, SYM>, kPropBlock,
                                                     propagate_lds_bytes(n_obs)) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-int occupancy_propagate(int dyn, int integ, int fast, int n_obs, int* blocks_per_cu) {
+int occupancy_propagate(int dyn, int integ, int sym, int n_obs, int* blocks_per_cu) {
   int nb;
+  // if raising the limit fails, launches above 64 KiB of LDS fail and
+  // report it; clear the error so that it does not surface at another call
+  if (allow_lds_all() != hipSuccess) (void)hipGetLastError();
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
     nb = occ_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(n_obs);
   else if (dyn == KP_DYN_DI6)
     nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(n_obs);
   else if (integ == KP_INT_EULER)
-    nb = fast ? occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(n_obs)
+    nb = sym ? occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(n_obs)
               : occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(n_obs);
   else
-    nb = fast ? occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(n_obs)
+    nb = sym ? occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(n_obs)
               : occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(n_obs);
   *blocks_per_cu = nb;
   return nb;

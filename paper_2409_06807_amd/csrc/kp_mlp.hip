@@ -17,6 +17,8 @@
 //                  (Kingma & Ba, 2015)
 //   k_log_path     training rows (parent features, normalised control) from
 //                  the edges of a root-to-node path
+//   k_edge_count,  training rows from every tree edge whose child lies closer
+//   k_edge_write   to the goal centre than its parent, in node id order
 //
 // Layout of the network in registers.  Every product is computed transposed,
 // out^T = W * in^T, so the weights are the A operand (16 x 32 per MFMA) and
@@ -712,6 +714,111 @@ __global__ __launch_bounds__(256) void k_log_path(const Env* __restrict__ env, f
   }
 }
 
+// Tree edges that move towards the goal: edge (parent(i), i) qualifies when
+// node i's position is strictly closer to the goal centre than its parent's.
+// Rows are written in node id order (a count pass per 4096-node tile, then a
+// write pass that sums the earlier tiles' counts), so the row set and its
+// order do not depend on the schedule.
+constexpr int kEdgeTile = 4096;
+constexpr int kEdgeBlock = 256;
+constexpr int kEdgePerThread = kEdgeTile / kEdgeBlock;  // 16 consecutive nodes per thread
+
+__device__ __forceinline__ bool edge_closer(const Params& p, const Dev& d, int32_t i) {
+  const int32_t a = d.parent[i];
+  if (a < 0) return false;
+  float dc = 0.0f, da = 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    const float ec = d.x[(size_t)k * d.capP + i] - p.goal_c[k];
+    const float ea = d.x[(size_t)k * d.capP + a] - p.goal_c[k];
+    dc = __builtin_fmaf(ec, ec, dc);
+    da = __builtin_fmaf(ea, ea, da);
+  }
+  return dc < da;
+}
+
+__device__ __forceinline__ uint32_t edge_bits(const Params& p, const Dev& d, int32_t N,
+                                              int32_t base) {
+  uint32_t bits = 0;
+  for (int k = 0; k < kEdgePerThread; ++k) {
+    const int32_t i = base + k;
+    if (i < N && edge_closer(p, d, i)) bits |= 1u << k;
+  }
+  return bits;
+}
+
+// block-wide exclusive prefix of per-thread counts; *total gets the sum
+__device__ __forceinline__ uint32_t edge_block_prefix(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t s_w[kEdgeBlock / 64];
+  const int w = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << __lane_id()) - 1ull;
+  uint32_t ex = 0, tot = 0;
+  for (int b = 0; b < 5; ++b) {   // counts are at most 16
+    const unsigned long long m = __ballot((v >> b) & 1u);
+    ex += (uint32_t)__popcll(m & below) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  if (__lane_id() == 0) s_w[w] = tot;
+  __syncthreads();
+  uint32_t off = 0, all = 0;
+  for (int k = 0; k < kEdgeBlock / 64; ++k) {
+    off += (k < w) ? s_w[k] : 0u;
+    all += s_w[k];
+  }
+  *total = all;
+  return off + ex;
+}
+
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_count(const Env* __restrict__ env,
+                                                           uint32_t* __restrict__ tcount) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  const int32_t N = d.ctl->N;
+  const int32_t base = blockIdx.x * kEdgeTile + threadIdx.x * kEdgePerThread;
+  const uint32_t bits = edge_bits(p, d, N, base);
+  uint32_t total;
+  (void)edge_block_prefix((uint32_t)__popc(bits), &total);
+  if (threadIdx.x == 0) tcount[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_write(const Env* __restrict__ env,
+                                                           const uint32_t* __restrict__ tcount,
+                                                           float* __restrict__ X,
+                                                           float* __restrict__ T,
+                                                           int32_t cap_rows, int32_t row0) {
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  const int32_t N = d.ctl->N;
+  __shared__ uint32_t s_pre;
+  if (threadIdx.x < 64) {
+    uint32_t part = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += 64) part += tcount[t];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (threadIdx.x == 0) s_pre = part;
+  }
+  __syncthreads();
+  const int32_t base = blockIdx.x * kEdgeTile + threadIdx.x * kEdgePerThread;
+  uint32_t bits = edge_bits(p, d, N, base);
+  uint32_t total;
+  const uint32_t off = edge_block_prefix((uint32_t)__popc(bits), &total);
+  int64_t row = (int64_t)row0 + s_pre + off;
+  while (bits) {
+    const int k = __ffs(bits) - 1;
+    bits &= bits - 1u;
+    if (row >= cap_rows) break;
+    const int32_t child = base + k, parent = d.parent[child];
+    const float pacc = node_pacc(d, parent);
+    for (int j = 0; j < kMlpIn; ++j)
+      X[(size_t)row * kMlpIn + j] = (raw_feature(p, d, parent, j, pacc) - p.fc[j]) * p.fs[j];
+    for (int j = 0; j < 4; ++j) {
+      const float lo = p.u_lo[j], hi = p.u_hi[j];
+      const float ctr = 0.5f * (lo + hi), half = 0.5f * (hi - lo);
+      T[(size_t)row * 4 + j] =
+          (j < p.m && half > 0.0f) ? (d.u[(size_t)j * d.capP + child] - ctr) / half : 0.0f;
+    }
+    ++row;
+  }
+}
+
 }  // namespace
 
 size_t mlp_packed_bytes() { return kPackedBytes; }
@@ -764,6 +871,22 @@ hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* par
                            float inv_bc1, float inv_bc2, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, m1, m2,
                      partials, n_partials, lr, beta1, beta2, eps, inv_bc1, inv_bc2);
+  return hipGetLastError();
+}
+
+int edge_tiles(int32_t n_nodes) { return (n_nodes + kEdgeTile - 1) / kEdgeTile; }
+
+hipError_t launch_edge_count(const Env* env, int tiles, uint32_t* tcount, hipStream_t s) {
+  if (tiles < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_count, dim3(tiles), dim3(kEdgeBlock), 0, s, env, tcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_write(const Env* env, int tiles, const uint32_t* tcount, float* x, float* t,
+                             int32_t cap_rows, int32_t row0, hipStream_t s) {
+  if (tiles < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_write, dim3(tiles), dim3(kEdgeBlock), 0, s, env, tcount, x, t,
+                     cap_rows, row0);
   return hipGetLastError();
 }
 

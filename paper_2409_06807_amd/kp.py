@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkinopax.so")
 
-KP_ABI_VERSION = 2
+KP_ABI_VERSION = 3
 OK, SOLVED, TIMEOUT, TREE_FULL, FRONTIER_EMPTY = 0, 1, 2, 3, 4
 E_ARG, E_DEVICE, E_WORKSPACE, E_START_INVALID, E_GOAL_INVALID, E_ORDER = -1, -2, -3, -4, -5, -6
 KERNELS = {"propagate": 0, "region": 1, "nodesets": 2, "frontier": 3, "commit": 4, "post": 5,
@@ -34,7 +34,8 @@ EXPORTED = [
     "kp_mlp_adam", "kp_mlp_train", "kp_set_proposal", "kp_log_path",
     "kp_batch_workspace_bytes", "kp_batch_create", "kp_batch_set_config", "kp_batch_get_config",
     "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error", "kp_batch_reset",
-    "kp_transfer_tree",
+    "kp_transfer_tree", "kp_set_trace", "kp_set_launch_limits", "kp_get_trajectory",
+    "kp_log_tree_edges",
 ]
 
 
@@ -73,6 +74,7 @@ class IterStats(C.Structure):
         ("n_new", C.c_int32), ("device_error", C.c_int32),
         ("lanes_total", C.c_uint64), ("valid_total", C.c_uint64), ("invalid_total", C.c_uint64),
         ("steps_total", C.c_uint64), ("box_tests_total", C.c_uint64),
+        ("checked_steps_total", C.c_uint64),
         ("grid_propagate", C.c_int32), ("grid_nodes", C.c_int32),
     ]
 
@@ -90,11 +92,12 @@ class TreeHost(C.Structure):
 
 
 TRACE_DTYPE = np.dtype({
-    "names": ["parent", "sample", "u", "x", "steps", "valid", "cell", "goal", "accept", "new_id"],
+    "names": ["parent", "sample", "u", "x", "steps", "fail_step", "valid", "cell", "goal",
+              "accept", "new_id"],
     "formats": [np.int32, np.int32, (np.float32, 4), (np.float32, 12), np.int32, np.int32,
-                np.uint32, np.int32, np.int32, np.int32],
-    "offsets": [0, 4, 8, 24, 72, 76, 80, 84, 88, 92],
-    "itemsize": 96,
+                np.int32, np.uint32, np.int32, np.int32, np.int32],
+    "offsets": [0, 4, 8, 24, 72, 76, 80, 84, 88, 92, 96],
+    "itemsize": 100,
 })
 
 _lib = None
@@ -140,6 +143,14 @@ def load_library():
     L.kp_set_profiling.restype = C.c_int
     L.kp_kernel_times.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.kp_kernel_times.restype = C.c_int
+    L.kp_log_tree_edges.argtypes = [P, P, P, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.kp_log_tree_edges.restype = C.c_int
+    L.kp_get_trajectory.argtypes = [P, C.c_int32, P, P, P, C.c_int32, C.POINTER(C.c_int32)]
+    L.kp_get_trajectory.restype = C.c_int
+    L.kp_set_trace.argtypes = [P, P]
+    L.kp_set_trace.restype = C.c_int
+    L.kp_set_launch_limits.argtypes = [P, C.c_int32, C.c_int32]
+    L.kp_set_launch_limits.restype = C.c_int
     L.kp_status_str.argtypes = [C.c_int]
     L.kp_status_str.restype = C.c_char_p
     L.kp_last_error.argtypes = [P]
@@ -315,7 +326,7 @@ class Planner:
         return {k: getattr(s, k) for k, _ in IterStats._fields_}
 
     def trace(self, buf, lanes: int):
-        a = buf[: lanes * 96].cpu().numpy()
+        a = buf[: lanes * TRACE_DTYPE.itemsize].cpu().numpy()
         return a.view(TRACE_DTYPE)
 
     # --- state ---
@@ -375,6 +386,8 @@ class Planner:
         """Draw controls from the packed network (kp_mlp_pack output) with
         probability mix; packed=None returns to the uniform draw."""
         import torch
+        if not (0.0 <= float(mix) < 1.0):
+            raise KPError(E_ARG, "mix must be in [0, 1): the uniform share keeps every control reachable")
         if packed is None or mix == 0.0:
             self._check(self.lib.kp_set_proposal(self.h, None, None, 0, C.c_float(0.0)))
             self._proposal = None
@@ -400,6 +413,17 @@ class Planner:
                                          C.byref(n)))
         return n.value
 
+    def log_tree_edges(self, X, T, row0: int) -> int:
+        """Training rows from every tree edge that moves towards the goal
+        (kp_log_tree_edges); returns the rows written."""
+        _need(X, MLP_INPUTS, "X")
+        _need(T, 4, "T", rows=int(X.shape[0]))
+        n = C.c_int32(0)
+        self._check(self.lib.kp_log_tree_edges(self.h, C.c_void_p(X.data_ptr()),
+                                               C.c_void_p(T.data_ptr()), int(X.shape[0]),
+                                               int(row0), C.byref(n)))
+        return n.value
+
     def transfer_from(self, other: "Planner"):
         """Take over `other`'s tree (same problem and seed, capacity >= its |T|)."""
         self._check(self.lib.kp_transfer_tree(other.h, self.h))
@@ -409,6 +433,31 @@ class Planner:
         ids = np.zeros(1 << 16, np.int32)
         self._check(self.lib.kp_get_path(self.h, int(node), _ptr(ids), len(ids), C.byref(n)))
         return ids[: n.value].copy()
+
+    def set_trace(self, buf):
+        """kp_plan writes per-lane records of its expansions into buf (a
+        trace_buffer()); None turns it off.  The buffer must stay alive."""
+        self._plan_trace = buf
+        ptr = C.c_void_p(buf.data_ptr()) if buf is not None else None
+        self._check(self.lib.kp_set_trace(self.h, ptr))
+
+    def set_launch_limits(self, prop_blocks: int = 0, node_blocks: int = 0):
+        """Cap the workgroups per launch (0: occupancy maximum); results do
+        not depend on it."""
+        self._check(self.lib.kp_set_launch_limits(self.h, int(prop_blocks), int(node_blocks)))
+
+    def trajectory(self, node: int) -> dict:
+        """Root-to-node trajectory: states x [len][n], edge controls u [len][m]
+        (zero for the root), integration steps per edge (0 for the root)."""
+        n = C.c_int32(0)
+        self._check(self.lib.kp_get_trajectory(self.h, int(node), None, None, None, 0, C.byref(n)))
+        L = int(n.value)
+        x = np.zeros((L, self.n), np.float32)
+        u = np.zeros((L, self.m), np.float32)
+        k = np.zeros(L, np.int32)
+        self._check(self.lib.kp_get_trajectory(self.h, int(node), _ptr(x), _ptr(u), _ptr(k), L,
+                                               C.byref(n)))
+        return dict(x=x, u=u, steps=k)
 
     # --- timing ---
     def set_profiling(self, on: bool):

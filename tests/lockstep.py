@@ -5,12 +5,16 @@ For each iteration:
      record (Alg. 2, per lane) on its own state;
   2. the GPU runs kp_expand on the same state (loaded from the oracle, or its
      own state from the previous GPU iteration) with a trace buffer;
-  3. per lane: parent/sample order and controls must be identical; the
-     validity outcome (first failing step), the sub-region and the goal test
-     must be identical unless the oracle marked that decision ambiguous (its
-     FP64 value within the ambiguity band of a decision surface), in which
-     case the GPU's outcome must be one of the admissible ones; states must
-     agree within 1e-5 * max(1, |ref|);
+  3. per lane: parent/sample order, controls and segment steps must be
+     identical; the validity outcome (first failing step), the sub-region of
+     x' (the end of the whole segment, valid or not) and the goal test must
+     be identical unless the oracle marked that decision ambiguous (its FP64
+     value within the ambiguity band of a decision surface), in which case the
+     GPU's outcome must be one of the admissible ones; end states must agree
+     within 1e-5 * max(1, |ref|).  A quadcopter lane whose FP64 trajectory
+     nears the Euler-angle singularity has no stable reference end state; its
+     GPU end state must satisfy a reach bound that any computation of the
+     segment satisfies, and its cell is adopted;
   4. the oracle's bookkeeping (counts, acceptance, V_U order, estimates, node
      sets, next frontier) is applied to the records -- with the GPU's outcome
      substituted only where the oracle itself found the decision ambiguous --
@@ -21,6 +25,7 @@ For each iteration:
 from __future__ import annotations
 
 import itertools
+import os
 
 import numpy as np
 
@@ -34,9 +39,11 @@ class Report:
         self.iterations = 0
         self.lanes = 0
         self.ambiguous_lanes = 0
+        self.ill_lanes = 0
         self.adopted = 0
         self.max_rel_err = 0.0
         self.learned_lanes = 0
+        self.max_lanes = 0
         self.failures = []
         self.final_status = None
 
@@ -50,7 +57,8 @@ class Report:
 
     def summary(self):
         s = (f"iterations={self.iterations} lanes={self.lanes} ambiguous={self.ambiguous_lanes} "
-             f"adopted={self.adopted} max_rel_err={self.max_rel_err:.2e} "
+             f"ill_conditioned={self.ill_lanes} adopted={self.adopted} "
+             f"max_rel_err={self.max_rel_err:.2e} max_lanes={self.max_lanes} "
              f"status={self.final_status} failures={len(self.failures)}")
         if self.failures:
             s += " first: " + "; ".join(self.failures[:5])
@@ -79,13 +87,44 @@ def admissible_cells(p, x, tol=oracle.kpo.AMB_TOL):
     return cells
 
 
+def reach_ok(p, traj, c, k_seg, u, pos):
+    """An ill-conditioned quadcopter segment: its FP64 states from step c on
+    are no reference for a lower-precision computation (the pitch nears the
+    Euler-angle singularity).  What still holds for any computation of it:
+    the thrust direction is a unit vector, so from the last well-conditioned
+    state (p_c, v_c) at step c - 1, after k = k_seg - c + 1 steps of h,
+      |p - (p_c + v_c k h - g e3 w)| <= (T / m) w,
+    with w = (k h)^2 / 2 for RK4 (its position update sums the stage
+    accelerations with the same weights as the exact integral) and
+    w = h^2 k (k - 1) / 2 for explicit Euler.  The slack covers the FP32
+    error of (p_c, v_c)."""
+    h = float(np.float32(p["h"]))
+    prm = np.asarray(p["dyn_params"], np.float32).astype(np.float64)
+    x = traj[c - 1]
+    k = k_seg - c + 1
+    tau = k * h
+    # the weight of the stage accelerations in the position after k steps:
+    # RK4 (kh)^2 / 2, like the exact integral; explicit Euler h^2 k (k - 1) / 2
+    w2 = 0.5 * tau * tau if int(p["integrator"]) == 1 else 0.5 * h * h * k * (k - 1)
+    center = x[:3] + x[6:9] * tau - np.array([0.0, 0.0, prm[1] * w2])
+    radius = float(u[0]) / prm[0] * w2
+    slack = 1e-3 * (1.0 + np.max(np.abs(x[:3]))) + 1e-3 * np.max(np.abs(x[6:9]))
+    return float(np.linalg.norm(np.asarray(pos, np.float64) - center)) <= radius + slack
+
+
 def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
     """Per-lane comparison; returns the records with admissible GPU outcomes
     substituted where the oracle marked the decision ambiguous.  gpu_prev: the
     GPU's own tree before this expansion, when it continues from its own FP32
     states; child states are then checked edge by edge against the FP64
-    re-integration of the GPU's stored parent."""
-    K = int(p["steps"])
+    re-integration of the GPU's stored parent.
+
+    x' is the end of the whole segment on both sides (Alg. 2), whatever the
+    validity outcome, so end states and cells are compared for every lane.
+    The exception is a quadcopter lane whose FP64 trajectory comes near the
+    Euler-angle singularity (the oracle's cond_step): there the GPU's end
+    state must satisfy the reach bound of reach_ok and its own cell map, and
+    its cell is adopted."""
     m = W.m
     n = W.n
     lanes = len(recs)
@@ -98,63 +137,98 @@ def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
     if not np.array_equal(gu, ou):
         k = int(np.nonzero(np.any(gu != ou, axis=1))[0][0])
         rep.fail(f"it{it}: control bits differ at lane {k}")
-    o_fail = np.where(recs["valid"] == 1, K + 1, recs["steps"])
-    g_fail = np.where(tr["valid"] == 1, K + 1, tr["steps"])
+    if not np.array_equal(tr["steps"], recs["steps"]):
+        k = int(np.nonzero(tr["steps"] != recs["steps"])[0][0])
+        rep.fail(f"it{it}: lane {k} integrates {tr['steps'][k]} steps, oracle {recs['steps'][k]}")
+        return recs
+    o_fail = recs["fail"]
+    g_fail = tr["fail_step"]
+    if not np.array_equal(tr["valid"] == 1, g_fail == tr["steps"] + 1):
+        rep.fail(f"it{it}: GPU valid flag and first failing step disagree")
     amb_valid = recs["fail_strict"] != recs["fail_loose"]
+    ill = recs["cond_step"] <= recs["k_seg"]
     rep.ambiguous_lanes += int(np.sum(amb_valid | (recs["amb_cell"] != 0) | (recs["amb_goal"] != 0)))
+    rep.ill_lanes += int(np.sum(ill))
     merged = recs.copy()
+    goal_c = np.asarray(p["goal_center"], np.float32).astype(np.float64)
+    goal_r = float(np.float32(p["goal_radius"]))
     for k in np.nonzero(o_fail != g_fail)[0]:
         if not (recs["fail_strict"][k] <= g_fail[k] <= recs["fail_loose"][k]):
             rep.fail(f"it{it}: lane {k} validity differs (oracle fail step {o_fail[k]}, "
                      f"gpu {g_fail[k]}, band [{recs['fail_strict'][k]}, {recs['fail_loose'][k]}])")
             continue
-        # admissible: adopt the GPU's first failing step, oracle state at that step
-        rec, traj = W.expand_one(recs["parent"][k], recs["sample"][k], want_traj=True,
-                                 control=recs["u"][k])
-        steps = min(int(g_fail[k]), int(recs["k_seg"][k]))
-        merged["valid"][k] = 1 if g_fail[k] == K + 1 else 0
-        merged["steps"][k] = steps
-        merged["x"][k][:n] = traj[steps]
-        merged["cell"][k] = tr["cell"][k]
-        if tr["cell"][k] not in admissible_cells(p, traj[steps]) and np.all(np.isfinite(traj[steps][:3])):
-            rep.fail(f"it{it}: lane {k} adopted cell not admissible")
-        gd = np.linalg.norm(traj[steps][:3] - np.asarray(p["goal_center"], np.float64))
-        merged["goal"][k] = 1 if (merged["valid"][k] and gd <= float(np.float32(p["goal_radius"]))) else 0
+        # admissible: adopt the GPU's validity outcome; x' does not depend on it
+        merged["valid"][k] = tr["valid"][k]
+        merged["fail"][k] = g_fail[k]
+        gd = np.linalg.norm(recs["x"][k][:3] - goal_c)
+        merged["goal"][k] = 1 if (merged["valid"][k] and gd <= goal_r) else 0
         rep.adopted += 1
-    same = o_fail == g_fail
-    idx = np.nonzero(same)[0]
+    # end states
+    well = np.nonzero(~ill)[0]
     if gpu_prev is not None:
         ref = oracle.integrate_batch(p, gpu_prev["x"][tr["parent"]].astype(np.float64),
                                      tr["u"][:, :m], tr["steps"])
-        e = rel_err(tr["x"][:, :n], ref)
-        rep.max_rel_err = max(rep.max_rel_err, e)
-        if e > REL_TOL:
-            rep.fail(f"it{it}: edge re-integration rel err {e:.2e}")
-    elif len(idx):
-        # states where the stop step agrees
-        e = rel_err(tr["x"][idx, :n], recs["x"][idx, :n])
-        rep.max_rel_err = max(rep.max_rel_err, e)
-        if e > REL_TOL:
-            bad = np.max(np.abs(tr["x"][idx, :n] - recs["x"][idx, :n]) /
-                         np.maximum(1, np.abs(recs["x"][idx, :n])), axis=1)
-            k = int(idx[np.argmax(bad)])
-            rep.fail(f"it{it}: lane {k} state rel err {e:.2e}")
-    # cells where the stop step agrees
-    for k in idx[tr["cell"][idx] != recs["cell"][idx]]:
+        e = rel_err(tr["x"][well, :n], ref[well])
+    else:
+        e = rel_err(tr["x"][well, :n], recs["x"][well, :n])
+        ref = recs["x"][:, :n]
+    rep.max_rel_err = max(rep.max_rel_err, e)
+    if e > REL_TOL:
+        errs = np.abs(tr["x"][well, :n] - ref[well]) / np.maximum(1, np.abs(ref[well]))
+        bad = np.max(errs, axis=1)
+        k = int(well[np.argmax(bad)])
+        j = int(np.argmax(errs[np.argmax(bad)]))
+        rep.fail(f"it{it}: lane {k} end state rel err {e:.2e} in component {j} "
+                 f"(gpu {tr['x'][k][j]!r}, ref {ref[k][j]!r}; valid {recs['valid'][k]}, "
+                 f"fail step {recs['fail'][k]}, {int(np.sum(bad > REL_TOL))} lanes above)")
+        dump = os.environ.get("LOCKSTEP_DUMP")
+        if dump:
+            os.makedirs(dump, exist_ok=True)
+            sel = well[bad > REL_TOL]
+            par = tr["parent"][sel]
+            x0 = (gpu_prev["x"][par] if gpu_prev is not None
+                  else np.asarray(W.state(copy=False)["x"])[par])
+            np.savez(os.path.join(dump, f"{p.get('name', 'case')}_it{it}_{os.getpid()}.npz"),
+                     lanes=sel, x0=np.asarray(x0), u=tr["u"][sel], gpu=tr["x"][sel],
+                     ref=ref[sel], valid=recs["valid"][sel], fail=recs["fail"][sel],
+                     steps=tr["steps"][sel])
+    # cells of well-conditioned lanes: identical unless within the band of a plane
+    for k in well[tr["cell"][well] != recs["cell"][well]]:
         if recs["amb_cell"][k] and tr["cell"][k] in admissible_cells(p, recs["x"][k]):
             merged["cell"][k] = tr["cell"][k]
             rep.adopted += 1
         else:
             rep.fail(f"it{it}: lane {k} cell differs ({tr['cell'][k]} vs {recs['cell'][k]})")
+    # ill-conditioned lanes: reach bound and the GPU's own cell map
+    if np.any(ill):
+        parent_cell = W.state(copy=False)["cell"]
+        for k in np.nonzero(ill)[0]:
+            if recs["valid"][k] or tr["valid"][k]:
+                rep.fail(f"it{it}: lane {k} ill-conditioned but valid")
+                continue
+            pos = np.asarray(tr["x"][k][:3], np.float64)
+            if np.all(np.isfinite(pos)):
+                _, traj = W.expand_one(recs["parent"][k], recs["sample"][k], want_traj=True,
+                                       control=recs["u"][k])
+                if not reach_ok(p, traj, int(recs["cond_step"][k]), int(recs["k_seg"][k]),
+                                recs["u"][k], pos):
+                    rep.fail(f"it{it}: ill-conditioned lane {k} ends outside its reach bound")
+                if tr["cell"][k] not in admissible_cells(p, pos):
+                    rep.fail(f"it{it}: ill-conditioned lane {k} cell is not its end point's")
+            elif tr["cell"][k] != parent_cell[recs["parent"][k]]:
+                rep.fail(f"it{it}: lane {k} non-finite end without its parent's cell")
+            merged["cell"][k] = tr["cell"][k]
     # goal test on accepted lanes (GPU reports goal only for accepted samples)
+    same = merged["valid"] == tr["valid"]
     acc = np.nonzero(same & (tr["accept"] == 1))[0]
-    for k in acc[(tr["goal"][acc] != 0) != (recs["goal"][acc] != 0)]:
+    for k in acc[(tr["goal"][acc] != 0) != (merged["goal"][acc] != 0)]:
         if recs["amb_goal"][k]:
             merged["goal"][k] = tr["goal"][k]
             rep.adopted += 1
         else:
             rep.fail(f"it{it}: lane {k} goal test differs")
     rep.lanes += lanes
+    rep.max_lanes = max(rep.max_lanes, lanes)
     return merged
 
 
@@ -287,10 +361,13 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
         # the kernel's own wave-summed counters agree with its per-lane trace
         gs1 = G.stats()
         got = (gs1["lanes_total"] - gs["lanes_total"], gs1["valid_total"] - gs["valid_total"],
-               gs1["steps_total"] - gs["steps_total"])
-        want = (len(tr), int(np.count_nonzero(tr["valid"])), int(tr["steps"].astype(np.int64).sum()))
+               gs1["steps_total"] - gs["steps_total"],
+               gs1["checked_steps_total"] - gs["checked_steps_total"])
+        checked = np.where(tr["valid"] == 1, tr["steps"], tr["fail_step"]).astype(np.int64)
+        want = (len(tr), int(np.count_nonzero(tr["valid"])), int(tr["steps"].astype(np.int64).sum()),
+                int(checked.sum()))
         if got != want:
-            rep.fail(f"it{it}: lanes / valid / steps counters {got}, trace {want}")
+            rep.fail(f"it{it}: lanes / valid / steps / checked counters {got}, trace {want}")
         merged = compare_expansion(p, W, recs, tr, rep, it, gpu_prev)
         W.apply(merged)
         g = G.copy_tree()
@@ -315,3 +392,170 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
         if not rep.ok:
             break
     return rep
+
+
+def run_lockstep_plan(p, iterations, device="cuda:0", reload=False, launch_limits=None,
+                      report=None):
+    """Lock-step of the planning loop itself: kp_plan with max_iters = 1 and
+    iters_per_sync = 1, so that each call runs exactly one iteration of the
+    timed path -- the propagate launch and the fused launch that commits V_U,
+    runs UpdateEstimates and UpdateNodeSets and builds the next frontier --
+    with per-lane records from kp_set_trace.  reload=False grows the GPU tree
+    on its own from the root (the next frontier comes from the fused launch);
+    reload=True loads the oracle's state before every call.  launch_limits:
+    (prop_blocks, node_blocks) caps, e.g. to make one block serve many tiles."""
+    from paper_2409_06807_amd import Planner
+    import torch
+
+    rep = report if report is not None else Report()
+    pp = dict(p, max_iters=1, iters_per_sync=1)
+    W = oracle.OraclePlanner(pp)
+    G = Planner(pp, device=device)
+    trace = G.trace_buffer()
+    G.set_trace(trace)
+    if launch_limits is not None:
+        G.set_launch_limits(*launch_limits)
+    for it in range(iterations):
+        if W.state(copy=False)["goal_id"] >= 0:
+            rep.final_status = oracle.SOLVED
+            break
+        if reload:
+            G.load_tree(gpu_state_from_oracle(W.state()))
+            gpu_prev = None
+        else:
+            gpu_prev = G.copy_tree()
+        st = W.frontier()
+        gs = G.stats()
+        ov = W.state(copy=False)
+        if gs["n_frontier"] != ov["nF"] or gs["lam"] != ov["lam"]:
+            rep.fail(f"it{it}: frontier size / lambda gpu ({gs['n_frontier']}, {gs['lam']}) "
+                     f"oracle ({ov['nF']}, {ov['lam']})")
+            break
+        if st != oracle.OK:
+            res = G.plan()
+            if res["status"] != st or gs["done_code"] != st:
+                rep.fail(f"it{it}: termination gpu {res['status']} / {gs['done_code']} oracle {st}")
+            rep.final_status = st
+            break
+        recs = W.expand_all()
+        res = G.plan()
+        torch.cuda.synchronize()
+        if res["iterations"] != 1:
+            rep.fail(f"it{it}: kp_plan ran {res['iterations']} iterations")
+            break
+        tr = G.trace(trace, len(recs))
+        gs1 = G.stats()
+        checked = np.where(tr["valid"] == 1, tr["steps"], tr["fail_step"]).astype(np.int64)
+        got = (gs1["lanes_total"] - gs["lanes_total"], gs1["valid_total"] - gs["valid_total"],
+               gs1["steps_total"] - gs["steps_total"],
+               gs1["checked_steps_total"] - gs["checked_steps_total"])
+        want = (len(tr), int(np.count_nonzero(tr["valid"])), int(tr["steps"].astype(np.int64).sum()),
+                int(checked.sum()))
+        if got != want:
+            rep.fail(f"it{it}: lanes / valid / steps / checked counters {got}, trace {want}")
+        merged = compare_expansion(p, W, recs, tr, rep, it, gpu_prev)
+        W.apply(merged)
+        W.update_estimates()
+        og = W.update_node_sets()
+        g = G.copy_tree()
+        compare_state(p, W, g, rep, it, "after kp_plan", gpu_prev)
+        # kp_plan stops on its one-iteration budget, or earlier on a goal, or
+        # when the next frontier it has just built gives eq. (6) lambda = 0 or
+        # is empty
+        if og >= 0:
+            want_status = oracle.SOLVED
+        else:
+            nxt = W.frontier()
+            want_status = nxt if nxt != oracle.OK else oracle.TIMEOUT
+        if res["status"] != want_status or res["goal_id"] != og:
+            rep.fail(f"it{it}: kp_plan status {res['status']} goal {res['goal_id']}, "
+                     f"oracle {want_status} goal {og}")
+        if gs1["device_error"]:
+            rep.fail(f"it{it}: device error bits {gs1['device_error']}")
+        rep.iterations += 1
+        if not rep.ok:
+            break
+    return rep
+
+
+def run_lockstep_batch(problems, iterations, config=None, device="cuda:0"):
+    """Lock-step of batched planning: every problem of one batch against its
+    own oracle.  Each kp_batch_plan call runs exactly one iteration of every
+    problem (each problem's iteration budget is 1), in the batched launches
+    (one grid row per problem); every problem writes its own per-lane trace.
+    Problems that stop (goal, full tree) drop out.  Returns one Report per
+    problem."""
+    from paper_2409_06807_amd import Planner, Batch
+    import torch
+
+    pps = [dict(p, max_iters=1, iters_per_sync=1) for p in problems]
+    Ws = [oracle.OraclePlanner(pp) for pp in pps]
+    Gs = [Planner(pp, device=device) for pp in pps]
+    traces = [G.trace_buffer() for G in Gs]
+    for G, t in zip(Gs, traces):
+        G.set_trace(t)
+    B = Batch(Gs)
+    if config:
+        B.set_config(**config)
+    reps = [Report() for _ in problems]
+    live = list(range(len(problems)))
+    for it in range(iterations):
+        recs, prev = {}, {}
+        for i in list(live):
+            W, G, rep = Ws[i], Gs[i], reps[i]
+            if W.state(copy=False)["goal_id"] >= 0:
+                rep.final_status = oracle.SOLVED
+                live.remove(i)
+                continue
+            st = W.frontier()
+            gs = G.stats()
+            ov = W.state(copy=False)
+            if gs["n_frontier"] != ov["nF"] or gs["lam"] != ov["lam"]:
+                rep.fail(f"it{it}: frontier size / lambda gpu ({gs['n_frontier']}, {gs['lam']}) "
+                         f"oracle ({ov['nF']}, {ov['lam']})")
+                live.remove(i)
+                continue
+            if st != oracle.OK:
+                if gs["done_code"] != st:
+                    rep.fail(f"it{it}: termination code gpu {gs['done_code']} oracle {st}")
+                rep.final_status = st
+                live.remove(i)
+                continue
+            recs[i] = W.expand_all()
+            prev[i] = G.copy_tree()
+        if not live:
+            break
+        res, _ = B.plan()
+        torch.cuda.synchronize()
+        for i in list(live):
+            W, G, rep, p = Ws[i], Gs[i], reps[i], problems[i]
+            if res[i]["iterations"] != 1:
+                rep.fail(f"it{it}: batch ran {res[i]['iterations']} iterations")
+                live.remove(i)
+                continue
+            tr = G.trace(traces[i], len(recs[i]))
+            merged = compare_expansion(p, W, recs[i], tr, rep, it, prev[i])
+            W.apply(merged)
+            W.update_estimates()
+            og = W.update_node_sets()
+            compare_state(p, W, G.copy_tree(), rep, it, "after kp_batch_plan", prev[i])
+            if og >= 0:
+                want = oracle.SOLVED
+            else:
+                nxt = W.frontier()
+                want = nxt if nxt != oracle.OK else oracle.TIMEOUT
+            if res[i]["status"] != want or res[i]["goal_id"] != og:
+                rep.fail(f"it{it}: batch status {res[i]['status']} goal {res[i]['goal_id']}, "
+                         f"oracle {want} goal {og}")
+            rep.iterations += 1
+            if not rep.ok:
+                live.remove(i)
+            elif want != oracle.TIMEOUT:
+                rep.final_status = want
+                live.remove(i)
+        if not live:
+            break
+    B.close()
+    for G in Gs:
+        G.close()
+    return reps

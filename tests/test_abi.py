@@ -113,7 +113,7 @@ def test_invalid_start_and_goal_detected_on_host(lib):
 def test_struct_layouts_match_header(lib):
     import paper_2409_06807_amd as kp
     assert C.sizeof(kp.kp.TreeHost) == 8 + 12 * 8
-    assert kp.TRACE_DTYPE.itemsize == 96
+    assert kp.TRACE_DTYPE.itemsize == 100
     src = open(os.path.join(ROOT, "include", "kp.h")).read()
     assert f"KP_ABI_VERSION {kp.kp.KP_ABI_VERSION}u" in src
     # the description's last fields: duration mode and a zero reserved word

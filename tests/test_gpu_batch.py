@@ -185,3 +185,35 @@ def test_batch_with_learned_proposals_equals_single(graph):
     res, _ = B.plan()
     check_same(ref, planners, res)
     B.close()
+
+
+def _batch_lockstep_problems(dyn):
+    from workloads import DI6, QUAD12
+    # obstacle counts up to 2000 (the batched workload's range): tables larger
+    # than 64 KiB of LDS per propagate block
+    ps = problem_batch(n=5, batch_seed=9, dynamics=DI6 if dyn == "di" else QUAD12,
+                       cap_range=(16384, 40000), obs_range=(1200, 2000))
+    ps += problem_batch(n=3, batch_seed=10, dynamics=DI6 if dyn == "di" else QUAD12,
+                        cap_range=(16384, 40000), obs_range=(10, 100))
+    return ps
+
+
+@pytest.mark.parametrize("dyn,config", [
+    ("di", None),
+    ("di", dict(use_graph=1, prop_blocks=3, node_blocks=1)),
+    ("quad", dict(prop_blocks=8, node_blocks=2)),
+])
+def test_batch_lockstep_against_oracle(dyn, config):
+    """Batched planning against the oracle, iteration by iteration: every
+    problem of the batch (one grid row each) must match its own FP64 oracle
+    lane by lane and in every integer field of its tree."""
+    import lockstep
+    ps = _batch_lockstep_problems(dyn)
+    _say(f"batch lock-step {dyn} config={config} obstacles={[len(p['obstacles']) for p in ps]}")
+    assert max(len(p["obstacles"]) for p in ps) > 1536
+    reps = lockstep.run_lockstep_batch(ps, iterations=12 if dyn == "di" else 8, config=config)
+    for k, rep in enumerate(reps):
+        print(f"problem {k}: {rep.summary()}", flush=True)
+    assert all(rep.ok for rep in reps), [rep.summary() for rep in reps if not rep.ok][:3]
+    assert all(rep.iterations >= 3 or rep.final_status in (oracle.TREE_FULL, oracle.SOLVED)
+               for rep in reps)

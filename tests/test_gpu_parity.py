@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import problem_small_di, problem_small_quad, problem_c5, EULER, RK4
+from workloads import (problem_small_di, problem_small_quad, problem_c1, problem_c2, problem_c5,
+                       EULER, RK4)
 
 import lockstep
 
@@ -84,3 +85,38 @@ def test_lockstep_until_goal():
     rep = lockstep.run_lockstep(p, iterations=60, reload=False)
     assert rep.ok, rep.summary()
     assert rep.final_status == oracle.SOLVED
+
+
+# The planning loop itself (kp_plan, one iteration per call): the propagate
+# launch and the fused commit / estimates / node-set launch that the bench
+# times, at the workloads' own configurations.
+PLAN_CASES = {
+    # c1 as specified (32768-node cap, lambda_max 4) until its tree is full
+    "c1": (lambda: problem_c1(seed=0), 40, None),
+    # c2 as specified (4M cap, lambda_max 4): from iteration ~20 on a launch
+    # has more than 16,384 lanes (several 256-tile chunks of the V_U commit)
+    "c2": (lambda: problem_c2(seed=0), 24, None),
+    # the c5 building at a reduced cap
+    "c5": (lambda: problem_c5(seed=2, node_cap=40000), 30, None),
+    # one node-pass block serving every 4096-node tile by ticket, two
+    # propagate blocks serving every wave tile
+    "di-few-blocks": (lambda: problem_small_di(seed=3, cap=20000, n_obs=20), 40, (2, 1)),
+    "quad-few-blocks": (lambda: problem_small_quad(seed=2, cap=24000, n_obs=60, lambda_max=8),
+                        14, (3, 2)),
+}
+
+
+@pytest.mark.parametrize("name", list(PLAN_CASES))
+@pytest.mark.parametrize("reload", [False, True])
+def test_lockstep_plan(name, reload):
+    make, iters, limits = PLAN_CASES[name]
+    p = make()
+    _announce(f"plan-lockstep {name} reload={reload} limits={limits}", p)
+    rep = lockstep.run_lockstep_plan(p, iterations=iters, reload=reload, launch_limits=limits)
+    print(rep.summary(), flush=True)
+    assert rep.ok, rep.summary()
+    assert rep.iterations >= 5 or rep.final_status in (oracle.TREE_FULL, oracle.SOLVED)
+    if name == "c2":
+        assert rep.max_lanes > 16384, rep.summary()
+    if name in ("c1", "di-few-blocks"):
+        assert rep.final_status == oracle.TREE_FULL, rep.summary()

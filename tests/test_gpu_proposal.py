@@ -6,6 +6,8 @@ replay in FP64."""
 
 import sys
 
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -153,17 +155,28 @@ def test_learned_lockstep(name, reload):
     assert rep.iterations >= 3 and rep.learned_lanes > 100
 
 
-def test_mix_zero_is_uniform_and_mix_one_is_all_learned():
-    """mix = 0 gives the uniform planner's tree bit for bit; with mix = 1 no
-    stored control is Alg. 2's uniform draw, and every one lies in U."""
-    from paper_2409_06807_amd import Planner
+def test_mix_zero_is_uniform_and_mix_one_is_refused():
+    """mix = 0 gives the uniform planner's tree bit for bit; mix = 1 (no
+    uniform share) is refused; with mix = 0.99 a node's stored control is
+    Alg. 2's uniform draw exactly when its mixture word says uniform, and
+    every control lies in U."""
+    from paper_2409_06807_amd import Planner, KPError, E_ARG
     from test_oracle_planner import expected_controls
-    _say("mix 0 / mix 1")
+    from oracle import proposal as PR
+    _say("mix 0 / mix 1 / mix 0.99")
     p = problem_small_di(seed=6, cap=4096, n_obs=12)
     params = mlp_inputs.params(12, scale=1.0, out_scale=1.0)
     pk = packed(params)
+    G = Planner(p)
+    for bad in (1.0, 1.5, -0.1):
+        with pytest.raises(KPError) as ei:
+            G.set_proposal(pk, bad)
+        assert ei.value.code == E_ARG
+        assert G.lib.kp_set_proposal(G.h, C.c_void_p(pk.data_ptr()), None, 0,
+                                     C.c_float(bad)) == E_ARG
+    G.close()
     trees = {}
-    for mix in (None, 0.0, 1.0):
+    for mix in (None, 0.0, 0.99):
         G = Planner(p)
         if mix is not None:
             G.set_proposal(pk, mix)
@@ -174,13 +187,19 @@ def test_mix_zero_is_uniform_and_mix_one_is_all_learned():
     assert a["N"] == b["N"]
     for k in ("x", "u", "parent", "cell", "flag", "thr"):
         assert np.array_equal(a[k], b[k]), k
-    g = trees[1.0]
+    g = trees[0.99]
     lo = np.asarray(p["u_lo"], np.float32)
     hi = np.asarray(p["u_hi"], np.float32)
     assert np.all(g["u"][1:] >= lo) and np.all(g["u"][1:] <= hi)
-    for i in range(1, min(g["N"], 300)):
-        uni = expected_controls(p, int(g["birth"][i]), int(g["parent"][i]), int(g["sample"][i]), 3)
-        assert not np.array_equal(g["u"][i], uni), i
+    thr = PR.mix_threshold(0.99)
+    n_uniform = 0
+    for i in range(1, min(g["N"], 2000)):
+        it, f, s = int(g["birth"][i]), int(g["parent"][i]), int(g["sample"][i])
+        uni = expected_controls(p, it, f, s, 3)
+        learned = PR.is_learned(int(p["seed"]), it, f, s, thr)
+        assert np.array_equal(g["u"][i], uni) == (not learned), i
+        n_uniform += int(not learned)
+    assert 0 < n_uniform < 100
 
 
 def test_log_path_rows_match_reference():
@@ -250,4 +269,57 @@ def test_trained_proposal_plans_replay_in_fp64():
         g = G.copy_tree()
         valid, reached, worst = replay_path_edgewise(p, g, path)
         assert valid and reached and worst <= 1e-5, (seed, valid, reached, worst)
+    G.close()
+
+
+@pytest.mark.parametrize("make", [lambda: problem_small_di(seed=6, cap=12000, n_obs=12),
+                                  lambda: problem_small_quad(seed=3, cap=16000, n_obs=40, lambda_max=8)])
+def test_tree_edge_rows(make):
+    """kp_log_tree_edges: one row per tree edge whose child is strictly closer
+    to the goal centre than its parent, in node id order; features of the
+    parent as the FP64 reference defines them, the edge's control in
+    normalised units.  The distance test is an FP32 decision: the reference
+    takes it in FP32 too, summing the squared offsets with one rounding per
+    term (a fused multiply-add; the exact product fits FP64)."""
+    import torch
+    from paper_2409_06807_amd import Planner
+    p = make()
+    _say(f"tree edge rows {p['name']} cap={p['node_cap']}")
+    G = Planner(p)
+    G.plan()
+    g = G.copy_tree()
+    N = int(g["N"])
+    x32 = g["x"][:N]
+    x = x32.astype(np.float64)
+    c32 = np.asarray(p["goal_center"], np.float32)
+    par = g["parent"][:N]
+
+    def dist2(rows):
+        d = np.zeros(len(rows), np.float32)
+        for k in range(3):
+            e = (x32[rows, k] - c32[k]).astype(np.float32)
+            d = (e.astype(np.float64) * e.astype(np.float64) + d.astype(np.float64)).astype(np.float32)
+        return d
+
+    ids = np.arange(1, N)
+    dc, da = dist2(ids), dist2(par[ids])
+    child = 1 + np.nonzero(dc < da)[0]
+    assert 100 < len(child) < N - 1
+    X = torch.zeros((N, 16), dtype=torch.float32, device="cuda:0")
+    T = torch.zeros((N, 4), dtype=torch.float32, device="cuda:0")
+    rows = G.log_tree_edges(X, T, 3)
+    assert rows == len(child)
+    m = G.m
+    Xh = X.cpu().numpy()
+    Th = T.cpu().numpy()
+    assert np.all(Xh[:3] == 0) and np.all(Xh[3 + rows:] == 0)
+    ref = P.features(p, x[par[child]], g["thr"][g["cell"][par[child]] >> 6])
+    np.testing.assert_allclose(Xh[3:3 + rows], ref, rtol=0, atol=1e-5)
+    lo = np.asarray(p["u_lo"], np.float32)[:m].astype(np.float64)
+    hi = np.asarray(p["u_hi"], np.float32)[:m].astype(np.float64)
+    want_t = (g["u"][child].astype(np.float64) - 0.5 * (lo + hi)) / (0.5 * (hi - lo))
+    np.testing.assert_allclose(Th[3:3 + rows, :m], want_t, rtol=0, atol=1e-6)
+    # a short buffer takes the first rows only
+    rows2 = G.log_tree_edges(X[:10], T[:10], 4)
+    assert rows2 == 6
     G.close()

@@ -293,3 +293,51 @@ def test_threads_do_not_change_results():
         oracle.set_threads(old)
     assert runs[0][0] == runs[1][0]
     assert runs[0][1] == runs[1][1]
+
+
+def _traj_of(p, s, path):
+    """The trajectory rows a GPU planner returns, from an oracle tree: FP32
+    states, controls of the edge into each node, steps of each edge."""
+    steps = [0] + [oracle.segment_steps(p, int(s["birth"][b]), int(s["parent"][b]),
+                                        int(s["sample"][b])) for b in path[1:]]
+    u = s["u"][path].copy()
+    u[0] = 0.0
+    return dict(x=s["x"][path].astype(np.float32), u=u, steps=np.asarray(steps, np.int32))
+
+
+@pytest.mark.parametrize("dur", [0, 1])
+def test_replay_trajectory_accepts_planned_paths(dur):
+    p = near_goal_problem(1 if dur else 0)
+    p["duration_mode"] = dur
+    P = oracle.OraclePlanner(p)
+    st, g, it = P.plan(max_iters=300)
+    assert st == oracle.SOLVED
+    s = P.state()
+    path = P.path(g)
+    r = oracle.replay_trajectory(p, _traj_of(p, s, path))
+    assert r["valid"] and r["reached"] and r["first_bad"] == -1
+    # FP32 storage of the states is the only difference from the FP64 tree
+    assert r["worst"] < 1e-6
+
+
+def test_replay_trajectory_quad_path_and_rejections():
+    p = problem_small_quad(seed=4, cap=4000)
+    P = oracle.OraclePlanner(p)
+    run_iters(P, 5)
+    s = P.state()
+    node = int(s["N"]) - 1
+    path = P.path(node)
+    assert len(path) >= 4
+    tr = _traj_of(p, s, path)
+    r = oracle.replay_trajectory(p, tr)
+    assert r["valid"] and not r["reached"] and r["worst"] < 1e-6
+    # a changed control: the edge no longer ends at its stored child
+    bad = dict(tr, u=tr["u"].copy())
+    bad["u"][2, 0] = np.float32(bad["u"][2, 0] * 0.5 + 1.0)
+    assert not oracle.replay_trajectory(p, bad)["valid"]
+    # an obstacle around the end of the last edge: that edge is invalid
+    e = len(path) - 2
+    c = tr["x"][-1][:3].astype(np.float64)
+    q = dict(p, obstacles=np.vstack([p["obstacles"], np.r_[c - 0.05, c + 0.05][None, :]]).astype(np.float32))
+    r = oracle.replay_trajectory(q, tr)
+    assert not r["valid"] and r["first_bad"] == e

@@ -293,7 +293,7 @@ def problem_small_quad(seed=0, scene_seed=12, n_obs=60, cap=8192, lambda_max=32,
     return p
 
 
-def problem_batch(n=256, batch_seed=3, dynamics=DI6, obs_range=(10, 1536),
+def problem_batch(n=256, batch_seed=3, dynamics=DI6, obs_range=(10, 2000),
                   cap_range=(16384, 1048576), min_sep=50.0, occupancy=0.03, **kw):
     """Independent queries of uneven size for batched planning.  Query k has
     its own generator PCG64([batch_seed, k]): an obstacle count and a node cap
