@@ -112,6 +112,21 @@ def reach_ok(p, traj, c, k_seg, u, pos):
     return float(np.linalg.norm(np.asarray(pos, np.float64) - center)) <= radius + slack
 
 
+def adopt_states(W, g):
+    """Continue mode: the oracle takes the GPU's stored FP32 states (widened to
+    FP64) for every node before it expands, so that each lane compares one
+    segment from the same parent (Alg. 2 propagates from the stored node).
+    Without this the FP64 and FP32 trees drift apart with depth, and a decision
+    near a surface would compare two different parents.  Integer state (ids,
+    parents, cells, flags, counts) is not touched: it is compared bit for bit
+    every iteration."""
+    x = W.state(copy=False)["x"]
+    N = int(g["N"])
+    if x.shape[0] != N:
+        raise AssertionError(f"tree sizes differ before adoption: oracle {x.shape[0]}, gpu {N}")
+    x[:, :] = np.asarray(g["x"][:N, :x.shape[1]], np.float32).astype(np.float64)
+
+
 def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
     """Per-lane comparison; returns the records with admissible GPU outcomes
     substituted where the oracle marked the decision ambiguous.  gpu_prev: the
@@ -198,7 +213,15 @@ def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
             merged["cell"][k] = tr["cell"][k]
             rep.adopted += 1
         else:
-            rep.fail(f"it{it}: lane {k} cell differs ({tr['cell'][k]} vs {recs['cell'][k]})")
+            pos_o = np.asarray(recs["x"][k][:3], np.float64)
+            pos_g = np.asarray(tr["x"][k][:3], np.float64)
+            w = (np.asarray(p["x_hi"], np.float64)[:3] - np.asarray(p["x_lo"], np.float64)[:3]) / \
+                (np.asarray(p["grid"], np.float64) * int(p["sub"]))
+            t = (pos_o - np.asarray(p["x_lo"], np.float64)[:3]) / w
+            plane = float(np.min(np.abs(t - np.round(t)) * w))
+            rep.fail(f"it{it}: lane {k} cell differs ({tr['cell'][k]} vs {recs['cell'][k]}; "
+                     f"end gpu {pos_g.tolist()} oracle {pos_o.tolist()}, nearest plane "
+                     f"{plane:.2e}, valid {recs['valid'][k]}, fail step {recs['fail'][k]})")
     # ill-conditioned lanes: reach bound and the GPU's own cell map
     if np.any(ill):
         parent_cell = W.state(copy=False)["cell"]
@@ -347,6 +370,8 @@ def run_lockstep(p, iterations, device="cuda:0", reload=True, G=None, report=Non
                 rep.fail(f"it{it}: termination code gpu {gs['done_code']} oracle {st}")
             rep.final_status = st
             break
+        if gpu_prev is not None:
+            adopt_states(W, gpu_prev)
         if proposal is None:
             recs = W.expand_all()
             G.expand(trace)
@@ -437,6 +462,8 @@ def run_lockstep_plan(p, iterations, device="cuda:0", reload=False, launch_limit
                 rep.fail(f"it{it}: termination gpu {res['status']} / {gs['done_code']} oracle {st}")
             rep.final_status = st
             break
+        if gpu_prev is not None:
+            adopt_states(W, gpu_prev)
         recs = W.expand_all()
         res = G.plan()
         torch.cuda.synchronize()
@@ -521,8 +548,9 @@ def run_lockstep_batch(problems, iterations, config=None, device="cuda:0"):
                 rep.final_status = st
                 live.remove(i)
                 continue
-            recs[i] = W.expand_all()
             prev[i] = G.copy_tree()
+            adopt_states(W, prev[i])
+            recs[i] = W.expand_all()
         if not live:
             break
         res, _ = B.plan()
