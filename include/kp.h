@@ -307,6 +307,8 @@ kp_status kp_set_trace(kp_problem* h, void* dev_trace);
 kp_status kp_set_launch_limits(kp_problem* h, int32_t prop_blocks, int32_t node_blocks);
 
 const char* kp_status_str(kp_status s);
+/* Text of the last error of handle h; with h = NULL, of the last failed call
+ * on this thread that takes no handle and reports one (kp_mlp_train_noalloc). */
 const char* kp_last_error(const kp_problem* h);
 
 /* ---------------------------------------------------------------------------
@@ -389,6 +391,28 @@ kp_status kp_mlp_train(float* dev_params, float* dev_m1, float* dev_m2, void* de
                        const float* dev_x, const float* dev_t, int32_t n_rows, int32_t n_ctrl,
                        int32_t batch, int32_t steps, int32_t step0, float lr, uint64_t sample_key,
                        float* dev_partials, float* dev_loss, void* hip_stream);
+
+/* kp_mlp_train without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results as
+ * kp_mlp_train, minus dev_partials: the partial gradients of each step live
+ * in a file-scope device array of the library that holds
+ * KP_MLP_STATIC_MAX_BATCH / KP_MLP_BLOCK_ROWS partial gradients (32 x
+ * KP_MLP_PARAMS floats, 2.5 MB).  Each GPU the library runs on holds its own
+ * copy until the process ends; the first call on a GPU looks up its address
+ * there (no allocation).  The call allocates nothing, on the device or the
+ * host.
+ *   batch > KP_MLP_STATIC_MAX_BATCH, or any argument kp_mlp_train refuses:
+ *   KP_E_ARG, with the reason in kp_last_error(NULL) (per thread).
+ * Every call on one GPU shares that GPU's array and it keeps the last call's
+ * contents: calls that overlap on one GPU (two streams, two threads) race and
+ * must not be made.  Each step writes every partial gradient it uses before
+ * it reads it, so nothing needs to start at zero. */
+#define KP_MLP_STATIC_MAX_BATCH 2048
+kp_status kp_mlp_train_noalloc(float* dev_params, float* dev_m1, float* dev_m2, void* dev_packed,
+                               const float* dev_x, const float* dev_t, int32_t n_rows,
+                               int32_t n_ctrl, int32_t batch, int32_t steps, int32_t step0,
+                               float lr, uint64_t sample_key, float* dev_loss, void* hip_stream);
 
 /* Use the packed network dev_packed for the handle's expansions from the next
  * kp_expand / kp_plan on, mixed with the uniform draw at rate mix in [0, 1):

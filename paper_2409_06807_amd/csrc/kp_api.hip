@@ -4,8 +4,10 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +18,15 @@
 using namespace kp;
 
 namespace {
+// Text of the last failed call without a handle, per thread (kp_last_error(NULL)).
+thread_local char g_call_err[256] = "";
+
+void call_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_call_err, sizeof g_call_err, fmt, ap);
+  va_end(ap);
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kProfKernels = 7;  // propagate, region, node sets, frontier, commit, fused post,
@@ -1010,12 +1021,63 @@ const char* kp_status_str(kp_status s) {
   return "unknown status";
 }
 
-const char* kp_last_error(const kp_problem* h) { return h ? h->err.c_str() : ""; }
+const char* kp_last_error(const kp_problem* h) { return h ? h->err.c_str() : g_call_err; }
 
 // ---------------------------------------------------------------------------
 // learned proposal
 // ---------------------------------------------------------------------------
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // extern "C"
+
+// Partial gradients of kp_mlp_train_noalloc: a file-scope device array, one
+// copy per GPU, in place of a caller workspace.  Host code never passes the
+// array's name to a kernel (on the host it only stands in for the symbol);
+// it passes the device address that hipGetSymbolAddress gives on each GPU.
+namespace {
+constexpr int kStaticPartials = KP_MLP_STATIC_MAX_BATCH / KP_MLP_BLOCK_ROWS;
+static_assert(KP_MLP_STATIC_MAX_BATCH % KP_MLP_BLOCK_ROWS == 0, "whole partial blocks");
+constexpr int kMaxDevices = 64;
+std::mutex g_partials_mu;
+float* g_partials_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) float scratch[(size_t)kStaticPartials * KP_MLP_PARAMS];
+
+namespace {
+// The device address of `scratch` on the GPU that stream s runs on, looked
+// up once per GPU with that GPU current.
+kp_status static_partials(hipStream_t s, float** out) {
+  int dev = -1;
+  hipError_t e = s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    call_error("kp_mlp_train_noalloc: no device for the stream (%s)", hipGetErrorString(e));
+    return KP_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_partials_mu);
+  if (!g_partials_ptr[dev]) {
+    int cur = -1;
+    e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void* ptr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess || !ptr) {
+      call_error("kp_mlp_train_noalloc: address of the partial-gradient array on device %d: %s",
+                 dev, hipGetErrorString(e));
+      return KP_E_DEVICE;
+    }
+    g_partials_ptr[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_partials_ptr[dev];
+  return KP_OK;
+}
+}  // namespace
+
+extern "C" {
 
 kp_status kp_mlp_pack(const float* dev_params, void* dev_packed, void* hip_stream) {
   if (!dev_params || !dev_packed || !aligned16(dev_packed)) return KP_E_ARG;
@@ -1088,6 +1150,28 @@ kp_status kp_mlp_train(float* dev_params, float* dev_m1, float* dev_m2, void* de
     if (st != KP_OK) return st;
   }
   return kp_mlp_pack(dev_params, dev_packed, hip_stream);
+}
+
+kp_status kp_mlp_train_noalloc(float* dev_params, float* dev_m1, float* dev_m2, void* dev_packed,
+                               const float* dev_x, const float* dev_t, int32_t n_rows,
+                               int32_t n_ctrl, int32_t batch, int32_t steps, int32_t step0,
+                               float lr, uint64_t sample_key, float* dev_loss, void* hip_stream) {
+  if (batch < 1 || batch > KP_MLP_STATIC_MAX_BATCH) {
+    call_error("kp_mlp_train_noalloc: batch %d outside 1 .. %d (the static partial-gradient "
+               "array holds %d partial gradients)", (int)batch, KP_MLP_STATIC_MAX_BATCH,
+               kStaticPartials);
+    return KP_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  float* partials = nullptr;
+  const kp_status st = static_partials(s, &partials);
+  if (st != KP_OK) return st;
+  const kp_status r = kp_mlp_train(dev_params, dev_m1, dev_m2, dev_packed, dev_x, dev_t, n_rows,
+                                   n_ctrl, batch, steps, step0, lr, sample_key, partials, dev_loss,
+                                   hip_stream);
+  if (r == KP_E_ARG) call_error("kp_mlp_train_noalloc: invalid argument (see kp_mlp_train)");
+  else if (r != KP_OK) call_error("kp_mlp_train_noalloc: launch failed");
+  return r;
 }
 
 kp_status kp_set_proposal(kp_problem* h, const void* dev_packed, float* dev_head, int64_t head_rows,

@@ -35,7 +35,7 @@ EXPORTED = [
     "kp_batch_workspace_bytes", "kp_batch_create", "kp_batch_set_config", "kp_batch_get_config",
     "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error", "kp_batch_reset",
     "kp_transfer_tree", "kp_set_trace", "kp_set_launch_limits", "kp_get_trajectory",
-    "kp_log_tree_edges",
+    "kp_log_tree_edges", "kp_mlp_train_noalloc",
 ]
 
 
@@ -163,10 +163,12 @@ def load_library():
                               C.c_float, P]
     L.kp_mlp_train.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                C.c_int32, C.c_float, C.c_uint64, P, P, P]
+    L.kp_mlp_train_noalloc.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_int32, C.c_int32, C.c_float, C.c_uint64, P, P]
     L.kp_set_proposal.argtypes = [P, P, P, C.c_int64, C.c_float]
     L.kp_log_path.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     for name in ("kp_mlp_pack", "kp_mlp_forward", "kp_mlp_grad", "kp_mlp_adam", "kp_mlp_train",
-                 "kp_set_proposal", "kp_log_path"):
+                 "kp_mlp_train_noalloc", "kp_set_proposal", "kp_log_path"):
         getattr(L, name).restype = C.c_int
     L.kp_batch_workspace_bytes.argtypes = [C.c_int32]
     L.kp_batch_workspace_bytes.restype = C.c_size_t
@@ -574,6 +576,33 @@ def mlp_train(params, m1, m2, packed, X, T, n_ctrl: int, batch: int, steps: int,
         int(key) & ((1 << 64) - 1), C.c_void_p(partials.data_ptr()), C.c_void_p(loss.data_ptr()),
         _stream_ptr(X)), "kp_mlp_train")
     return loss[:steps].sum(dim=1)
+
+
+MLP_STATIC_MAX_BATCH = 2048
+
+
+def mlp_train_noalloc(params, m1, m2, packed, X, T, n_ctrl: int, batch: int, steps: int,
+                      lr: float, key: int, loss, step0: int = 0):
+    """kp_mlp_train_noalloc: mlp_train with the partial gradients in the
+    library's static device array; loss (steps x ceil(batch/64) float32,
+    caller-owned) receives the partial losses.  Allocates nothing."""
+    import torch
+    _need(X, MLP_INPUTS, "X")
+    _need(T, 4, "T", rows=int(X.shape[0]))
+    for t, name in ((params, "params"), (m1, "m1"), (m2, "m2")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == MLP_PARAMS):
+            raise KPError(E_ARG, f"{name}: need {MLP_PARAMS} contiguous float32 CUDA values")
+    if not (loss.is_cuda and loss.dtype == torch.float32 and loss.is_contiguous() and
+            loss.numel() >= max(int(steps), 1) * mlp_partials(max(int(batch), 1))):
+        raise KPError(E_ARG, "loss: need steps x ceil(batch/64) contiguous float32 CUDA values")
+    lib = load_library()
+    st = lib.kp_mlp_train_noalloc(
+        C.c_void_p(params.data_ptr()), C.c_void_p(m1.data_ptr()), C.c_void_p(m2.data_ptr()),
+        C.c_void_p(packed.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+        int(X.shape[0]), int(n_ctrl), int(batch), int(steps), int(step0), C.c_float(lr),
+        int(key) & ((1 << 64) - 1), C.c_void_p(loss.data_ptr()), _stream_ptr(X))
+    if st != OK:
+        raise KPError(st, "kp_mlp_train_noalloc: " + (lib.kp_last_error(None) or b"").decode())
 
 
 # ---------------------------------------------------------------------------

@@ -116,6 +116,7 @@ def test_struct_layouts_match_header(lib):
     assert kp.TRACE_DTYPE.itemsize == 100
     src = open(os.path.join(ROOT, "include", "kp.h")).read()
     assert f"KP_ABI_VERSION {kp.kp.KP_ABI_VERSION}u" in src
+    assert f"#define KP_MLP_STATIC_MAX_BATCH {kp.kp.MLP_STATIC_MAX_BATCH}\n" in src
     # the description's last fields: duration mode and a zero reserved word
     assert kp.kp.Desc.duration_mode.offset + 8 == C.sizeof(kp.kp.Desc)
     p = problem_small_di()
