@@ -38,7 +38,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t ctl, env, x, u, parent, cell, flag, birth, sample, F;
   size_t nv, ni, visited, thr, avail, obs, st_front, st_nodes, path;
-  size_t sx, su, scell, slane, spar, scount, ssum;
+  size_t sx, su, scell, slane, spar, scount, ssum, og;
   size_t total;
   int capP, tiles_node, nchunk;
 };
@@ -83,6 +83,102 @@ std::string check_desc(const kp_problem_desc* d) {
   return std::string();
 }
 
+// Uniform grid over the workspace that lists, per cell, the obstacles a
+// swept box touching the cell may hit (a double integrator among more than
+// kGridMinObstacles boxes; other problems cull per tile instead).  Cells are cubes of width 1 / inv from org
+// (the workspace grown by the margin and a little more), the index of
+// coordinate x on axis a is floor((x - org_a) * inv) clamped to the grid,
+// and an obstacle is listed in every cell of the index range of its own box,
+// each end widened by 1e-3 of a cell.  The kernel widens the index range of a
+// swept box the same way; a point that a swept box shares with an obstacle
+// then lies in a cell that the kernel visits and that lists the obstacle, as
+// long as the kernel's FP32 index map errs by less than 1e-3 of a cell (it
+// errs by a few units in the last place).  The grid is the finest of a few
+// sizes whose words (cell offsets, then ids, u16) fit kGridMaxWords, with at
+// most max(64, 16 n_obs) cells.
+struct ObsGrid {
+  int n[3] = {0, 0, 0};
+  float org[3] = {0.0f, 0.0f, 0.0f};
+  float inv = 0.0f;
+  std::vector<uint16_t> words;  // offsets [ncell + 1], then obstacle ids; even length
+};
+
+ObsGrid build_obs_grid(const kp_problem_desc* d) {
+  ObsGrid g;
+  if (d->dynamics != KP_DYN_DI6 || d->n_obstacles <= kGridMinObstacles) return g;
+  const int no = d->n_obstacles;
+  double lo[3], ext = 0.0, span[3];
+  for (int a = 0; a < 3; ++a) {
+    const double big = std::fmax(std::fabs((double)d->x_lo[a]), std::fabs((double)d->x_hi[a]));
+    const double pad = (double)d->margin + 1e-3 * (1.0 + big);
+    lo[a] = (double)d->x_lo[a] - pad;
+    span[a] = ((double)d->x_hi[a] + pad) - lo[a];
+    ext = std::fmax(ext, span[a]);
+  }
+  static const int kCells[] = {32, 24, 20, 16, 12, 10, 8, 6, 5, 4, 3, 2, 1};
+  for (const int gm : kCells) {
+    const float inv = (float)((double)gm / ext);
+    const double invd = (double)inv;
+    int n[3];
+    float org[3];
+    long long ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+      org[a] = (float)lo[a];
+      n[a] = (int)std::ceil(((double)lo[a] + span[a] - (double)org[a]) * invd);
+      if (n[a] < 1) n[a] = 1;
+      ncell *= n[a];
+    }
+    if (gm > 1 && (ncell > std::max<long long>(64, 16LL * no) || ncell + 1 > kGridMaxWords))
+      continue;
+    // cell index range of each obstacle, per axis
+    std::vector<int> rng((size_t)6 * (no > 0 ? no : 1));
+    for (int k = 0; k < no; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        auto idx = [&](double x, double slack) {
+          const double t = std::floor((x - (double)org[a]) * invd + slack);
+          return (int)std::fmin(std::fmax(t, 0.0), (double)(n[a] - 1));
+        };
+        const double olo = d->obstacles[6 * k + a], ohi = d->obstacles[6 * k + 3 + a];
+        const int i0 = idx(std::fmin(olo, ohi), -1e-3), i1 = idx(std::fmax(olo, ohi), 1e-3);
+        rng[6 * k + a] = i0;
+        rng[6 * k + 3 + a] = i1;
+      }
+    }
+    std::vector<uint32_t> cnt((size_t)ncell + 1, 0u);
+    long long total = 0;
+    for (int k = 0; k < no; ++k) {
+      const int* r = &rng[6 * k];
+      for (int z = r[2]; z <= r[5]; ++z)
+        for (int y = r[1]; y <= r[4]; ++y)
+          for (int x = r[0]; x <= r[3]; ++x) ++cnt[((size_t)z * n[1] + y) * n[0] + x];
+      total += (long long)(r[3] - r[0] + 1) * (r[4] - r[1] + 1) * (r[5] - r[2] + 1);
+    }
+    if (gm > 1 && ncell + 1 + total > kGridMaxWords) continue;
+    g.words.assign((size_t)(ncell + 1 + total + 1) & ~(size_t)1, 0);
+    uint32_t off = 0;
+    for (long long c = 0; c < ncell; ++c) {
+      g.words[(size_t)c] = (uint16_t)off;
+      off += cnt[(size_t)c];
+    }
+    g.words[(size_t)ncell] = (uint16_t)off;
+    std::vector<uint32_t> fill(g.words.begin(), g.words.begin() + ncell);
+    uint16_t* ids = g.words.data() + ncell + 1;
+    for (int k = 0; k < no; ++k) {  // ascending ids in every list
+      const int* r = &rng[6 * k];
+      for (int z = r[2]; z <= r[5]; ++z)
+        for (int y = r[1]; y <= r[4]; ++y)
+          for (int x = r[0]; x <= r[3]; ++x) ids[fill[((size_t)z * n[1] + y) * n[0] + x]++] = (uint16_t)k;
+    }
+    for (int a = 0; a < 3; ++a) {
+      g.n[a] = n[a];
+      g.org[a] = org[a];
+    }
+    g.inv = inv;
+    return g;
+  }
+  return g;  // not reached: one cell always fits
+}
+
 Layout make_layout(const kp_problem_desc* d) {
   Layout L{};
   const int n = state_dim(d->dynamics), m = ctrl_dim(d->dynamics);
@@ -123,6 +219,7 @@ Layout make_layout(const kp_problem_desc* d) {
   L.spar = take(capP * 4);
   L.scount = take(((size_t)d->node_cap / 64 + 2) * 4);  // one count per 64-lane wave tile
   L.ssum = take((size_t)L.nchunk * 2 * 4);
+  L.og = take(build_obs_grid(d).words.size() * 2 + 4);
   L.total = off;
   return L;
 }
@@ -144,6 +241,8 @@ double point_box_d2(const double* c, const double* lo, const double* hi) {
 struct kp_problem {
   kp_problem_desc desc;
   std::vector<float> obs;  // row-major copy
+  ObsGrid og;              // double integrator: obstacle grid (uploaded at create)
+  size_t lds_prop = 0;     // dynamic LDS of a propagate block
   Params prm;
   Dev dev;
   Env* env_dev;  // device copy of {prm, dev} read by the kernels
@@ -257,6 +356,12 @@ void fill_params(kp_problem* h) {
   p.box_sym = quad_box_symmetric(d) ? 1 : 0;
   p.key0 = (uint32_t)d.seed;
   p.key1 = (uint32_t)(d.seed >> 32);
+  for (int a = 0; a < 3; ++a) {
+    p.og_n[a] = h->og.n[a];
+    p.og_org[a] = h->og.org[a];
+  }
+  p.og_inv = h->og.inv;
+  p.og_words = (int32_t)h->og.words.size();
   p.delta = d.delta;
   p.eps = d.epsilon;
   // Culling radius: a step is collision-checked only when it starts from a
@@ -317,6 +422,7 @@ void carve(kp_problem* h, void* ws) {
   v.thr = reinterpret_cast<unsigned long long*>(b + L.thr);
   v.avail = reinterpret_cast<uint8_t*>(b + L.avail);
   v.obs = reinterpret_cast<float*>(b + L.obs);
+  v.og = reinterpret_cast<const uint16_t*>(b + L.og);
   v.st_front = reinterpret_cast<unsigned long long*>(b + L.st_front);
   v.st_nodes = reinterpret_cast<unsigned long long*>(b + L.st_nodes);
   v.path = reinterpret_cast<int32_t*>(b + L.path);
@@ -421,13 +527,14 @@ kp_status do_frontier(kp_problem* h, long long n_nodes) {
 // with_commit false: the caller follows with do_post (kp_plan)
 kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_commit) {
   h->ctl_fresh = false;
-  long long tiles = (lanes_ub + kPropBlock - 1) / kPropBlock;
+  // one block per 64-lane tile up to the cap (the kernel hands the first
+  // tiles to wave 0 of every block)
+  long long tiles = (lanes_ub + 63) / 64;
   const int gmax = cap_prop(h);
   int grid = (int)(tiles < gmax ? tiles : gmax);
   if (grid < 1) grid = 1;
   hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm.box_sym, h->env_dev,
-                                  h->desc.n_obstacles, trace, grid, h->stream,
-                                  prof_slot(h, 0));
+                                  h->lds_prop, trace, grid, h->stream, prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
   if (!with_commit) return KP_OK;
   const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
@@ -448,7 +555,8 @@ kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
   const int cmax = cap_commit(h), nmax = cap_node(h);
   const int nc = (int)(ctiles < cmax ? ctiles : cmax);
   const int nn = (int)(ntiles < nmax ? ntiles : nmax);
-  hipError_t e = launch_post(h->env_dev, nc, nn, h->stream, prof_slot(h, 5));
+  hipError_t e = launch_post(h->env_dev, post_region_blocks(h->R), nc, nn, h->stream,
+                             prof_slot(h, 5));
   if (e != hipSuccess) return hip_fail(h, e, "post launch");
   return KP_OK;
 }
@@ -565,6 +673,8 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
   h->desc = *desc;
   h->desc.obstacles = nullptr;
   h->obs.assign(desc->obstacles, desc->obstacles + (size_t)6 * desc->n_obstacles);
+  h->og = build_obs_grid(desc);
+  h->lds_prop = propagate_lds_bytes(desc->dynamics, desc->n_obstacles, (int)h->og.words.size());
   h->n = n;
   h->m = ctrl_dim(desc->dynamics);
   h->R = desc->grid[0] * desc->grid[1] * desc->grid[2];
@@ -588,7 +698,7 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
     return KP_E_DEVICE;
   }
   int bp = 1, bn = 1, bc = 1;
-  occupancy_propagate(desc->dynamics, desc->integrator, h->prm.box_sym, desc->n_obstacles, &bp);
+  occupancy_propagate(desc->dynamics, desc->integrator, h->prm.box_sym, h->lds_prop, &bp);
   occupancy_nodes(&bn);
   occupancy_commit(&bc);
   h->grid_prop_max = bp * h->cu_count;
@@ -607,6 +717,9 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
     for (int c = 0; c < 6; ++c) soa[(size_t)c * desc->n_obstacles + k] = h->obs[(size_t)6 * k + c];
   e = hipMemcpyAsync(h->dev.obs, soa.data(), soa.size() * sizeof(float), hipMemcpyHostToDevice,
                      h->stream);
+  if (e == hipSuccess && !h->og.words.empty())
+    e = hipMemcpyAsync(const_cast<uint16_t*>(h->dev.og), h->og.words.data(),
+                       h->og.words.size() * sizeof(uint16_t), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->dev.ctl, 0, sizeof(Ctl), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -1251,7 +1364,9 @@ struct kp_batch {
   BatchStatus* st_host = nullptr;     // pinned mirror
   hipStream_t stream = nullptr;       // the batch's own stream
   hipStream_t user_stream = nullptr;  // the problems' stream
-  int dyn = 0, integ = 0, n_obs_max = 0;
+  int dyn = 0, integ = 0;
+  size_t lds_prop = 0;                // dynamic LDS of a propagate block: the largest problem's
+  int region_blocks = 1;              // region blocks of a post grid row: the largest problem's
   int sym = 1;                        // every problem's state box is symmetric
   int learned = 0;                    // some problem has a learned proposal (set per plan)
   int prop_max = 1, node_max = 1;     // single-problem grid maxima
@@ -1291,15 +1406,15 @@ hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_
     hipError_t e = launch_mlp_head_batch(b->table, n, (int)(hb < cap ? hb : cap), b->stream);
     if (e != hipSuccess) return e;
   }
-  long long t = (lanes_ub + kPropBlock - 1) / kPropBlock;
+  long long t = (lanes_ub + 63) / 64;
   const int gp = (int)(t < b->cfg.prop_blocks ? t : b->cfg.prop_blocks);
   t = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   const int nc = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
   t = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
   const int nn = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
-  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->sym, b->table, n, b->n_obs_max,
+  hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->sym, b->table, n, b->lds_prop,
                                         gp < 1 ? 1 : gp, b->stream);
-  if (e == hipSuccess) e = launch_post_batch(b->table, n, nc, nn, b->stream);
+  if (e == hipSuccess) e = launch_post_batch(b->table, n, b->region_blocks, nc, nn, b->stream);
   return e;
 }
 
@@ -1368,13 +1483,14 @@ kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_work
   int prop_max = 1, node_max = 1;
   for (int i = 0; i < n; ++i) {
     const kp_problem* h = problems[i];
-    if (h->desc.n_obstacles > b->n_obs_max) b->n_obs_max = h->desc.n_obstacles;
+    if (h->lds_prop > b->lds_prop) b->lds_prop = h->lds_prop;
+    if (post_region_blocks(h->R) > b->region_blocks) b->region_blocks = post_region_blocks(h->R);
     if (!h->prm.box_sym) b->sym = 0;
     if (h->grid_node_max > node_max) node_max = h->grid_node_max;
     if (h->grid_commit_max > node_max) node_max = h->grid_commit_max;
   }
   int bp = 1;
-  occupancy_propagate(b->dyn, b->integ, b->sym, b->n_obs_max, &bp);
+  occupancy_propagate(b->dyn, b->integ, b->sym, b->lds_prop, &bp);
   prop_max = bp * problems[0]->cu_count;
   b->prop_max = prop_max;
   b->node_max = node_max;

@@ -5,14 +5,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kp.h"
+
 namespace kp {
 
-constexpr int kPropBlock = 256;      // lanes per propagate tile (4 waves)
+// threads per propagate block: 8 waves for the double integrator (two blocks
+// of up to 80 KiB of LDS per compute unit), 4 for the quadcopter
+__host__ __device__ constexpr int prop_block(int dyn) { return dyn == KP_DYN_DI6 ? 512 : 256; }
+// largest obstacle grid (u16 words: cell offsets and obstacle ids) a
+// double-integrator block stages in LDS
+constexpr int kGridMaxWords = 16384;
+// double integrators with more obstacles than this use the grid; with fewer,
+// a wave's candidate list is short or empty and costs less than a grid
+// lookup at every step
+constexpr int kGridMinObstacles = 64;
 constexpr int kNodeBlock = 1024;     // threads per node-pass block
 constexpr int kNodesPerThread = 4;   // nodes per thread in the node passes
 constexpr int kNodeTile = kNodeBlock * kNodesPerThread;  // nodes per node-pass tile (4096)
 constexpr int kChunkTiles = 256;     // 64-lane wave tiles per accepted-sample chunk sum
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
+constexpr int kRegionsPerBlock = 4 * 1024;  // regions per region block of k_post (4 per thread)
+// region blocks at the start of a k_post grid row
+__host__ __device__ constexpr int post_region_blocks(int R) {
+  return (R + kRegionsPerBlock - 1) / kRegionsPerBlock;
+}
 constexpr int kCommitBlock = 1024;   // threads per commit block (16 waves)
 constexpr int kMaxPath = 65536;      // longest path kp_get_path can return
 constexpr int kDoneNone = 0;
@@ -59,6 +75,12 @@ struct alignas(256) Ctl {
   // the iteration as k_propagate found it, read by k_post (whose finaliser
   // rewrites the fields above while other blocks may still start)
   int32_t slanes, slam;
+  // region pass of k_post over several blocks: the largest score (bits of a
+  // non-negative double), the sum of the scaled scores, and the blocks that
+  // have added to each and written their thresholds; k_propagate clears them
+  alignas(128) unsigned long long rg_max;
+  unsigned long long rg_sum;
+  uint32_t rg_cnt_max, rg_cnt_sum, rg_cnt_thr;
   TotLine tot[kGroups];  // propagate totals per group; the host adds the groups
   TkLine tkp[kGroups];   // propagate tile tickets per group; cleared by k_commit / k_post
 };
@@ -83,6 +105,12 @@ struct Params {
   float inv_m, inv_Ixx, inv_Iyy, inv_Izz;
   float dIyz, dIzx, dIxy;   // Iyy - Izz, Izz - Ixx, Ixx - Iyy
   uint32_t key0, key1;
+  // obstacle grid of the double integrator (og_n[0] = 0: none): og_n cells
+  // per axis of width 1 / og_inv from og_org; og_words u16 words
+  int32_t og_n[3];
+  int32_t og_words;
+  float og_org[3];
+  float og_inv;
   double delta, eps;
   // learned proposal: a sample takes the network's Gaussian when its mixture
   // word is below mix_thr (0: uniform only); network inputs are
@@ -118,6 +146,9 @@ struct Dev {
   unsigned long long* thr;      // [R]
   uint8_t* avail;      // [R]
   float* obs;          // [6][n_obs] SoA
+  // obstacle grid (double integrator): u16 offsets of the cells' lists
+  // [ncell + 1], then the lists' obstacle ids; padded to an even count
+  const uint16_t* og;
   unsigned long long* st_front;  // look-back status, one word per tile
   unsigned long long* st_nodes;
   // accepted samples staged per 64-lane wave tile: slot = tile * 64 + rank
@@ -161,12 +192,14 @@ struct Timing {
 hipError_t launch_zero(const Params& p, const Dev& d, const Env* env, hipStream_t s);
 hipError_t launch_root(const Env* env, Vec12 x_init, hipStream_t s);
 hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t);
-hipError_t launch_propagate(int dyn, int integ, int sym, const Env* env, int n_obs,
+hipError_t launch_propagate(int dyn, int integ, int sym, const Env* env, size_t lds,
                             TraceRec* trace, int grid, hipStream_t s, Timing t);
 hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
                          hipStream_t s, Timing t);
 hipError_t launch_region(const Env* env, hipStream_t s, Timing t);
-hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s, Timing t);
+// n_region: post_region_blocks(R) (the largest over a batch)
+hipError_t launch_post(const Env* env, int n_region, int n_commit, int n_nodes, hipStream_t s,
+                       Timing t);
 hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t);
 hipError_t launch_path(const Env* env, int32_t node, hipStream_t s);
 // rows of kTrajWords words (state, control, steps) of the path k_path wrote
@@ -179,9 +212,9 @@ struct BatchStatus {
   unsigned long long lanes_total, valid_total;
 };
 hipError_t launch_propagate_batch(int dyn, int integ, int sym, const Env* const* envs, int n,
-                                  int n_obs_max, int grid, hipStream_t s);
-hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
-                             hipStream_t s);
+                                  size_t lds, int grid, hipStream_t s);
+hipError_t launch_post_batch(const Env* const* envs, int n, int n_region, int n_commit,
+                             int n_nodes, hipStream_t s);
 hipError_t launch_batch_status(const Env* const* envs, int n, BatchStatus* out, hipStream_t s);
 hipError_t launch_set_done(const Env* env, int32_t code, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
@@ -211,9 +244,9 @@ int edge_tiles(int32_t n_nodes);
 hipError_t launch_edge_count(const Env* env, int tiles, uint32_t* tcount, hipStream_t s);
 hipError_t launch_edge_write(const Env* env, int tiles, const uint32_t* tcount, float* x, float* t,
                              int32_t cap_rows, int32_t row0, hipStream_t s);
-int occupancy_propagate(int dyn, int integ, int sym, int n_obs, int* blocks_per_cu);
+int occupancy_propagate(int dyn, int integ, int sym, size_t lds, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
 int occupancy_commit(int* blocks_per_cu);
-size_t propagate_lds_bytes(int n_obs);
+size_t propagate_lds_bytes(int dyn, int n_obs, int grid_words);
 
 }  // namespace kp

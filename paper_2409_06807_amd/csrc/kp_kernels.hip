@@ -767,13 +767,24 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int n_obs) {
          (size_t)kGroupsPerWave * 4;
 }
 constexpr int kBoundsFloats = 2 * 12;   // state box (lo[12], hi[12]) at the start of the block LDS
-constexpr size_t prop_lds_bytes(int n_obs) {
+// LDS of a propagate block.  Quadcopter: state box, obstacle table, per-wave
+// candidate lists.  Double integrator: state box, obstacle table, and the
+// obstacle grid (grid_words u16 words: cell offsets, then obstacle ids).
+constexpr size_t prop_lds_bytes(int dyn, int n_obs, int grid_words) {
   return kBoundsFloats * sizeof(float) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
-         (size_t)(kPropBlock / 64) * wave_lds_bytes(n_obs);
+         (grid_words > 0 ? (size_t)((grid_words + 1) & ~1) * 2
+                         : (size_t)(prop_block(dyn) / 64) * wave_lds_bytes(n_obs));
 }
-// gfx950 gives a workgroup up to 160 KiB of LDS
-static_assert(prop_lds_bytes(KP_MAX_OBSTACLES) <= 160 * 1024, "propagate LDS above 160 KiB");
-size_t propagate_lds_bytes(int n_obs) { return prop_lds_bytes(n_obs); }
+// gfx950 gives a workgroup up to 160 KiB of LDS; a double-integrator block
+// stays at or below 80 KiB, so that two of them share a compute unit
+static_assert(prop_lds_bytes(KP_DYN_QUAD12, KP_MAX_OBSTACLES, 0) <= 160 * 1024,
+              "propagate LDS above 160 KiB");
+static_assert(prop_lds_bytes(KP_DYN_DI6, KP_MAX_OBSTACLES, kGridMaxWords) <= 82 * 1024 &&
+                  prop_lds_bytes(KP_DYN_DI6, kGridMinObstacles, 0) <= 80 * 1024,
+              "double-integrator propagate LDS above two blocks per compute unit");
+size_t propagate_lds_bytes(int dyn, int n_obs, int grid_words) {
+  return prop_lds_bytes(dyn, n_obs, grid_words);
+}
 
 
 // Separation of two closed boxes: the largest gap along any axis between a
@@ -789,12 +800,52 @@ __device__ __forceinline__ float box_separation(float lx, float ly, float lz, fl
   return fmaxf(s0, s1);
 }
 
+// Box of every position a double-integrator segment passes through.  With
+// constant control the positions are a quadratic in the step index j:
+// explicit Euler gives p_j = p_0 + j h v_0 + h^2 u j (j - 1) / 2, and RK4,
+// exact on this system, p_0 + j h v_0 + (j h)^2 u / 2.  Per axis the range
+// over j in [0, K] is spanned by the two ends and, when it lies inside, the
+// vertex.  The box is widened by a bound on the rounding of K FP32 steps
+// (each at most a few units in the last place of coordinates below M), so
+// it holds the positions the kernel computes, not only the exact ones.
+template <int INTEG>
+__device__ __forceinline__ void segment_box_di(const float* x, const float* u, int K, float h,
+                                               float* lo, float* hi) {
+  const float kf = (float)K;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float A = 0.5f * h * h * u[a];
+    const float B = (INTEG == KP_INT_EULER) ? __builtin_fmaf(h, x[3 + a], -A) : h * x[3 + a];
+    const float C = x[a];
+    const float fk = __builtin_fmaf(kf, __builtin_fmaf(kf, A, B), C);
+    float l = fminf(C, fk), g = fmaxf(C, fk);
+    // vertex at j* = -B / (2A), value C - B^2 / (4A)
+    const float js = -B / (2.0f * A);
+    const bool inside = A != 0.0f && js > 0.0f && js < kf;
+    const float fv = C - (B * B) / (4.0f * A);
+    l = inside ? fminf(l, fv) : l;
+    g = inside ? fmaxf(g, fv) : g;
+    const float eps = 1e-3f + (kf + 4.0f) * 1e-6f * (1.0f + fmaxf(fabsf(l), fabsf(g)));
+    lo[a] = l - eps;
+    hi[a] = g + eps;
+  }
+}
+
+// Cell index floor(t) of a grid coordinate t, clamped to [0, ncell - 1]
+// (t is finite: the swept boxes tested lie inside the state box).
+__device__ __forceinline__ int clamp_cell(float t, int ncell) {
+  const int c = (int)floorf(t);
+  return c < 0 ? 0 : (c > ncell - 1 ? ncell - 1 : c);
+}
+
 template <int DYN, int INTEG, bool SYM>
 __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, TraceRec* trace) {
   const Params& p = env->p;
   const Dev& d = env->d;
   constexpr int n = Dim<DYN>::n;
   constexpr int m = Dim<DYN>::m;
+  constexpr int PB = prop_block(DYN);
+  constexpr int kWaves = PB / 64;
   extern __shared__ float lds[];
   Ctl* c = d.ctl;
   const int done = c->done;
@@ -807,6 +858,9 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   // copied for k_post
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c->tk_nodes = 0u;
+    c->rg_max = 0ull;
+    c->rg_sum = 0ull;
+    c->rg_cnt_max = c->rg_cnt_sum = c->rg_cnt_thr = 0u;
     c->sN = c->N;
     c->sit = (int32_t)it;
     c->sdone = done;
@@ -822,30 +876,50 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   const float margin = p.margin;
   const int n_obs = p.n_obs;
   const int wave = threadIdx.x >> 6;
+  // a double integrator among more than kGridMinObstacles boxes finds its
+  // obstacles through the grid at each step; otherwise (and always for the
+  // quadcopter) a wave culls them once per tile into candidate lists
+  const bool use_grid = DYN == KP_DYN_DI6 && p.og_n[0] > 0;
   // obstacle k in LDS: lo x, lo y, lo z, hi x, hi y, hi z (6 floats, read as 3 float2)
   float* bnd = lds;  // state box
   float* otab = lds + kBoundsFloats;
   const float2* obox = reinterpret_cast<const float2*>(otab);
-  char* wlds = reinterpret_cast<char*>(otab) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
-               (size_t)wave * wave_lds_bytes(n_obs);
+  char* after_tab = reinterpret_cast<char*>(otab) + (size_t)(n_obs + 1) * 6 * sizeof(float);
+  // double integrator: the obstacle grid (cell offsets, then obstacle ids)
+  uint16_t* goff = reinterpret_cast<uint16_t*>(after_tab);
+  const int gnx = p.og_n[0], gny = p.og_n[1];
+  const uint16_t* gent = goff + gnx * gny * p.og_n[2] + 1;
+  // quadcopter: this wave's candidate lists
+  char* wlds = after_tab + (size_t)wave * wave_lds_bytes(n_obs);
   uint16_t* cand = reinterpret_cast<uint16_t*>(wlds);
   uint16_t* glist = cand + union_stride(n_obs);
   uint32_t* gcnt = reinterpret_cast<uint32_t*>(glist + kGroupsPerWave * kGroupStride);
   // per-wave running totals (wave-uniform), flushed once per block
   unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0, t_checked = 0;
 
-  // A wave's first tile is its index in the grid.  Later tiles come from
-  // per-group ticket counters: group q (block index mod ng) hands out tiles
+  // A wave's first tile is wave * gridDim.x + block: the first gridDim.x
+  // tiles go to wave 0 of every block, the next ones to wave 1, and so on, so
+  // that a launch with fewer tiles than the grid has waves runs one wave per
+  // block, spread over the compute units.  Later tiles come from per-group
+  // ticket counters: group q (block index mod ng) hands out tiles
   // nwaves + ng * k + q.  No burst of tickets at launch, and each counter
   // sees about 1/ng of the requests.  A block whose first tiles are all past
   // the end has nothing to do (an oversized grid costs no atomics).
-  const uint32_t nwaves = gridDim.x * (kPropBlock / 64);
+  const uint32_t nwaves = gridDim.x * kWaves;
   const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
   const uint32_t grp = blockIdx.x % ng;
-  if (blockIdx.x * (kPropBlock / 64) >= ntiles) return;
-  for (int k = threadIdx.x; k < 6 * n_obs; k += kPropBlock) {
+  if (blockIdx.x >= ntiles) return;
+  for (int k = threadIdx.x; k < 6 * n_obs; k += PB) {
     const int ob = k / 6, comp = k - 6 * ob;
     otab[k] = d.obs[(size_t)comp * n_obs + ob];
+  }
+  if (use_grid) {
+    // the grid's u16 words, copied two at a time (the device copy is padded
+    // to an even count)
+    const int nw2 = (p.og_words + 1) >> 1;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(d.og);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(goff);
+    for (int k = threadIdx.x; k < nw2; k += PB) dst[k] = src[k];
   }
   if (threadIdx.x < 6) otab[6 * n_obs + threadIdx.x] = (threadIdx.x < 3) ? 3.0e38f : -3.0e38f;
   if (threadIdx.x < (unsigned)n) {
@@ -854,7 +928,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   }
   __syncthreads();
 
-  uint32_t next = blockIdx.x * (kPropBlock / 64) + (uint32_t)wave;
+  uint32_t next = (uint32_t)wave * gridDim.x + blockIdx.x;
   for (;;) {
     const uint32_t tile = next;
     if (tile >= ntiles) break;
@@ -911,91 +985,113 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       for (int j = 0; j < m; ++j) u[j] = 0.0f;
     }
 
-    // Obstacle culling.  Until its first failing step, a segment stays
-    // within rc (per axis) of its parent: every checked step starts from a
-    // state inside the velocity bounds.  Obstacles that overlap the union of
-    // the wave's parent boxes grown by rc + margin form the wave's union
-    // list.  The parents of one tile can lie far apart, and then the union
-    // box covers much of the scene; one such tile ran several times longer
-    // than the rest and set the launch time.  So a long union list is culled
-    // again per group of four lanes (one parent when lambda = 4) into short
-    // group lists; a lane tests only its group's list.
-    const float big = 3.0e38f;
-    const float bx0 = wave_min(active ? x[0] - p.rc : big);
-    const float by0 = wave_min(active ? x[1] - p.rc : big);
-    const float bz0 = wave_min(active ? x[2] - p.rc : big);
-    const float bx1 = wave_max(active ? x[0] + p.rc : -big);
-    const float by1 = wave_max(active ? x[1] + p.rc : -big);
-    const float bz1 = wave_max(active ? x[2] + p.rc : -big);
-    uint32_t ncand = 0;
-    for (int k0 = 0; k0 < n_obs; k0 += 64) {
-      const int k = k0 + (int)__lane_id();
-      bool ov = false;
-      if (k < n_obs) {
-        ov = box_separation(bx0 - p.margin, by0 - p.margin, bz0 - p.margin, bx1 + p.margin,
-                            by1 + p.margin, bz1 + p.margin, obox + 3 * k) <= 0.0f;
-      }
-      const unsigned long long b = __ballot(ov);
-      if (ov) cand[ncand + __popcll(b & lanes_below())] = (uint16_t)k;
-      ncand += (uint32_t)__popcll(b);
-    }
-    // the candidate lists are private to this wave: order their LDS writes
-    // before the reads of other lanes below
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t lane = __lane_id();
+    // Obstacle culling (without the grid).  Each lane has a reach box that
+    // holds every swept box its checked steps can test.  Double integrator:
+    // the box of the whole segment's positions (segment_box_di).
+    // Quadcopter: until its first failing step a segment stays within rc
+    // (per axis) of its parent, since every checked step starts from a state
+    // inside the velocity bounds.  Obstacles that overlap the union of the
+    // wave's reach boxes grown by the margin form the wave's union list.  The
+    // parents of one tile can lie far apart, and then the union box covers
+    // much of the scene; one such tile ran several times longer than the
+    // rest and set the launch time.  So a long union list is culled again
+    // per group of four lanes (one parent when lambda = 4) into short group
+    // lists; a lane tests only its group's list.
     const uint16_t* my = cand;  // this lane's candidate list and its length
-    uint32_t mycnt = ncand;
-    if (ncand > kGroupCull) {
-      // group box: the reach boxes of lanes 4q .. 4q+3
-      float q0 = active ? x[0] - p.rc : big, q1 = active ? x[1] - p.rc : big;
-      float q2 = active ? x[2] - p.rc : big, q3 = active ? x[0] + p.rc : -big;
-      float q4 = active ? x[1] + p.rc : -big, q5 = active ? x[2] + p.rc : -big;
-      static_assert(kLaneGroup == 4, "group boxes are reduced inside quads");
-      q0 = quad_min(q0);
-      q1 = quad_min(q1);
-      q2 = quad_min(q2);
-      q3 = quad_max(q3);
-      q4 = quad_max(q4);
-      q5 = quad_max(q5);
-      // in the passes below lane l serves group l % 16 and union entries
-      // c0 + l / 16, so one pass tests four entries against all 16 groups
-      const uint32_t gq = lane & (kGroupsPerWave - 1);
-      const int src = (int)gq * kLaneGroup;
-      const float m = p.margin;
-      const float b0 = __shfl(q0, src) - m, b1 = __shfl(q1, src) - m, b2 = __shfl(q2, src) - m;
-      const float b3 = __shfl(q3, src) + m, b4 = __shfl(q4, src) + m, b5 = __shfl(q5, src) + m;
-      const unsigned long long gm = 0x0001000100010001ull << gq;
-      uint32_t qn = 0;
-      for (uint32_t c0 = 0; c0 < ncand; c0 += 4) {
-        const uint32_t ci = c0 + (lane >> 4);
-        bool ov = false;
-        uint32_t ob = 0;
-        if (ci < ncand) {
-          ob = cand[ci];
-          ov = box_separation(b0, b1, b2, b3, b4, b5, obox + 3 * ob) <= 0.0f;
+    uint32_t mycnt = 0;
+    uint32_t kmax = 0;          // every list is read to this even length
+    if (!use_grid) {
+      const float big = 3.0e38f;
+      float rlo[3], rhi[3];
+      if constexpr (DYN == KP_DYN_DI6) {
+        segment_box_di<INTEG>(x, u, K, sc.h, rlo, rhi);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          rlo[a] = x[a] - p.rc;
+          rhi[a] = x[a] + p.rc;
         }
-        const unsigned long long hb = __ballot(ov) & gm;
-        const uint32_t pos = qn + (uint32_t)__popcll(hb & lanes_below());
-        if (ov && pos < (uint32_t)kGroupCap) glist[gq * kGroupStride + pos] = (uint16_t)ob;
-        qn += (uint32_t)__popcll(hb);
       }
-      if (lane < (uint32_t)kGroupsPerWave) gcnt[lane] = qn;
-      // every group fits: each lane takes its group's list; else the union
-      if (__ballot(qn > (uint32_t)kGroupCap) == 0ull) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t g4 = lane / kLaneGroup;
-        my = glist + g4 * kGroupStride;
-        mycnt = gcnt[g4];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        rlo[a] = active ? rlo[a] : big;
+        rhi[a] = active ? rhi[a] : -big;
       }
+      const float bx0 = wave_min(rlo[0]);
+      const float by0 = wave_min(rlo[1]);
+      const float bz0 = wave_min(rlo[2]);
+      const float bx1 = wave_max(rhi[0]);
+      const float by1 = wave_max(rhi[1]);
+      const float bz1 = wave_max(rhi[2]);
+      uint32_t ncand = 0;
+      for (int k0 = 0; k0 < n_obs; k0 += 64) {
+        const int k = k0 + (int)__lane_id();
+        bool ov = false;
+        if (k < n_obs) {
+          ov = box_separation(bx0 - p.margin, by0 - p.margin, bz0 - p.margin, bx1 + p.margin,
+                              by1 + p.margin, bz1 + p.margin, obox + 3 * k) <= 0.0f;
+        }
+        const unsigned long long b = __ballot(ov);
+        if (ov) cand[ncand + __popcll(b & lanes_below())] = (uint16_t)k;
+        ncand += (uint32_t)__popcll(b);
+      }
+      // the candidate lists are private to this wave: order their LDS writes
+      // before the reads of other lanes below
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t lane = __lane_id();
+      mycnt = ncand;
+      if (ncand > kGroupCull) {
+        // group box: the reach boxes of lanes 4q .. 4q+3
+        float q0 = rlo[0], q1 = rlo[1], q2 = rlo[2], q3 = rhi[0], q4 = rhi[1], q5 = rhi[2];
+        static_assert(kLaneGroup == 4, "group boxes are reduced inside quads");
+        q0 = quad_min(q0);
+        q1 = quad_min(q1);
+        q2 = quad_min(q2);
+        q3 = quad_max(q3);
+        q4 = quad_max(q4);
+        q5 = quad_max(q5);
+        // in the passes below lane l serves group l % 16 and union entries
+        // c0 + l / 16, so one pass tests four entries against all 16 groups
+        const uint32_t gq = lane & (kGroupsPerWave - 1);
+        const int src = (int)gq * kLaneGroup;
+        const float mg = p.margin;
+        const float b0 = __shfl(q0, src) - mg, b1 = __shfl(q1, src) - mg,
+                    b2 = __shfl(q2, src) - mg;
+        const float b3 = __shfl(q3, src) + mg, b4 = __shfl(q4, src) + mg,
+                    b5 = __shfl(q5, src) + mg;
+        const unsigned long long gm = 0x0001000100010001ull << gq;
+        uint32_t qn = 0;
+        for (uint32_t c0 = 0; c0 < ncand; c0 += 4) {
+          const uint32_t ci = c0 + (lane >> 4);
+          bool ov = false;
+          uint32_t ob = 0;
+          if (ci < ncand) {
+            ob = cand[ci];
+            ov = box_separation(b0, b1, b2, b3, b4, b5, obox + 3 * ob) <= 0.0f;
+          }
+          const unsigned long long hb = __ballot(ov) & gm;
+          const uint32_t pos = qn + (uint32_t)__popcll(hb & lanes_below());
+          if (ov && pos < (uint32_t)kGroupCap) glist[gq * kGroupStride + pos] = (uint16_t)ob;
+          qn += (uint32_t)__popcll(hb);
+        }
+        if (lane < (uint32_t)kGroupsPerWave) gcnt[lane] = qn;
+        // every group fits: each lane takes its group's list; else the union
+        if (__ballot(qn > (uint32_t)kGroupCap) == 0ull) {
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const uint32_t g4 = lane / kLaneGroup;
+          my = glist + g4 * kGroupStride;
+          mycnt = gcnt[g4];
+        }
+      }
+      // every list is read to the same even length; pad with the sentinel
+      kmax = (wave_max_u32(mycnt) + 1u) & ~1u;
+      for (uint32_t k = mycnt + (lane & (kLaneGroup - 1)); k < kmax; k += kLaneGroup)
+        const_cast<uint16_t*>(my)[k] = (uint16_t)n_obs;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    // every list is read to the same even length; pad with the sentinel
-    const uint32_t kmax = (wave_max_u32(mycnt) + 1u) & ~1u;
-    for (uint32_t k = mycnt + (lane & (kLaneGroup - 1)); k < kmax; k += kLaneGroup)
-      const_cast<uint16_t*>(my)[k] = (uint16_t)n_obs;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
 
     // x' = PropagateODE(x, u, dt): every lane integrates its whole segment.
     // Validity is decided step by step along the way (state box, then the
@@ -1028,19 +1124,47 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
             const float lz = fminf(pz, x[2]) - margin, hz = fmaxf(pz, x[2]) + margin;
             // six comparisons per candidate (closed boxes: touching is a hit);
             // measured faster here than the separation form used for culling.
-            // Two candidates per trip (one 32-bit read of their indices) so
-            // that their LDS reads overlap.
             bool hit = false;
-            for (uint32_t q = 0; q < kmax; q += 2) {
-              const uint32_t ij = *reinterpret_cast<const uint32_t*>(my + q);
-              const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
-              const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
-              hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
-                     (o[2] <= hz);
-              hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
-                     (r[2] <= hz);
+            if (use_grid) {
+              // the obstacles listed in the grid cells the swept box touches:
+              // its cell range, widened by 1e-3 of a cell so that FP32
+              // rounding of the index map cannot drop a cell (the lists were
+              // built with the same slack); on one row of cells (fixed y, z)
+              // the lists of the x range are contiguous
+              const float gi = p.og_inv;
+              const int cx0 = clamp_cell((lx - p.og_org[0]) * gi - 1e-3f, gnx);
+              const int cx1 = clamp_cell((hx - p.og_org[0]) * gi + 1e-3f, gnx);
+              const int cy0 = clamp_cell((ly - p.og_org[1]) * gi - 1e-3f, gny);
+              const int cy1 = clamp_cell((hy - p.og_org[1]) * gi + 1e-3f, gny);
+              const int cz0 = clamp_cell((lz - p.og_org[2]) * gi - 1e-3f, p.og_n[2]);
+              const int cz1 = clamp_cell((hz - p.og_org[2]) * gi + 1e-3f, p.og_n[2]);
+              for (int cz = cz0; cz <= cz1; ++cz) {
+                for (int cy = cy0; cy <= cy1; ++cy) {
+                  const int row = (cz * gny + cy) * gnx;
+                  const uint32_t k1 = goff[row + cx1 + 1];
+                  uint32_t k = goff[row + cx0];
+                  box_tests += k1 - k;
+                  for (; k < k1; ++k) {
+                    const float* o = reinterpret_cast<const float*>(obox + 3 * gent[k]);
+                    hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) &
+                           (lz <= o[5]) & (o[2] <= hz);
+                  }
+                }
+              }
+            } else {
+              // two candidates per trip (one 32-bit read of their indices)
+              // so that their LDS reads overlap
+              for (uint32_t q = 0; q < kmax; q += 2) {
+                const uint32_t ij = *reinterpret_cast<const uint32_t*>(my + q);
+                const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
+                const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
+                hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
+                       (o[2] <= hz);
+                hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
+                       (r[2] <= hz);
+              }
+              box_tests += mycnt;
             }
-            box_tests += mycnt;
             ok = !hit;
           }
           if (!ok) {
@@ -1133,7 +1257,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     t_box += wave_sum_u64((unsigned long long)box_tests);
   }
 
-  __shared__ unsigned long long s_tot[kPropBlock / 64][5];
+  __shared__ unsigned long long s_tot[kWaves][5];
   if (__lane_id() == 0) {
     s_tot[wave][0] = t_lanes;
     s_tot[wave][1] = t_valid;
@@ -1144,7 +1268,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long a[5] = {0, 0, 0, 0, 0};
-    for (int w = 0; w < kPropBlock / 64; ++w)
+    for (int w = 0; w < kWaves; ++w)
       for (int q = 0; q < 5; ++q) a[q] += s_tot[w][q];
     if (a[0]) {
       TotLine* t = &c->tot[blockIdx.x % kGroups];
@@ -1297,6 +1421,15 @@ __device__ __forceinline__ double region_score(double delta, unsigned long long 
   return num / den;
 }
 
+// P_accept = min(1, q / Q + eps) of a region with score sc as a 32-bit
+// threshold, the scores scaled by 2^(46 - e) (e: exponent of the largest).
+__device__ __forceinline__ unsigned long long region_thr(double sc, int e, unsigned long long Q,
+                                                         double eps) {
+  const unsigned long long qr = (unsigned long long)floor(ldexp(sc, 46 - e));
+  const double P = (Q > 0ull) ? (double)qr / (double)Q + eps : eps;
+  return (P >= 1.0) ? (1ull << 32) : (unsigned long long)floor(P * 4294967296.0);
+}
+
 // One workgroup of NT threads: three passes over the regions.
 // Up to kRegionsHeld regions per thread keep their score in registers
 // across the three passes (one read of the region counters); larger grids
@@ -1355,11 +1488,7 @@ __device__ void region_body(const Env* __restrict__ env) {
   unsigned long long Q = 0;
   for (int k = 0; k < NT / 64; ++k) Q += s_sum[k];
   // pass 3: P_accept = min(1, q / Q + eps) as a 32-bit threshold
-  auto thr_of = [&](double sc) -> unsigned long long {
-    const unsigned long long qr = (unsigned long long)floor(ldexp(sc, 46 - e));
-    const double P = (Q > 0ull) ? (double)qr / (double)Q + p.eps : p.eps;
-    return (P >= 1.0) ? (1ull << 32) : (unsigned long long)floor(P * 4294967296.0);
-  };
+  auto thr_of = [&](double sc) { return region_thr(sc, e, Q, p.eps); };
   if (held) {
 #pragma unroll
     for (int k = 0; k < kRegionsHeld; ++k) {
@@ -1376,6 +1505,99 @@ __device__ void region_body(const Env* __restrict__ env) {
 
 __global__ __launch_bounds__(kRegionBlock) void k_region(const Env* __restrict__ env) {
   region_body<kRegionBlock>(env);
+}
+
+// Wait until *ctr (incremented once by each region block) reaches n.  Every
+// region block of a grid row is dispatched before any other block of that
+// row, so they are resident together; the spin is bounded all the same.
+__device__ __forceinline__ void wait_count(Ctl* c, uint32_t* ctr, uint32_t n) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) {
+      if (++spins > (1u << 22)) {
+        atomicOr(&c->err, 8u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// UpdateEstimates in k_post, over nrb blocks of NT threads: block b holds
+// regions b * kRegionsPerBlock + threadIdx.x + k * NT (k < 4) in registers.
+// The largest score and the exact sum of the scaled scores are combined
+// across the blocks with device atomics (a maximum and an integer sum give
+// the same result in any order), so the thresholds are those of the
+// one-block pass.  The last block to write its thresholds publishes the
+// epoch in region_ready.
+template <int NT>
+__device__ void region_part(const Env* __restrict__ env, uint32_t b, uint32_t nrb, uint32_t epoch) {
+  static_assert(kRegionsPerBlock == 4 * NT, "four regions per thread");
+  const Params& p = env->p;
+  const Dev& d = env->d;
+  Ctl* c = d.ctl;
+  __shared__ double s_max[NT / 64];
+  __shared__ unsigned long long s_sum[NT / 64];
+  const int wave = threadIdx.x >> 6;
+  double sc[4];
+  double mx = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = (int)b * kRegionsPerBlock + threadIdx.x + k * NT;
+    sc[k] = -1.0;
+    if (r < p.R && d.avail[r])
+      sc[k] = region_score(p.delta, d.nv[r], d.ni[r], __popcll(d.visited[r]));
+    mx = fmax(mx, sc[k]);
+  }
+  mx = wave_max_f64(mx);
+  if (__lane_id() == 0) s_max[wave] = mx;
+  __syncthreads();
+  mx = 0.0;
+  for (int k = 0; k < NT / 64; ++k) mx = fmax(mx, s_max[k]);
+  if (nrb > 1) {
+    // non-negative doubles order like their bit patterns
+    if (threadIdx.x == 0) {
+      atomicMax(&c->rg_max, (unsigned long long)__double_as_longlong(mx));
+      __threadfence();
+      atomicAdd(&c->rg_cnt_max, 1u);
+    }
+    wait_count(c, &c->rg_cnt_max, nrb);
+    mx = __longlong_as_double((long long)__hip_atomic_load(&c->rg_max, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+  }
+  const int e = (mx > 0.0) ? ilogb(mx) : 0;
+  unsigned long long q = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (sc[k] >= 0.0) q += (unsigned long long)floor(ldexp(sc[k], 46 - e));
+  q = wave_sum_u64(q);
+  if (__lane_id() == 0) s_sum[wave] = q;
+  __syncthreads();
+  unsigned long long Q = 0;
+  for (int k = 0; k < NT / 64; ++k) Q += s_sum[k];
+  if (nrb > 1) {
+    if (threadIdx.x == 0) {
+      atomicAdd(&c->rg_sum, Q);
+      __threadfence();
+      atomicAdd(&c->rg_cnt_sum, 1u);
+    }
+    wait_count(c, &c->rg_cnt_sum, nrb);
+    Q = __hip_atomic_load(&c->rg_sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = (int)b * kRegionsPerBlock + threadIdx.x + k * NT;
+    if (r < p.R && sc[k] >= 0.0) d.thr[r] = region_thr(sc[k], e, Q, p.eps);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = (nrb > 1) ? atomicAdd(&c->rg_cnt_thr, 1u) : 0u;
+    if (prev + 1u == nrb)
+      __hip_atomic_store(&c->region_ready, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1549,21 +1771,25 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
   constexpr uint32_t wpb = kCommitBlock / 64;
   __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
 
-  if (blockIdx.x == 0) {
+  // grid row: nrb region blocks, nc commit blocks, then node-set blocks
+  const uint32_t nrb = (uint32_t)post_region_blocks(p.R);
+  if (blockIdx.x < nrb) {
     // ---- UpdateEstimates; and the counters of the next expansion ----
-    uint32_t* nxt = d.ssum + (size_t)((it + 1u) & 1u) * (size_t)d.nchunk;
-    for (int j = threadIdx.x; j < d.nchunk; j += kCommitBlock) nxt[j] = 0u;
-    if (threadIdx.x < (unsigned)kGroups) c->tkp[threadIdx.x].v = 0u;
-    if (!done) region_body<kCommitBlock>(env);
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0) {
+      uint32_t* nxt = d.ssum + (size_t)((it + 1u) & 1u) * (size_t)d.nchunk;
+      for (int j = threadIdx.x; j < d.nchunk; j += kCommitBlock) nxt[j] = 0u;
+      if (threadIdx.x < (unsigned)kGroups) c->tkp[threadIdx.x].v = 0u;
+    }
+    if (!done) {
+      region_part<kCommitBlock>(env, blockIdx.x, nrb, epoch);
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
       __threadfence();
       __hip_atomic_store(&c->region_ready, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
-  if (blockIdx.x <= (uint32_t)nc) {
-    const uint32_t ci = blockIdx.x - 1u;
+  if (blockIdx.x < nrb + (uint32_t)nc) {
+    const uint32_t ci = blockIdx.x - nrb;
     // ---- V_U ----
     CommitCtx k;
     k.N = N;
@@ -1602,8 +1828,8 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
     return;
   }
   // ---- UpdateNodeSets over the old nodes ----
-  const uint32_t nb = gridDim.x - 1u - (uint32_t)nc;
-  const uint32_t bi = blockIdx.x - 1u - (uint32_t)nc;
+  const uint32_t nb = gridDim.x - nrb - (uint32_t)nc;
+  const uint32_t bi = blockIdx.x - nrb - (uint32_t)nc;
   const bool goal = c->goal_hit != 0u;
   const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
   const bool by_ticket = ntiles > nb;
@@ -1697,17 +1923,18 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
 
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
 // batched launch over a table of problems; the work of each problem is the
-// same either way.  Waves per SIMD: the double-integrator kernels fit 96
-// registers and run 5; the quadcopter kernels need more than 96 (the tilt
-// sin / cos keep their range-checked reduction for segments that have left
-// the state box) and run 4.
+// same either way.  Waves per SIMD: 4 (at most 128 registers).  The
+// quadcopter kernels need more than 96 (the tilt sin / cos keep their
+// range-checked reduction for segments that have left the state box); a
+// compute unit holds two 8-wave double-integrator blocks either way, so a
+// fifth wave per SIMD would gain nothing there.
 template <int DYN, int INTEG, bool SYM>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate(
+__global__ __launch_bounds__(prop_block(DYN)) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(
     const Env* __restrict__ env, TraceRec* trace) {
   propagate_body<DYN, INTEG, SYM>(env, trace);
 }
 template <int DYN, int INTEG, bool SYM>
-__global__ __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(DYN == KP_DYN_DI6 ? 5 : 4))) void k_propagate_batch(
+__global__ __launch_bounds__(prop_block(DYN)) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate_batch(
     const Env* const* __restrict__ envs) {
   const Env* env = envs[blockIdx.y];
   propagate_body<DYN, INTEG, SYM>(env, env->d.trace);
@@ -1820,26 +2047,24 @@ hipError_t launch_frontier(const Env* env, int grid, hipStream_t s, Timing t) {
 }
 
 template <int DYN, int INTEG, bool SYM>
-static hipError_t launch_prop_t(const Env* env, int n_obs, TraceRec* trace, int grid,
+static hipError_t launch_prop_t(const Env* env, size_t lds, TraceRec* trace, int grid,
                                 hipStream_t s, Timing t) {
-  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG, SYM>), dim3(grid), dim3(kPropBlock),
-                        (uint32_t)propagate_lds_bytes(n_obs), s, t.start, t.stop, 0, env, trace);
+  hipExtLaunchKernelGGL((k_propagate<DYN, INTEG, SYM>), dim3(grid), dim3(prop_block(DYN)),
+                        (uint32_t)lds, s, t.start, t.stop, 0, env, trace);
   return hipGetLastError();
 }
 
-// sym: the quadcopter's state box is symmetric about zero outside position,
-// so its test is |x| <= hi there
-hipError_t launch_propagate(int dyn, int integ, int sym, const Env* env, int n_obs,
+hipError_t launch_propagate(int dyn, int integ, int sym, const Env* env, size_t lds,
                             TraceRec* trace, int grid, hipStream_t s, Timing t) {
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(env, n_obs, trace, grid, s, t);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(env, lds, trace, grid, s, t);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
-    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(env, n_obs, trace, grid, s, t);
+    return launch_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(env, lds, trace, grid, s, t);
   if (integ == KP_INT_EULER)
-    return sym ? launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(env, n_obs, trace, grid, s, t)
-                : launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(env, n_obs, trace, grid, s, t);
-  return sym ? launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(env, n_obs, trace, grid, s, t)
-              : launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(env, n_obs, trace, grid, s, t);
+    return sym ? launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(env, lds, trace, grid, s, t)
+                : launch_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(env, lds, trace, grid, s, t);
+  return sym ? launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(env, lds, trace, grid, s, t)
+              : launch_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(env, lds, trace, grid, s, t);
 }
 
 hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_region,
@@ -1851,11 +2076,12 @@ hipError_t launch_commit(const Env* env, TraceRec* trace, int grid, int with_reg
   return hipGetLastError();
 }
 
-hipError_t launch_post(const Env* env, int n_commit, int n_nodes, hipStream_t s, Timing t) {
+hipError_t launch_post(const Env* env, int n_region, int n_commit, int n_nodes, hipStream_t s,
+                       Timing t) {
   if (n_commit < 1) n_commit = 1;
   if (n_nodes < 1) n_nodes = 1;
-  hipExtLaunchKernelGGL(k_post, dim3(1 + n_commit + n_nodes), dim3(kCommitBlock), 0, s, t.start,
-                        t.stop, 0, env, n_commit);
+  hipExtLaunchKernelGGL(k_post, dim3(n_region + n_commit + n_nodes), dim3(kCommitBlock), 0, s,
+                        t.start, t.stop, 0, env, n_commit);
   return hipGetLastError();
 }
 
@@ -1870,33 +2096,33 @@ hipError_t launch_nodesets(const Env* env, int grid, hipStream_t s, Timing t) {
 }
 
 template <int DYN, int INTEG, bool SYM>
-static hipError_t launch_prop_batch_t(const Env* const* envs, int n, int n_obs_max, int grid,
+static hipError_t launch_prop_batch_t(const Env* const* envs, int n, size_t lds, int grid,
                                       hipStream_t s) {
-  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG, SYM>), dim3(grid, n), dim3(kPropBlock),
-                     (uint32_t)propagate_lds_bytes(n_obs_max), s, envs);
+  hipLaunchKernelGGL((k_propagate_batch<DYN, INTEG, SYM>), dim3(grid, n), dim3(prop_block(DYN)),
+                     (uint32_t)lds, s, envs);
   return hipGetLastError();
 }
 
 hipError_t launch_propagate_batch(int dyn, int integ, int sym, const Env* const* envs, int n,
-                                  int n_obs_max, int grid, hipStream_t s) {
+                                  size_t lds, int grid, hipStream_t s) {
   if (grid < 1) grid = 1;
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_EULER, false>(envs, n, n_obs_max, grid, s);
+    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_EULER, false>(envs, n, lds, grid, s);
   if (dyn == KP_DYN_DI6 && integ == KP_INT_RK4)
-    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_RK4, false>(envs, n, n_obs_max, grid, s);
+    return launch_prop_batch_t<KP_DYN_DI6, KP_INT_RK4, false>(envs, n, lds, grid, s);
   if (integ == KP_INT_EULER)
-    return sym ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, true>(envs, n, n_obs_max, grid, s)
-                : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, false>(envs, n, n_obs_max, grid, s);
-  return sym ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, true>(envs, n, n_obs_max, grid, s)
-              : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, false>(envs, n, n_obs_max, grid, s);
+    return sym ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, true>(envs, n, lds, grid, s)
+                : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_EULER, false>(envs, n, lds, grid, s);
+  return sym ? launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, true>(envs, n, lds, grid, s)
+              : launch_prop_batch_t<KP_DYN_QUAD12, KP_INT_RK4, false>(envs, n, lds, grid, s);
 }
 
-hipError_t launch_post_batch(const Env* const* envs, int n, int n_commit, int n_nodes,
-                             hipStream_t s) {
+hipError_t launch_post_batch(const Env* const* envs, int n, int n_region, int n_commit,
+                             int n_nodes, hipStream_t s) {
   if (n_commit < 1) n_commit = 1;
   if (n_nodes < 1) n_nodes = 1;
-  hipLaunchKernelGGL(k_post_batch, dim3(1 + n_commit + n_nodes, n), dim3(kCommitBlock), 0, s, envs,
-                     n_commit);
+  hipLaunchKernelGGL(k_post_batch, dim3(n_region + n_commit + n_nodes, n), dim3(kCommitBlock), 0, s,
+                     envs, n_commit);
   return hipGetLastError();
 }
 
@@ -1927,7 +2153,10 @@ hipError_t launch_path(const Env* env, int32_t node, hipStream_t s) {
 // never inside a captured graph.
 template <int DYN, int INTEG, bool SYM>
 static hipError_t allow_lds_t() {
-  const int bytes = (int)prop_lds_bytes(KP_MAX_OBSTACLES);
+  // the largest table: the double integrator's with the grid, the
+  // quadcopter's with per-wave candidate lists
+  const int bytes =
+      (int)prop_lds_bytes(DYN, KP_MAX_OBSTACLES, DYN == KP_DYN_DI6 ? kGridMaxWords : 0);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<DYN, INTEG, SYM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
@@ -1948,29 +2177,29 @@ static hipError_t allow_lds_all() {
 }
 
 template <int DYN, int INTEG, bool SYM>
-static int occ_prop_t(int n_obs) {
+static int occ_prop_t(size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG, SYM>, kPropBlock,
-                                                    propagate_lds_bytes(n_obs)) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_propagate<DYN, INTEG, SYM>,
+                                                    prop_block(DYN), lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-int occupancy_propagate(int dyn, int integ, int sym, int n_obs, int* blocks_per_cu) {
+int occupancy_propagate(int dyn, int integ, int sym, size_t lds, int* blocks_per_cu) {
   int nb;
   // if raising the limit fails, launches above 64 KiB of LDS fail and
   // report it; clear the error so that it does not surface at another call
   if (allow_lds_all() != hipSuccess) (void)hipGetLastError();
   if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
-    nb = occ_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(n_obs);
+    nb = occ_prop_t<KP_DYN_DI6, KP_INT_EULER, false>(lds);
   else if (dyn == KP_DYN_DI6)
-    nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(n_obs);
+    nb = occ_prop_t<KP_DYN_DI6, KP_INT_RK4, false>(lds);
   else if (integ == KP_INT_EULER)
-    nb = sym ? occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(n_obs)
-              : occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(n_obs);
+    nb = sym ? occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, true>(lds)
+              : occ_prop_t<KP_DYN_QUAD12, KP_INT_EULER, false>(lds);
   else
-    nb = sym ? occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(n_obs)
-              : occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(n_obs);
+    nb = sym ? occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, true>(lds)
+              : occ_prop_t<KP_DYN_QUAD12, KP_INT_RK4, false>(lds);
   *blocks_per_cu = nb;
   return nb;
 }
