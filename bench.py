@@ -397,10 +397,11 @@ def batched_leg(n_queries, batch_seed=3):
     }
 
 
-def sweep(workload, seeds, caps, eps_delta):
+def sweep(workload, seeds, caps, eps_delta, lambdas=(), only_lambda=False):
     """Time-to-solution and failures against the tree capacity t_e (the
     paper's only scaling experiment, Sec. VI), then against epsilon and delta
-    at the workload's own capacity.  One JSON line per setting."""
+    at the workload's own capacity, and against the branching bound lambda_max
+    of eq. (6).  One JSON line per setting."""
     from paper_2409_06807_amd import Planner, SOLVED
 
     def run(p):
@@ -422,6 +423,14 @@ def sweep(workload, seeds, caps, eps_delta):
                 "mean_tts_ms": statistics.mean(solved) if solved else None,
                 "median_iterations": statistics.median(it), "statuses": st}
 
+    for lam in lambdas:
+        p = gpu_workload(workload, 0)
+        p["lambda_max"] = int(lam)
+        print(json.dumps({"mode": "lambda_max sweep", "workload": p["name"], "lambda_max": int(lam),
+                          "node_cap": int(p["node_cap"]), "seeds": len(seeds), **run(p)}),
+              flush=True)
+    if only_lambda:
+        return
     for cap in caps:
         p = gpu_workload(workload, 0)
         p["node_cap"] = int(cap)
@@ -489,6 +498,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the bench line, sweep the tree capacity t_e and then epsilon "
                          "and delta on the workload (one JSON line per setting)")
+    ap.add_argument("--lambda-sweep", action="store_true",
+                    help="instead of the bench line, sweep lambda_max (eq. 6) on the workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-planning leg")
     ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
@@ -510,12 +521,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if args.sweep:
+    if args.sweep or args.lambda_sweep:
         seeds = list(range(max(args.steps, 1)))
         base = int(gpu_workload(args.workload, 0)["node_cap"])
         caps = [base // 8, base // 4, base // 2, base, base * 2]
         eps_delta = [(1e-2, 1e-3), (1e-3, 1e-3), (1e-1, 1e-3), (1e-2, 1e-1), (1e-2, 1e-5)]
-        sweep(args.workload, seeds, caps, eps_delta)
+        lambdas = (2, 4, 6, 8, 12, 16, 32)
+        sweep(args.workload, seeds, caps, eps_delta, lambdas=lambdas,
+              only_lambda=args.lambda_sweep)
         return
 
     p = gpu_workload(args.workload, 0)

@@ -253,6 +253,7 @@ struct kp_problem {
   int cu_count;
   int grid_prop_max;
   int grid_node_max;
+  int grid_post_max;   // k_post blocks resident at once (its node-set blocks are capped by it)
   int grid_commit_max;
   int grid_head_max;
   int lim_prop = 0, lim_node = 0;  // kp_set_launch_limits caps (0: none)
@@ -505,6 +506,9 @@ int cap_prop(const kp_problem* h) {
 int cap_node(const kp_problem* h) {
   return (h->lim_node > 0 && h->lim_node < h->grid_node_max) ? h->lim_node : h->grid_node_max;
 }
+int cap_post_nodes(const kp_problem* h) {
+  return (h->lim_node > 0 && h->lim_node < h->grid_post_max) ? h->lim_node : h->grid_post_max;
+}
 int cap_commit(const kp_problem* h) {
   return (h->lim_node > 0 && h->lim_node < h->grid_commit_max) ? h->lim_node : h->grid_commit_max;
 }
@@ -552,7 +556,7 @@ kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
   h->ctl_fresh = false;
   const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   const long long ntiles = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
-  const int cmax = cap_commit(h), nmax = cap_node(h);
+  const int cmax = cap_commit(h), nmax = cap_post_nodes(h);
   const int nc = (int)(ctiles < cmax ? ctiles : cmax);
   const int nn = (int)(ntiles < nmax ? ntiles : nmax);
   hipError_t e = launch_post(h->env_dev, post_region_blocks(h->R), nc, nn, h->stream,
@@ -697,12 +701,14 @@ kp_status kp_create_problem(const kp_problem_desc* desc, void* dev_workspace, si
     delete h;
     return KP_E_DEVICE;
   }
-  int bp = 1, bn = 1, bc = 1;
+  int bp = 1, bn = 1, bc = 1, bpo = 1;
   occupancy_propagate(desc->dynamics, desc->integrator, h->prm.box_sym, h->lds_prop, &bp);
   occupancy_nodes(&bn);
   occupancy_commit(&bc);
+  occupancy_post(&bpo);
   h->grid_prop_max = bp * h->cu_count;
   h->grid_node_max = bn * h->cu_count;
+  h->grid_post_max = bpo * h->cu_count;
   h->grid_commit_max = bc * h->cu_count;
   h->grid_head_max = mlp_head_grid_max(h->cu_count);
   if (hipHostMalloc(reinterpret_cast<void**>(&h->hctl), sizeof(Ctl), hipHostMallocDefault) !=
@@ -1486,7 +1492,7 @@ kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_work
     if (h->lds_prop > b->lds_prop) b->lds_prop = h->lds_prop;
     if (post_region_blocks(h->R) > b->region_blocks) b->region_blocks = post_region_blocks(h->R);
     if (!h->prm.box_sym) b->sym = 0;
-    if (h->grid_node_max > node_max) node_max = h->grid_node_max;
+    if (h->grid_post_max > node_max) node_max = h->grid_post_max;
     if (h->grid_commit_max > node_max) node_max = h->grid_commit_max;
   }
   int bp = 1;

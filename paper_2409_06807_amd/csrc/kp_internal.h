@@ -247,6 +247,7 @@ hipError_t launch_edge_write(const Env* env, int tiles, const uint32_t* tcount, 
 int occupancy_propagate(int dyn, int integ, int sym, size_t lds, int* blocks_per_cu);
 int occupancy_nodes(int* blocks_per_cu);
 int occupancy_commit(int* blocks_per_cu);
+int occupancy_post(int* blocks_per_cu);
 size_t propagate_lds_bytes(int dyn, int n_obs, int grid_words);
 
 }  // namespace kp

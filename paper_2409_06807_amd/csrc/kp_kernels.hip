@@ -2213,6 +2213,15 @@ int occupancy_commit(int* blocks_per_cu) {
   return nb;
 }
 
+int occupancy_post(int* blocks_per_cu) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_post, kCommitBlock, 0) != hipSuccess)
+    nb = 1;
+  if (nb < 1) nb = 1;
+  *blocks_per_cu = nb;
+  return nb;
+}
+
 int occupancy_nodes(int* blocks_per_cu) {
   int a = 0, b = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nodesets, kNodeBlock, 0) != hipSuccess)
