@@ -258,16 +258,19 @@ def expand_only(G, p, dyn, integ, reps):
 TRAIN_SEED0 = 1000  # training queries use planner seeds disjoint from the evaluated ones
 
 
-def learned_leg(G, p, steps, warmup, n_paths, train_steps, batch, lr, mix):
-    """Learned proposal against the uniform planner: log the solution paths
-    of uniform queries on training seeds, train the network on the GPU, then
-    time the same evaluation seeds with the learned proposal mixed in."""
+def learned_leg(G, p, steps, warmup, n_paths, rows_target, train_steps, batch, lr, mix):
+    """Learned proposal against the uniform planner: log training rows from
+    uniform queries on training seeds (the solution paths of n_paths queries,
+    then, up to rows_target rows, every tree edge of those queries that moves
+    towards the goal: valid expansions that made progress), train the network
+    on the GPU, then time the same evaluation seeds with the learned proposal
+    mixed in."""
     import torch
     import paper_2409_06807_amd as kp
     from paper_2409_06807_amd import SOLVED
     from workloads import mlp_inputs
     m = 3 if int(p["dynamics"]) == 0 else 4
-    cap = 64 * n_paths
+    cap = max(64 * n_paths, rows_target)
     X = torch.zeros((cap, 16), dtype=torch.float32, device="cuda:0")
     T = torch.zeros((cap, 4), dtype=torch.float32, device="cuda:0")
     rows = solved_paths = 0
@@ -278,6 +281,15 @@ def learned_leg(G, p, steps, warmup, n_paths, train_steps, batch, lr, mix):
         if r["status"] == SOLVED:
             rows += G.log_path(r["goal_id"], X, T, rows)
             solved_paths += 1
+    path_rows = rows
+    edge_trees = 0
+    for s in range(TRAIN_SEED0, TRAIN_SEED0 + n_paths):
+        if rows >= rows_target:
+            break
+        G.reset(s)
+        G.plan()
+        rows += G.log_tree_edges(X, T, rows)
+        edge_trees += 1
     collect_s = time.perf_counter() - t0
     params = torch.tensor(mlp_inputs.params(13), dtype=torch.float32, device="cuda:0")
     m1 = torch.zeros_like(params)
@@ -330,7 +342,9 @@ def learned_leg(G, p, steps, warmup, n_paths, train_steps, batch, lr, mix):
         "proposal_ms_per_launch": head_ms / n_head if n_head else None,
         "training": {
             "seeds": f"{TRAIN_SEED0}..{TRAIN_SEED0 + n_paths - 1} (uniform planner)",
-            "solved_paths": solved_paths, "rows": rows, "steps": train_steps, "batch": batch,
+            "solved_paths": solved_paths, "path_rows": path_rows,
+            "progress_edge_rows": rows - path_rows, "progress_edge_trees": edge_trees,
+            "rows": rows, "steps": train_steps, "batch": batch,
             "lr": lr, "loss_first10": float(lv[:10].mean()), "loss_last10": float(lv[-10:].mean()),
             "collect_s": collect_s, "train_ms": train_ms,
         },
@@ -493,7 +507,10 @@ def main():
                     help="skip the learned-proposal leg")
     ap.add_argument("--learned-paths", type=int, default=256,
                     help="uniform training queries whose solution paths are logged")
-    ap.add_argument("--learned-train-steps", type=int, default=1000)
+    ap.add_argument("--learned-rows", type=int, default=2_000_000,
+                    help="training rows: solution paths, then progress edges of the training trees")
+    ap.add_argument("--learned-train-steps", type=int, default=3000)
+    ap.add_argument("--learned-batch", type=int, default=2048)
     ap.add_argument("--learned-mix", type=float, default=0.7)
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the bench line, sweep the tree capacity t_e and then epsilon "
@@ -634,7 +651,8 @@ def main():
     replays = {"uniform": paths}
     if not args.no_learned:
         lpaths, lrn = learned_leg(G, p, args.steps, args.warmup, args.learned_paths,
-                                  args.learned_train_steps, 512, 3e-3, args.learned_mix)
+                                  args.learned_rows, args.learned_train_steps, args.learned_batch,
+                                  3e-3, args.learned_mix)
         replays["learned"] = lpaths
         um, lm = line["median_tts_ms"], lrn["median_tts_ms"]
         lrn["median_tts_ratio_learned_over_uniform"] = lm / um if (um and lm) else None
