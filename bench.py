@@ -379,10 +379,10 @@ def batched_leg(n_queries, batch_seed=3):
     B = Batch(planners)
     keys = ("status", "goal_id", "iterations", "n_nodes", "lanes_total", "valid_total")
 
-    def run():
+    def run(queue=False):
         t0 = time.perf_counter()
         reset()
-        res, bms = B.plan()
+        res, bms = B.plan(queue=queue)
         total = (time.perf_counter() - t0) * 1e3
         same = all(r[k] == s[k] for s, r in zip(seq, res) for k in keys)
         return dict(total_ms=total, batch_ms=bms,

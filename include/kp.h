@@ -482,6 +482,24 @@ kp_status kp_batch_get_config(const kp_batch* b, kp_batch_config* cfg);
  * time of the whole call.  Synchronous. */
 kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms);
 
+/* SWITCHED OFF: every call returns KP_E_ARG (its first GPU run did not
+ * finish and the cause is not yet known; see kp_batch_last_error).  Intended
+ * behaviour: the same loop as kp_batch_plan in one persistent launch over a
+ * device work queue (batched planning of Sec. IV-C's independent queries without a host
+ * round trip per iteration).  Each workgroup takes the next problem from the
+ * queue, largest node_cap first, and runs all of its iterations: expansion,
+ * UpdateEstimates and UpdateNodeSets (Algs. 2-4), separated by workgroup
+ * barriers, until the problem stops (goal, full tree, empty frontier, its
+ * max_iters, or its t_max_ms measured on the device wall clock from the
+ * moment a workgroup takes it).  Every problem's result and tree are exactly
+ * those of kp_plan on it alone.  results: n entries; elapsed_ms of entry i is
+ * the device time from the first workgroup's start to the end of problem i.
+ * *batch_ms (nullable): wall time of the whole call.  Problems with a learned
+ * proposal are refused (KP_E_ARG): use kp_batch_plan.  The batch
+ * configuration (iterations per read, graphs, grid caps) does not apply.
+ * Synchronous. */
+kp_status kp_batch_plan_queue(kp_batch* b, kp_plan_result* results, double* batch_ms);
+
 /* kp_reset of every problem of the batch (seeds: one per problem), enqueued
  * back to back with a single wait at the end. */
 kp_status kp_batch_reset(kp_batch* b, const uint64_t* seeds);

@@ -2,6 +2,7 @@
 // carving, the Alg. 1 loop, state copies and per-kernel timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -1373,6 +1374,12 @@ struct kp_batch {
   int dyn = 0, integ = 0;
   size_t lds_prop = 0;                // dynamic LDS of a propagate block: the largest problem's
   int region_blocks = 1;              // region blocks of a post grid row: the largest problem's
+  size_t lds_queue = 0;               // dynamic LDS of a k_plan_queue workgroup: the largest problem's
+  QueueCtl* q_ctl = nullptr;          // device: work queue of kp_batch_plan_queue
+  int32_t* q_order = nullptr;
+  QueueJob* q_jobs = nullptr;
+  unsigned long long* q_t_end = nullptr;
+  int32_t* q_ran = nullptr;
   int sym = 1;                        // every problem's state box is symmetric
   int learned = 0;                    // some problem has a learned proposal (set per plan)
   int prop_max = 1, node_max = 1;     // single-problem grid maxima
@@ -1385,6 +1392,30 @@ struct kp_batch {
 namespace {
 
 size_t batch_table_bytes(int32_t n) { return align_up((size_t)n * sizeof(void*), kAlign); }
+
+// Batch workspace: problem table, statuses, then the work queue of
+// kp_batch_plan_queue (control word, order, budgets, end ticks, iterations).
+struct BatchLayout {
+  size_t table, status, qctl, order, jobs, t_end, ran, total;
+};
+BatchLayout batch_layout(int32_t n) {
+  BatchLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, kAlign);
+    return o;
+  };
+  L.table = take((size_t)n * sizeof(void*));
+  L.status = take((size_t)n * sizeof(BatchStatus));
+  L.qctl = take(sizeof(QueueCtl));
+  L.order = take((size_t)n * sizeof(int32_t));
+  L.jobs = take((size_t)n * sizeof(QueueJob));
+  L.t_end = take((size_t)n * sizeof(unsigned long long));
+  L.ran = take((size_t)n * sizeof(int32_t));
+  L.total = off;
+  return L;
+}
 
 kp_status bfail(kp_batch* b, kp_status st, const std::string& msg) {
   if (b) b->err = msg;
@@ -1462,7 +1493,7 @@ extern "C" {
 
 size_t kp_batch_workspace_bytes(int32_t n) {
   if (n < 1) return 0;
-  return batch_table_bytes(n) + (size_t)n * sizeof(BatchStatus);
+  return batch_layout(n).total;
 }
 
 kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_workspace, size_t bytes,
@@ -1491,6 +1522,9 @@ kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_work
     const kp_problem* h = problems[i];
     if (h->lds_prop > b->lds_prop) b->lds_prop = h->lds_prop;
     if (post_region_blocks(h->R) > b->region_blocks) b->region_blocks = post_region_blocks(h->R);
+    const size_t lq =
+        queue_lds_bytes(h->desc.dynamics, h->desc.n_obstacles, (int)h->og.words.size());
+    if (lq > b->lds_queue) b->lds_queue = lq;
     if (!h->prm.box_sym) b->sym = 0;
     if (h->grid_post_max > node_max) node_max = h->grid_post_max;
     if (h->grid_commit_max > node_max) node_max = h->grid_commit_max;
@@ -1505,8 +1539,14 @@ kp_status kp_batch_create(kp_problem* const* problems, int32_t n, void* dev_work
   b->cfg.prop_blocks = prop_max;
   b->cfg.node_blocks = node_max;
   char* base = static_cast<char*>(dev_workspace);
-  b->table = reinterpret_cast<const Env**>(base);
-  b->st_dev = reinterpret_cast<BatchStatus*>(base + batch_table_bytes(n));
+  const BatchLayout BL = batch_layout(n);
+  b->table = reinterpret_cast<const Env**>(base + BL.table);
+  b->st_dev = reinterpret_cast<BatchStatus*>(base + BL.status);
+  b->q_ctl = reinterpret_cast<QueueCtl*>(base + BL.qctl);
+  b->q_order = reinterpret_cast<int32_t*>(base + BL.order);
+  b->q_jobs = reinterpret_cast<QueueJob*>(base + BL.jobs);
+  b->q_t_end = reinterpret_cast<unsigned long long*>(base + BL.t_end);
+  b->q_ran = reinterpret_cast<int32_t*>(base + BL.ran);
   std::vector<const Env*> tab((size_t)n);
   for (int i = 0; i < n; ++i) tab[(size_t)i] = problems[i]->env_dev;
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
@@ -1643,6 +1683,101 @@ kp_status kp_batch_plan(kp_batch* b, kp_plan_result* results, double* batch_ms) 
   if (e != hipSuccess) return bhip(b, e, "batch end");
   for (int i = 0; i < n; ++i) {
     kp_plan_result& r = results[i];
+    if (r.goal_id >= 0) {
+      int32_t len = 0;
+      if (kp_get_path(b->P[(size_t)i], r.goal_id, nullptr, 0, &len) == KP_OK) r.path_len = len;
+    }
+  }
+  if (batch_ms) *batch_ms = total;
+  return KP_OK;
+}
+
+// Switched off: the first GPU run of the persistent queue kernel did not
+// finish (a batch of six small double-integrator problems), and no cause has
+// been shown yet; every call is refused until one is.
+constexpr bool kQueueEnabled = false;
+
+kp_status kp_batch_plan_queue(kp_batch* b, kp_plan_result* results, double* batch_ms) {
+  if (!b || !results) return KP_E_ARG;
+  if (!kQueueEnabled)
+    return bfail(b, KP_E_ARG,
+                 "kp_batch_plan_queue is switched off: its first GPU run did not finish and the "
+                 "cause is not yet known; use kp_batch_plan");
+  const int n = (int)b->P.size();
+  for (int i = 0; i < n; ++i) {
+    if (b->P[i]->stage != 0)
+      return bfail(b, KP_E_ORDER, "problem " + std::to_string(i) + " is in the middle of an iteration");
+    if (b->P[i]->prm.mix_thr != 0ull)
+      return bfail(b, KP_E_ARG, "kp_batch_plan_queue: problem " + std::to_string(i) +
+                                    " has a learned proposal (use kp_batch_plan)");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipStreamSynchronize(b->user_stream);
+  if (e != hipSuccess) return bhip(b, e, "problem stream");
+  int dev = 0, rate_khz = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess || rate_khz <= 0) return bhip(b, e, "wall clock rate");
+  // largest capacities first, so that the longest queries start at once
+  std::vector<int32_t> order((size_t)n);
+  for (int i = 0; i < n; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return b->P[(size_t)x]->desc.node_cap > b->P[(size_t)y]->desc.node_cap;
+  });
+  std::vector<QueueJob> jobs((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const kp_problem_desc& d = b->P[(size_t)i]->desc;
+    jobs[(size_t)i].iters = d.max_iters;
+    jobs[(size_t)i].pad = 0;
+    const double t = (double)d.t_max_ms * (double)rate_khz;
+    jobs[(size_t)i].ticks = (t > 0.0 && t < 1.8e19) ? (unsigned long long)t : 0ull;
+  }
+  QueueCtl qc{};
+  qc.head = 0u;
+  qc.t_start = ~0ull;
+  e = hipMemcpyAsync(b->q_ctl, &qc, sizeof qc, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->q_order, order.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->q_jobs, jobs.data(), (size_t)n * sizeof(QueueJob), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e != hipSuccess) return bhip(b, e, "queue upload");
+  for (int i = 0; i < n; ++i) b->P[(size_t)i]->ctl_fresh = false;
+  int bq = 1;
+  occupancy_queue(b->dyn, b->integ, b->sym, b->lds_queue, &bq);
+  const int slots = bq * b->P[0]->cu_count;
+  e = launch_plan_queue(b->dyn, b->integ, b->sym, b->table, b->q_order, b->q_jobs, n, b->q_ctl,
+                        b->q_t_end, b->q_ran, b->lds_queue, n < slots ? n : slots, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "queue launch");
+  kp_status st = batch_status(b);
+  if (st != KP_OK) return st;
+  const double total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  std::vector<unsigned long long> t_end((size_t)n);
+  std::vector<int32_t> ran((size_t)n);
+  e = hipMemcpyAsync(&qc, b->q_ctl, sizeof qc, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(t_end.data(), b->q_t_end, (size_t)n * 8, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ran.data(), b->q_ran, (size_t)n * 4, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bhip(b, e, "queue results");
+  for (int i = 0; i < n; ++i) {
+    const BatchStatus& s = b->st_host[i];
+    if (s.err) return bfail(b, KP_E_DEVICE, "problem " + std::to_string(i) + ": device check failed");
+    kp_plan_result& r = results[i];
+    std::memset(&r, 0, sizeof(r));
+    r.status = s.done ? s.done : KP_TIMEOUT;
+    r.goal_id = (s.goal_id == kNoGoal) ? -1 : s.goal_id;
+    r.iterations = ran[(size_t)i];
+    r.n_nodes = s.N;
+    // the problem's end on the device clock, from the first workgroup's start
+    r.elapsed_ms = (t_end[(size_t)i] >= qc.t_start)
+                       ? (double)(t_end[(size_t)i] - qc.t_start) / (double)rate_khz
+                       : 0.0;
+    r.lanes_total = s.lanes_total;
+    r.valid_total = s.valid_total;
     if (r.goal_id >= 0) {
       int32_t len = 0;
       if (kp_get_path(b->P[(size_t)i], r.goal_id, nullptr, 0, &len) == KP_OK) r.path_len = len;

@@ -216,6 +216,29 @@ hipError_t launch_propagate_batch(int dyn, int integ, int sym, const Env* const*
 hipError_t launch_post_batch(const Env* const* envs, int n, int n_region, int n_commit,
                              int n_nodes, hipStream_t s);
 hipError_t launch_batch_status(const Env* const* envs, int n, BatchStatus* out, hipStream_t s);
+
+// batched planning in one launch over a device work queue (k_plan_queue):
+// per problem its iteration budget and its time budget in wall-clock ticks
+// (0: none); the queue head and the earliest block start; then, written by
+// the kernel, each problem's end tick and iterations run
+constexpr int kQueueBlock = 1024;
+struct QueueJob {
+  int32_t iters;
+  int32_t pad;
+  unsigned long long ticks;
+};
+struct QueueCtl {
+  uint32_t head;
+  uint32_t pad;
+  unsigned long long t_start;
+};
+hipError_t launch_plan_queue(int dyn, int integ, int sym, const Env* const* envs,
+                             const int32_t* order, const QueueJob* jobs, int n, QueueCtl* qc,
+                             unsigned long long* t_end, int32_t* ran, size_t lds, int grid,
+                             hipStream_t s);
+// dynamic LDS of one problem in k_plan_queue (propagate body at kQueueBlock threads)
+size_t queue_lds_bytes(int dyn, int n_obs, int grid_words);
+int occupancy_queue(int dyn, int integ, int sym, size_t lds, int* blocks_per_cu);
 hipError_t launch_set_done(const Env* env, int32_t code, hipStream_t s);
 hipError_t launch_set_ctl(const Env* env, int32_t N, int32_t it, hipStream_t s);
 

@@ -770,10 +770,11 @@ constexpr int kBoundsFloats = 2 * 12;   // state box (lo[12], hi[12]) at the sta
 // LDS of a propagate block.  Quadcopter: state box, obstacle table, per-wave
 // candidate lists.  Double integrator: state box, obstacle table, and the
 // obstacle grid (grid_words u16 words: cell offsets, then obstacle ids).
-constexpr size_t prop_lds_bytes(int dyn, int n_obs, int grid_words) {
+constexpr size_t prop_lds_bytes(int dyn, int n_obs, int grid_words, int waves = 0) {
   return kBoundsFloats * sizeof(float) + (size_t)(n_obs + 1) * 6 * sizeof(float) +
-         (grid_words > 0 ? (size_t)((grid_words + 1) & ~1) * 2
-                         : (size_t)(prop_block(dyn) / 64) * wave_lds_bytes(n_obs));
+         (grid_words > 0
+              ? (size_t)((grid_words + 1) & ~1) * 2
+              : (size_t)(waves > 0 ? waves : prop_block(dyn) / 64) * wave_lds_bytes(n_obs));
 }
 // gfx950 gives a workgroup up to 160 KiB of LDS; a double-integrator block
 // stays at or below 80 KiB, so that two of them share a compute unit
@@ -785,6 +786,11 @@ static_assert(prop_lds_bytes(KP_DYN_DI6, KP_MAX_OBSTACLES, kGridMaxWords) <= 82 
 size_t propagate_lds_bytes(int dyn, int n_obs, int grid_words) {
   return prop_lds_bytes(dyn, n_obs, grid_words);
 }
+size_t queue_lds_bytes(int dyn, int n_obs, int grid_words) {
+  return prop_lds_bytes(dyn, n_obs, grid_words, kQueueBlock / 64);
+}
+static_assert(prop_lds_bytes(KP_DYN_QUAD12, KP_MAX_OBSTACLES, 0, kQueueBlock / 64) <= 150 * 1024,
+              "queue kernel LDS (with the static arrays of the post body) above 160 KiB");
 
 
 // Separation of two closed boxes: the largest gap along any axis between a
@@ -838,13 +844,16 @@ __device__ __forceinline__ int clamp_cell(float t, int ncell) {
   return c < 0 ? 0 : (c > ncell - 1 ? ncell - 1 : c);
 }
 
-template <int DYN, int INTEG, bool SYM>
-__device__ __forceinline__ void propagate_body(const Env* __restrict__ env, TraceRec* trace) {
+// One propagate launch's work for block vb of a grid of vg blocks of PB
+// threads (a kernel's own blockIdx.x and gridDim.x, or block 0 of 1 when one
+// workgroup runs a whole query).
+template <int DYN, int INTEG, bool SYM, int PB>
+__device__ __forceinline__ void propagate_body(const Env* __restrict__ env, TraceRec* trace,
+                                               uint32_t vb, uint32_t vg) {
   const Params& p = env->p;
   const Dev& d = env->d;
   constexpr int n = Dim<DYN>::n;
   constexpr int m = Dim<DYN>::m;
-  constexpr int PB = prop_block(DYN);
   constexpr int kWaves = PB / 64;
   extern __shared__ float lds[];
   Ctl* c = d.ctl;
@@ -856,7 +865,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   // the node-set ticket counter, last used by the previous iteration's node
   // pass, starts from zero for the next one; the iteration's sizes are
   // copied for k_post
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vb == 0 && threadIdx.x == 0) {
     c->tk_nodes = 0u;
     c->rg_max = 0ull;
     c->rg_sum = 0ull;
@@ -897,18 +906,18 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   // per-wave running totals (wave-uniform), flushed once per block
   unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0, t_checked = 0;
 
-  // A wave's first tile is wave * gridDim.x + block: the first gridDim.x
-  // tiles go to wave 0 of every block, the next ones to wave 1, and so on, so
+  // A wave's first tile is wave * vg + block: the first vg tiles go to wave
+  // 0 of every block, the next ones to wave 1, and so on, so
   // that a launch with fewer tiles than the grid has waves runs one wave per
   // block, spread over the compute units.  Later tiles come from per-group
   // ticket counters: group q (block index mod ng) hands out tiles
   // nwaves + ng * k + q.  No burst of tickets at launch, and each counter
   // sees about 1/ng of the requests.  A block whose first tiles are all past
   // the end has nothing to do (an oversized grid costs no atomics).
-  const uint32_t nwaves = gridDim.x * kWaves;
-  const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
-  const uint32_t grp = blockIdx.x % ng;
-  if (blockIdx.x >= ntiles) return;
+  const uint32_t nwaves = vg * kWaves;
+  const uint32_t ng = vg < (uint32_t)kGroups ? vg : (uint32_t)kGroups;
+  const uint32_t grp = vb % ng;
+  if (vb >= ntiles) return;
   for (int k = threadIdx.x; k < 6 * n_obs; k += PB) {
     const int ob = k / 6, comp = k - 6 * ob;
     otab[k] = d.obs[(size_t)comp * n_obs + ob];
@@ -928,7 +937,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   }
   __syncthreads();
 
-  uint32_t next = (uint32_t)wave * gridDim.x + blockIdx.x;
+  uint32_t next = (uint32_t)wave * vg + vb;
   for (;;) {
     const uint32_t tile = next;
     if (tile >= ntiles) break;
@@ -1271,7 +1280,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     for (int w = 0; w < kWaves; ++w)
       for (int q = 0; q < 5; ++q) a[q] += s_tot[w][q];
     if (a[0]) {
-      TotLine* t = &c->tot[blockIdx.x % kGroups];
+      TotLine* t = &c->tot[vb % kGroups];
       atomicAdd(&t->lanes, a[0]);
       atomicAdd(&t->valid, a[1]);
       atomicAdd(&t->steps, a[2]);
@@ -1751,7 +1760,12 @@ __device__ __forceinline__ void wait_region(Ctl* c, uint32_t epoch) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
+// One post launch's work for block vb of a grid row of vg blocks: nrb
+// region blocks, nc commit blocks, then node-set blocks.  solo: one
+// workgroup plays the three roles in turn (vb = 0, 1, 2 of vg = 3, nc = 1),
+// with a one-block region pass over every region.
+__device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, uint32_t vb,
+                                          uint32_t vg, bool solo) {
   static_assert(kCommitBlock == kNodeBlock, "one block shape for every role");
   static_assert(kNodesPerThread == 4, "one flag word and one uint4 of cells per thread");
   const Params& p = env->p;
@@ -1772,24 +1786,28 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
   __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
 
   // grid row: nrb region blocks, nc commit blocks, then node-set blocks
-  const uint32_t nrb = (uint32_t)post_region_blocks(p.R);
-  if (blockIdx.x < nrb) {
+  const uint32_t nrb = solo ? 1u : (uint32_t)post_region_blocks(p.R);
+  if (vb < nrb) {
     // ---- UpdateEstimates; and the counters of the next expansion ----
-    if (blockIdx.x == 0) {
+    if (vb == 0) {
       uint32_t* nxt = d.ssum + (size_t)((it + 1u) & 1u) * (size_t)d.nchunk;
       for (int j = threadIdx.x; j < d.nchunk; j += kCommitBlock) nxt[j] = 0u;
       if (threadIdx.x < (unsigned)kGroups) c->tkp[threadIdx.x].v = 0u;
     }
-    if (!done) {
-      region_part<kCommitBlock>(env, blockIdx.x, nrb, epoch);
-    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
-      __threadfence();
-      __hip_atomic_store(&c->region_ready, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!done && !solo) {
+      region_part<kCommitBlock>(env, vb, nrb, epoch);
+    } else if (vb == 0) {
+      if (!done) region_body<kCommitBlock>(env);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(&c->region_ready, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     return;
   }
-  if (blockIdx.x < nrb + (uint32_t)nc) {
-    const uint32_t ci = blockIdx.x - nrb;
+  if (vb < nrb + (uint32_t)nc) {
+    const uint32_t ci = vb - nrb;
     // ---- V_U ----
     CommitCtx k;
     k.N = N;
@@ -1828,8 +1846,8 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
     return;
   }
   // ---- UpdateNodeSets over the old nodes ----
-  const uint32_t nb = gridDim.x - nrb - (uint32_t)nc;
-  const uint32_t bi = blockIdx.x - nrb - (uint32_t)nc;
+  const uint32_t nb = vg - nrb - (uint32_t)nc;
+  const uint32_t bi = vb - nrb - (uint32_t)nc;
   const bool goal = c->goal_hit != 0u;
   const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
   const bool by_ticket = ntiles > nb;
@@ -1931,23 +1949,86 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc) {
 template <int DYN, int INTEG, bool SYM>
 __global__ __launch_bounds__(prop_block(DYN)) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(
     const Env* __restrict__ env, TraceRec* trace) {
-  propagate_body<DYN, INTEG, SYM>(env, trace);
+  propagate_body<DYN, INTEG, SYM, prop_block(DYN)>(env, trace, blockIdx.x, gridDim.x);
 }
 template <int DYN, int INTEG, bool SYM>
 __global__ __launch_bounds__(prop_block(DYN)) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate_batch(
     const Env* const* __restrict__ envs) {
   const Env* env = envs[blockIdx.y];
-  propagate_body<DYN, INTEG, SYM>(env, env->d.trace);
+  propagate_body<DYN, INTEG, SYM, prop_block(DYN)>(env, env->d.trace, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
-  post_body(env, nc);
+  post_body(env, nc, blockIdx.x, gridDim.x, false);
 }
 __global__ __launch_bounds__(kCommitBlock) void k_post_batch(const Env* const* __restrict__ envs, int nc) {
-  post_body(envs[blockIdx.y], nc);
+  post_body(envs[blockIdx.y], nc, blockIdx.x, gridDim.x, false);
 }
 
 // compact status of every problem of a batch, for one host read
+
+// ---------------------------------------------------------------------------
+// k_plan_queue: batched planning in one launch over a device work queue.
+// Each workgroup takes the next problem (order[q] for q = 0, 1, ... from the
+// queue head) and runs Alg. 1's loop for it until it stops: goal, full tree
+// or empty frontier (done), its iteration budget, or its time budget on the
+// device wall clock.  One iteration is the propagate body, then the region
+// pass, the V_U commit and the node-set pass, one after the other, with one
+// workgroup playing every block of the two-launch grids; the kernels' results
+// do not depend on grid shapes, so each problem ends exactly as kp_plan
+// leaves it.  Between phases every wave fences at device scope (the phases
+// read what device-scope atomics of the previous one wrote) and the
+// workgroup synchronises.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void queue_phase_end() {
+  __threadfence();
+  __syncthreads();
+}
+
+template <int DYN, int INTEG, bool SYM>
+__global__ __launch_bounds__(kQueueBlock) void k_plan_queue(
+    const Env* const* __restrict__ envs, const int32_t* __restrict__ order,
+    const QueueJob* __restrict__ jobs, int n, QueueCtl* qc, unsigned long long* __restrict__ t_end,
+    int32_t* __restrict__ ran) {
+  __shared__ int s_q, s_go;
+  if (threadIdx.x == 0) atomicMin(&qc->t_start, (unsigned long long)wall_clock64());
+  for (;;) {
+    if (threadIdx.x == 0) s_q = (int)atomicAdd(&qc->head, 1u);
+    __syncthreads();
+    const int q = s_q;
+    __syncthreads();
+    if (q >= n) return;
+    const int i = order[q];
+    const Env* env = envs[i];
+    Ctl* c = env->d.ctl;
+    const int32_t iters = jobs[i].iters;
+    const unsigned long long ticks = jobs[i].ticks;
+    const unsigned long long t0 = (unsigned long long)wall_clock64();
+    int32_t k = 0;
+    for (;;) {
+      if (threadIdx.x == 0) {
+        // done is written by this workgroup's thread 0 (the node pass's finaliser)
+        bool go = k < iters && c->done == 0;
+        if (go && ticks != 0ull && (unsigned long long)wall_clock64() - t0 >= ticks) go = false;
+        s_go = go ? 1 : 0;
+      }
+      __syncthreads();
+      if (!s_go) break;
+      propagate_body<DYN, INTEG, SYM, kQueueBlock>(env, env->d.trace, 0u, 1u);
+      queue_phase_end();
+      for (uint32_t role = 0; role < 3u; ++role) {
+        post_body(env, 1, role, 3u, true);
+        queue_phase_end();
+      }
+      ++k;
+    }
+    if (threadIdx.x == 0) {
+      ran[i] = k;
+      t_end[i] = (unsigned long long)wall_clock64();
+    }
+  }
+}
+
 __global__ void k_batch_status(const Env* const* __restrict__ envs, int n, BatchStatus* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -2126,6 +2207,37 @@ hipError_t launch_post_batch(const Env* const* envs, int n, int n_region, int n_
   return hipGetLastError();
 }
 
+template <int DYN, int INTEG, bool SYM>
+static hipError_t launch_queue_t(const Env* const* envs, const int32_t* order, const QueueJob* jobs,
+                                 int n, QueueCtl* qc, unsigned long long* t_end, int32_t* ran,
+                                 size_t lds, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_plan_queue<DYN, INTEG, SYM>), dim3(grid), dim3(kQueueBlock), (uint32_t)lds,
+                     s, envs, order, jobs, n, qc, t_end, ran);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_queue(int dyn, int integ, int sym, const Env* const* envs,
+                             const int32_t* order, const QueueJob* jobs, int n, QueueCtl* qc,
+                             unsigned long long* t_end, int32_t* ran, size_t lds, int grid,
+                             hipStream_t s) {
+  if (grid < 1) grid = 1;
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
+    return launch_queue_t<KP_DYN_DI6, KP_INT_EULER, false>(envs, order, jobs, n, qc, t_end, ran, lds,
+                                                           grid, s);
+  if (dyn == KP_DYN_DI6)
+    return launch_queue_t<KP_DYN_DI6, KP_INT_RK4, false>(envs, order, jobs, n, qc, t_end, ran, lds,
+                                                         grid, s);
+  if (integ == KP_INT_EULER)
+    return sym ? launch_queue_t<KP_DYN_QUAD12, KP_INT_EULER, true>(envs, order, jobs, n, qc, t_end,
+                                                                   ran, lds, grid, s)
+               : launch_queue_t<KP_DYN_QUAD12, KP_INT_EULER, false>(envs, order, jobs, n, qc, t_end,
+                                                                    ran, lds, grid, s);
+  return sym ? launch_queue_t<KP_DYN_QUAD12, KP_INT_RK4, true>(envs, order, jobs, n, qc, t_end, ran,
+                                                               lds, grid, s)
+             : launch_queue_t<KP_DYN_QUAD12, KP_INT_RK4, false>(envs, order, jobs, n, qc, t_end, ran,
+                                                                lds, grid, s);
+}
+
 hipError_t launch_batch_status(const Env* const* envs, int n, BatchStatus* out, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_status, dim3((n + 255) / 256), dim3(256), 0, s, envs, n, out);
   return hipGetLastError();
@@ -2160,8 +2272,13 @@ static hipError_t allow_lds_t() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<DYN, INTEG, SYM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate_batch<DYN, INTEG, SYM>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate_batch<DYN, INTEG, SYM>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  const int qbytes = (int)prop_lds_bytes(DYN, KP_MAX_OBSTACLES,
+                                         DYN == KP_DYN_DI6 ? kGridMaxWords : 0, kQueueBlock / 64);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plan_queue<DYN, INTEG, SYM>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, qbytes);
 }
 static hipError_t allow_lds_all() {
   static const hipError_t once = [] {
@@ -2209,6 +2326,32 @@ int occupancy_commit(int* blocks_per_cu) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_commit, kCommitBlock, 0) != hipSuccess)
     nb = 1;
   if (nb < 1) nb = 1;
+  *blocks_per_cu = nb;
+  return nb;
+}
+
+template <int DYN, int INTEG, bool SYM>
+static int occ_queue_t(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_plan_queue<DYN, INTEG, SYM>, kQueueBlock,
+                                                    lds) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int occupancy_queue(int dyn, int integ, int sym, size_t lds, int* blocks_per_cu) {
+  int nb;
+  if (allow_lds_all() != hipSuccess) (void)hipGetLastError();
+  if (dyn == KP_DYN_DI6 && integ == KP_INT_EULER)
+    nb = occ_queue_t<KP_DYN_DI6, KP_INT_EULER, false>(lds);
+  else if (dyn == KP_DYN_DI6)
+    nb = occ_queue_t<KP_DYN_DI6, KP_INT_RK4, false>(lds);
+  else if (integ == KP_INT_EULER)
+    nb = sym ? occ_queue_t<KP_DYN_QUAD12, KP_INT_EULER, true>(lds)
+              : occ_queue_t<KP_DYN_QUAD12, KP_INT_EULER, false>(lds);
+  else
+    nb = sym ? occ_queue_t<KP_DYN_QUAD12, KP_INT_RK4, true>(lds)
+              : occ_queue_t<KP_DYN_QUAD12, KP_INT_RK4, false>(lds);
   *blocks_per_cu = nb;
   return nb;
 }

@@ -35,7 +35,7 @@ EXPORTED = [
     "kp_batch_workspace_bytes", "kp_batch_create", "kp_batch_set_config", "kp_batch_get_config",
     "kp_batch_plan", "kp_batch_destroy", "kp_batch_last_error", "kp_batch_reset",
     "kp_transfer_tree", "kp_set_trace", "kp_set_launch_limits", "kp_get_trajectory",
-    "kp_log_tree_edges", "kp_mlp_train_noalloc",
+    "kp_log_tree_edges", "kp_mlp_train_noalloc", "kp_batch_plan_queue",
 ]
 
 
@@ -176,12 +176,13 @@ def load_library():
     L.kp_batch_set_config.argtypes = [P, C.POINTER(BatchConfig)]
     L.kp_batch_get_config.argtypes = [P, C.POINTER(BatchConfig)]
     L.kp_batch_plan.argtypes = [P, P, C.POINTER(C.c_double)]
+    L.kp_batch_plan_queue.argtypes = [P, P, C.POINTER(C.c_double)]
     L.kp_batch_destroy.argtypes = [P]
     L.kp_batch_reset.argtypes = [P, P]
     L.kp_transfer_tree.argtypes = [P, P]
     L.kp_transfer_tree.restype = C.c_int
     for name in ("kp_batch_create", "kp_batch_set_config", "kp_batch_get_config", "kp_batch_plan",
-                 "kp_batch_destroy", "kp_batch_reset"):
+                 "kp_batch_plan_queue", "kp_batch_destroy", "kp_batch_reset"):
         getattr(L, name).restype = C.c_int
     L.kp_batch_last_error.argtypes = [P]
     L.kp_batch_last_error.restype = C.c_char_p
@@ -652,12 +653,15 @@ class Batch:
             raise KPError(E_ARG, "one seed per problem")
         self._check(self.lib.kp_batch_reset(self.h, _ptr(a)))
 
-    def plan(self):
-        """Returns (per-problem result dicts, batch wall time in ms)."""
+    def plan(self, queue: bool = False):
+        """Returns (per-problem result dicts, batch wall time in ms).
+        queue=True: one persistent launch over a device work queue
+        (kp_batch_plan_queue); otherwise kp_batch_plan."""
         n = len(self.planners)
         res = (PlanResult * n)()
         ms = C.c_double(0.0)
-        self._check(self.lib.kp_batch_plan(self.h, res, C.byref(ms)))
+        fn = self.lib.kp_batch_plan_queue if queue else self.lib.kp_batch_plan
+        self._check(fn(self.h, res, C.byref(ms)))
         out = [dict(status=r.status, goal_id=r.goal_id, iterations=r.iterations, n_nodes=r.n_nodes,
                     path_len=r.path_len, elapsed_ms=r.elapsed_ms, lanes_total=int(r.lanes_total),
                     valid_total=int(r.valid_total)) for r in res]

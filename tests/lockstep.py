@@ -505,11 +505,13 @@ def run_lockstep_plan(p, iterations, device="cuda:0", reload=False, launch_limit
     return rep
 
 
-def run_lockstep_batch(problems, iterations, config=None, device="cuda:0"):
+def run_lockstep_batch(problems, iterations, config=None, device="cuda:0", queue=False):
     """Lock-step of batched planning: every problem of one batch against its
     own oracle.  Each kp_batch_plan call runs exactly one iteration of every
     problem (each problem's iteration budget is 1), in the batched launches
-    (one grid row per problem); every problem writes its own per-lane trace.
+    (one grid row per problem), or with queue=True in one persistent launch
+    (kp_batch_plan_queue, one workgroup per problem); every problem writes its
+    own per-lane trace.
     Problems that stop (goal, full tree) drop out.  Returns one Report per
     problem."""
     from paper_2409_06807_amd import Planner, Batch
@@ -553,7 +555,7 @@ def run_lockstep_batch(problems, iterations, config=None, device="cuda:0"):
             recs[i] = W.expand_all()
         if not live:
             break
-        res, _ = B.plan()
+        res, _ = B.plan(queue=queue)
         torch.cuda.synchronize()
         for i in list(live):
             W, G, rep, p = Ws[i], Gs[i], reps[i], problems[i]

@@ -217,3 +217,119 @@ def test_batch_lockstep_against_oracle(dyn, config):
     assert all(rep.ok for rep in reps), [rep.summary() for rep in reps if not rep.ok][:3]
     assert all(rep.iterations >= 3 or rep.final_status in (oracle.TREE_FULL, oracle.SOLVED)
                for rep in reps)
+
+
+# ---------------------------------------------------------------------------
+# one persistent launch over a device work queue (kp_batch_plan_queue)
+# ---------------------------------------------------------------------------
+QUEUE_OFF = ("kp_batch_plan_queue is switched off: its first GPU run (the six small "
+             "double-integrator problems below) did not finish and the cause is not yet known")
+
+
+def test_queue_is_refused_while_switched_off():
+    from paper_2409_06807_amd import Planner, Batch, KPError, E_ARG
+    _say("queue refused while switched off")
+    planners = [Planner(p) for p in small_batch()[:2]]
+    B = Batch(planners)
+    with pytest.raises(KPError) as ei:
+        B.plan(queue=True)
+    assert ei.value.code == E_ARG
+    B.close()
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+def test_queue_equals_single_planner():
+    from paper_2409_06807_amd import Planner, Batch
+    _say("queue vs single")
+    ps = small_batch()
+    ref = alone(ps)
+    planners = [Planner(p) for p in ps]
+    B = Batch(planners)
+    res, ms = B.plan(queue=True)
+    assert ms > 0 and all(0.0 <= r["elapsed_ms"] <= ms for r in res)
+    check_same(ref, planners, res)
+    # again after a batch reset, and then through the two-launch path
+    B.reset([p["seed"] for p in ps])
+    res2, _ = B.plan(queue=True)
+    check_same(ref, planners, res2)
+    B.reset([p["seed"] for p in ps])
+    res3, _ = B.plan()
+    check_same(ref, planners, res3)
+    B.close()
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+def test_queue_quad_and_grid_problems_equal_single():
+    from paper_2409_06807_amd import Planner, Batch
+    _say("queue quad batch")
+    ps = [problem_small_quad(seed=s, scene_seed=40 + s, n_obs=o, cap=c)
+          for c, o, s in [(8192, 60, 0), (3000, 20, 1), (12000, 90, 2)]]
+    ref = alone(ps)
+    planners = [Planner(p) for p in ps]
+    B = Batch(planners)
+    res, _ = B.plan(queue=True)
+    check_same(ref, planners, res)
+    B.close()
+    _say("queue DI batch with obstacle grids")
+    ps = problem_batch(n=6, batch_seed=9, cap_range=(16384, 40000), obs_range=(300, 2000))
+    ref = alone(ps)
+    planners = [Planner(p) for p in ps]
+    B = Batch(planners)
+    res, _ = B.plan(queue=True)
+    check_same(ref, planners, res)
+    B.close()
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+def test_queue_budget_stops_one_problem_and_it_resumes():
+    from paper_2409_06807_amd import Planner, Batch
+    _say("queue budget")
+    ps = small_batch()[:3]
+    ps[1] = dict(ps[1], max_iters=3)
+    ref = alone(ps)
+    assert ref[1][0]["status"] == oracle.TIMEOUT and ref[1][0]["iterations"] == 3
+    planners = [Planner(p) for p in ps]
+    B = Batch(planners)
+    res, _ = B.plan(queue=True)
+    check_same(ref, planners, res)
+    G1 = Planner(ps[1])
+    G1.plan()
+    r_single = G1.plan()
+    r_batch = planners[1].plan()
+    for k in KEYS:
+        assert r_single[k] == r_batch[k], k
+    B.close()
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+def test_queue_refuses_learned_proposals():
+    import paper_2409_06807_amd as kp
+    from paper_2409_06807_amd import Planner, Batch, KPError, E_ARG
+    import torch
+    from workloads import mlp_inputs
+    _say("queue refuses learned proposals")
+    ps = small_batch()[:2]
+    planners = [Planner(p) for p in ps]
+    params = torch.tensor(mlp_inputs.params(31), dtype=torch.float32, device="cuda:0")
+    planners[1].set_proposal(kp.mlp_pack(params), 0.5)
+    B = Batch(planners)
+    with pytest.raises(KPError) as ei:
+        B.plan(queue=True)
+    assert ei.value.code == E_ARG
+    B.close()
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+@pytest.mark.parametrize("dyn", ["di", "quad"])
+def test_queue_lockstep_against_oracle(dyn):
+    """The persistent queue kernel against the oracle, one iteration of every
+    problem per call, lane by lane and in every integer field."""
+    import lockstep
+    ps = _batch_lockstep_problems(dyn)
+    _say(f"queue lock-step {dyn} obstacles={[len(p['obstacles']) for p in ps]}")
+    reps = lockstep.run_lockstep_batch(ps, iterations=12 if dyn == "di" else 8, queue=True)
+    for k, rep in enumerate(reps):
+        print(f"problem {k}: {rep.summary()}", flush=True)
+    assert all(rep.ok for rep in reps), [rep.summary() for rep in reps if not rep.ok][:3]
+    assert all(rep.iterations >= 3 or rep.final_status in (oracle.TREE_FULL, oracle.SOLVED)
+               for rep in reps)
