@@ -76,16 +76,41 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str = "k_propagate"):
+    """Scaled HBM bytes per launch of `kernel` on `workload` from the counter
+    record, or None when the record is missing or the kernel sources changed."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    entry = rec.get("workloads", {}).get(workload)
-    if entry is None or rec.get("kernel_source_sha256") != kernel_source_hash():
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
         return None
+    entry = rec.get("workloads", {}).get(workload)
+    if entry is None:
+        return None
+    if kernel != "k_propagate":
+        entry = entry.get("other_kernels", {}).get(kernel)
+        if entry is None:
+            return None
     return entry["bytes_per_launch"]
+
+
+PEAK_HBM_GBS = 8000.0
+
+
+def post_hbm(workload: str, kt):
+    """HBM entry of k_post (commit, estimates and node sets: the region and
+    tree phases): counter bytes per launch over the live average launch."""
+    n, ms = kt["post"]
+    b = measured_traffic(workload, "k_post")
+    if not n or b is None:
+        return {"kernel": "k_post", "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": None, "traffic": b,
+                "avg_launch_ms": ms / n if n else None}
+    gbs = b / (ms / n * 1e-3) / 1e9
+    return {"kernel": "k_post", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": b, "avg_launch_ms": ms / n}
 
 
 def gpu_workload(name: str, seed: int = 0):
@@ -644,6 +669,7 @@ def main():
             "checked_steps_per_lane": checked_tot / lanes_prof if lanes_prof else None,
             "box_tests_per_checked_step": box_tot / checked_tot if checked_tot else None,
         },
+        "post_hbm": post_hbm(p["name"], kt),
         "grid": {"propagate": G.stats()["grid_propagate"], "nodes": G.stats()["grid_nodes"]},
         "kernel_ms": {k: v[1] for k, v in kt.items()},
         "kernel_launches": {k: v[0] for k, v in kt.items()},

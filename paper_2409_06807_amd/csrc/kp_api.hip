@@ -507,6 +507,13 @@ int cap_prop(const kp_problem* h) {
 int cap_node(const kp_problem* h) {
   return (h->lim_node > 0 && h->lim_node < h->grid_node_max) ? h->lim_node : h->grid_node_max;
 }
+// a propagate grid of g blocks rounded up to a multiple of 8 when g >= 8,
+// not above gmax rounded down to one
+int xcd_grid(int g, int gmax) {
+  if (g < 8) return g;
+  const int up = (g + 7) & ~7, cap = gmax & ~7;
+  return up <= cap ? up : (cap >= 8 ? cap : g);
+}
 int cap_post_nodes(const kp_problem* h) {
   return (h->lim_node > 0 && h->lim_node < h->grid_post_max) ? h->lim_node : h->grid_post_max;
 }
@@ -533,11 +540,13 @@ kp_status do_frontier(kp_problem* h, long long n_nodes) {
 kp_status do_propagate(kp_problem* h, TraceRec* trace, long long lanes_ub, bool with_commit) {
   h->ctl_fresh = false;
   // one block per 64-lane tile up to the cap (the kernel hands the first
-  // tiles to wave 0 of every block)
+  // tiles to wave 0 of every block), a multiple of 8 blocks from 8 on (the
+  // kernel gives each XCD a contiguous range of them)
   long long tiles = (lanes_ub + 63) / 64;
   const int gmax = cap_prop(h);
   int grid = (int)(tiles < gmax ? tiles : gmax);
   if (grid < 1) grid = 1;
+  grid = xcd_grid(grid, gmax);
   hipError_t e = launch_propagate(h->desc.dynamics, h->desc.integrator, h->prm.box_sym, h->env_dev,
                                   h->lds_prop, trace, grid, h->stream, prof_slot(h, 0));
   if (e != hipSuccess) return hip_fail(h, e, "propagate launch");
@@ -1444,7 +1453,9 @@ hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_
     if (e != hipSuccess) return e;
   }
   long long t = (lanes_ub + 63) / 64;
-  const int gp = (int)(t < b->cfg.prop_blocks ? t : b->cfg.prop_blocks);
+  int gp = (int)(t < b->cfg.prop_blocks ? t : b->cfg.prop_blocks);
+  if (gp < 1) gp = 1;
+  gp = xcd_grid(gp, b->cfg.prop_blocks);
   t = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   const int nc = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
   t = (old_nodes_ub + kNodeTile - 1) / kNodeTile;

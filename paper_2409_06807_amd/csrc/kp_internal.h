@@ -9,9 +9,10 @@
 
 namespace kp {
 
-// threads per propagate block: 8 waves for the double integrator (two blocks
-// of up to 80 KiB of LDS per compute unit), 4 for the quadcopter
-__host__ __device__ constexpr int prop_block(int dyn) { return dyn == KP_DYN_DI6 ? 512 : 256; }
+// threads per propagate block: 16 waves, one block per compute unit at 4
+// waves per SIMD.  Every block stages the obstacle table (and the grid) in
+// its LDS, so fewer, larger blocks read that shared input fewer times.
+__host__ __device__ constexpr int prop_block(int) { return 1024; }
 // largest obstacle grid (u16 words: cell offsets and obstacle ids) a
 // double-integrator block stages in LDS
 constexpr int kGridMaxWords = 16384;

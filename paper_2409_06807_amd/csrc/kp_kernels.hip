@@ -776,13 +776,11 @@ constexpr size_t prop_lds_bytes(int dyn, int n_obs, int grid_words, int waves = 
               ? (size_t)((grid_words + 1) & ~1) * 2
               : (size_t)(waves > 0 ? waves : prop_block(dyn) / 64) * wave_lds_bytes(n_obs));
 }
-// gfx950 gives a workgroup up to 160 KiB of LDS; a double-integrator block
-// stays at or below 80 KiB, so that two of them share a compute unit
-static_assert(prop_lds_bytes(KP_DYN_QUAD12, KP_MAX_OBSTACLES, 0) <= 160 * 1024,
-              "propagate LDS above 160 KiB");
-static_assert(prop_lds_bytes(KP_DYN_DI6, KP_MAX_OBSTACLES, kGridMaxWords) <= 82 * 1024 &&
-                  prop_lds_bytes(KP_DYN_DI6, kGridMinObstacles, 0) <= 80 * 1024,
-              "double-integrator propagate LDS above two blocks per compute unit");
+// gfx950 gives a workgroup up to 160 KiB of LDS
+static_assert(prop_lds_bytes(KP_DYN_QUAD12, KP_MAX_OBSTACLES, 0) <= 150 * 1024 &&
+                  prop_lds_bytes(KP_DYN_DI6, KP_MAX_OBSTACLES, kGridMaxWords) <= 150 * 1024 &&
+                  prop_lds_bytes(KP_DYN_DI6, kGridMinObstacles, 0) <= 150 * 1024,
+              "propagate LDS (with the static arrays) above 160 KiB");
 size_t propagate_lds_bytes(int dyn, int n_obs, int grid_words) {
   return prop_lds_bytes(dyn, n_obs, grid_words);
 }
@@ -906,18 +904,24 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   // per-wave running totals (wave-uniform), flushed once per block
   unsigned long long t_lanes = 0, t_valid = 0, t_steps = 0, t_box = 0, t_checked = 0;
 
-  // A wave's first tile is wave * vg + block: the first vg tiles go to wave
-  // 0 of every block, the next ones to wave 1, and so on, so
-  // that a launch with fewer tiles than the grid has waves runs one wave per
-  // block, spread over the compute units.  Later tiles come from per-group
-  // ticket counters: group q (block index mod ng) hands out tiles
-  // nwaves + ng * k + q.  No burst of tickets at launch, and each counter
-  // sees about 1/ng of the requests.  A block whose first tiles are all past
-  // the end has nothing to do (an oversized grid costs no atomics).
+  // A wave's first tile is wave * vg + slot(block): the first vg tiles go to
+  // wave 0 of every block, the next ones to wave 1, and so on, so that a
+  // launch with fewer tiles than the grid has waves runs one wave per block,
+  // spread over the compute units.  Workgroups are dispatched to the 8 XCDs
+  // round robin (block b on XCD b mod 8), and neighbouring tiles read
+  // neighbouring parents, whose 128-byte lines they share: slot(b) gives
+  // XCD x the contiguous slots x * vg/8 .. (x+1) * vg/8 - 1, so neighbours
+  // meet in one L2 (the host makes vg a multiple of 8, or below 8).  Later
+  // tiles come from per-group ticket counters: group q (block index mod ng)
+  // hands out tiles nwaves + ng * k + q.  No burst of tickets at launch, and
+  // each counter sees about 1/ng of the requests.  A block whose first tiles
+  // are all past the end has nothing to do (an oversized grid costs no
+  // atomics).
   const uint32_t nwaves = vg * kWaves;
   const uint32_t ng = vg < (uint32_t)kGroups ? vg : (uint32_t)kGroups;
   const uint32_t grp = vb % ng;
-  if (vb >= ntiles) return;
+  const uint32_t slot = (vg % 8u == 0u) ? (vb % 8u) * (vg / 8u) + vb / 8u : vb;
+  if (slot >= ntiles) return;
   for (int k = threadIdx.x; k < 6 * n_obs; k += PB) {
     const int ob = k / 6, comp = k - 6 * ob;
     otab[k] = d.obs[(size_t)comp * n_obs + ob];
@@ -937,7 +941,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   }
   __syncthreads();
 
-  uint32_t next = (uint32_t)wave * vg + vb;
+  uint32_t next = (uint32_t)wave * vg + slot;
   for (;;) {
     const uint32_t tile = next;
     if (tile >= ntiles) break;
@@ -1941,11 +1945,10 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
 
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
 // batched launch over a table of problems; the work of each problem is the
-// same either way.  Waves per SIMD: 4 (at most 128 registers).  The
-// quadcopter kernels need more than 96 (the tilt sin / cos keep their
-// range-checked reduction for segments that have left the state box); a
-// compute unit holds two 8-wave double-integrator blocks either way, so a
-// fifth wave per SIMD would gain nothing there.
+// same either way.  Waves per SIMD: 4 (at most 128 registers; one 16-wave
+// block per compute unit).  The quadcopter kernels need more than 96 (the
+// tilt sin / cos keep their range-checked reduction for segments that have
+// left the state box).
 template <int DYN, int INTEG, bool SYM>
 __global__ __launch_bounds__(prop_block(DYN)) __attribute__((amdgpu_waves_per_eu(4))) void k_propagate(
     const Env* __restrict__ env, TraceRec* trace) {
