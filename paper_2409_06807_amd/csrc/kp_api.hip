@@ -451,7 +451,8 @@ kp_status sync_ctl(kp_problem* h) {
     char msg[200];
     std::snprintf(msg, sizeof msg,
                   "device check failed (bits 0x%x: 1 frontier look-back wait limit, 2 commit id "
-                  "past |T| + lanes, 4 node-set look-back wait limit, 8 estimates wait limit)",
+                  "past |T| + lanes, 4 node-set look-back wait limit, 8 estimates wait limit, 16 "
+                  "node-set grid below one block per chunk)",
                   err);
     return fail(h, KP_E_DEVICE, msg);
   }
@@ -566,9 +567,14 @@ kp_status do_post(kp_problem* h, long long lanes_ub, long long old_nodes_ub) {
   h->ctl_fresh = false;
   const long long ctiles = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   const long long ntiles = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
-  const int cmax = cap_commit(h), nmax = cap_post_nodes(h);
+  // commit blocks take at most half of the resident k_post blocks, so a wide
+  // expansion leaves room for the node-set blocks that follow them in the grid
+  const int chalf = h->grid_post_max / 2 > 0 ? h->grid_post_max / 2 : 1;
+  const int cmax = cap_commit(h) < chalf ? cap_commit(h) : chalf, nmax = cap_post_nodes(h);
   const int nc = (int)(ctiles < cmax ? ctiles : cmax);
-  const int nn = (int)(ntiles < nmax ? ntiles : nmax);
+  // node-set blocks: up to the cap, but at least one per kChunkTilesMax tiles
+  int nn = (int)(ntiles < nmax ? ntiles : nmax);
+  if (ntiles > (long long)kChunkTilesMax * nn) nn = (int)((ntiles + kChunkTilesMax - 1) / kChunkTilesMax);
   hipError_t e = launch_post(h->env_dev, post_region_blocks(h->R), nc, nn, h->stream,
                              prof_slot(h, 5));
   if (e != hipSuccess) return hip_fail(h, e, "post launch");
@@ -1459,7 +1465,8 @@ hipError_t batch_iteration(kp_batch* b, long long lanes_ub, long long old_nodes_
   t = (lanes_ub + kCommitBlock - 1) / kCommitBlock;
   const int nc = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
   t = (old_nodes_ub + kNodeTile - 1) / kNodeTile;
-  const int nn = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
+  int nn = (int)(t < b->cfg.node_blocks ? t : b->cfg.node_blocks);
+  if (t > (long long)kChunkTilesMax * nn) nn = (int)((t + kChunkTilesMax - 1) / kChunkTilesMax);
   hipError_t e = launch_propagate_batch(b->dyn, b->integ, b->sym, b->table, n, b->lds_prop,
                                         gp < 1 ? 1 : gp, b->stream);
   if (e == hipSuccess) e = launch_post_batch(b->table, n, b->region_blocks, nc, nn, b->stream);
@@ -1484,10 +1491,14 @@ kp_status batch_status(kp_batch* b) {
 kp_status batch_graph(kp_batch* b) {
   if (b->exec) return KP_OK;
   const long long big = (long long)1 << 40;
+  // |T| is bounded by the largest node capacity (the node-set grid follows it)
+  long long cap = 1;
+  for (const kp_problem* h : b->P)
+    if (h->desc.node_cap > cap) cap = h->desc.node_cap;
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return bhip(b, e, "graph capture");
   hipError_t le = hipSuccess;
-  for (int k = 0; k < b->cfg.iters_per_sync && le == hipSuccess; ++k) le = batch_iteration(b, big, big);
+  for (int k = 0; k < b->cfg.iters_per_sync && le == hipSuccess; ++k) le = batch_iteration(b, big, cap);
   e = hipStreamEndCapture(b->stream, &b->graph);
   if (le != hipSuccess) e = le;
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);

@@ -24,6 +24,7 @@ constexpr int kNodeBlock = 1024;     // threads per node-pass block
 constexpr int kNodesPerThread = 4;   // nodes per thread in the node passes
 constexpr int kNodeTile = kNodeBlock * kNodesPerThread;  // nodes per node-pass tile (4096)
 constexpr int kChunkTiles = 256;     // 64-lane wave tiles per accepted-sample chunk sum
+constexpr int kChunkTilesMax = 16;   // node tiles a k_post block takes as one chunk (4 V_E bits each in a u64)
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
 constexpr int kRegionsPerBlock = 4 * 1024;  // regions per region block of k_post (4 per thread)
 // region blocks at the start of a k_post grid row
@@ -62,7 +63,7 @@ struct alignas(256) Ctl {
   uint32_t epoch;     // tags look-back status words; bumped once per iteration
   uint32_t tk_front, tk_nodes;   // tile tickets of the node passes
   uint32_t bd_front, bd_nodes;   // blocks finished (last-block finalisation)
-  uint32_t err;       // nonzero: a look-back wait hit its spin limit
+  uint32_t err;       // nonzero: a device check failed (a wait hit its spin limit, a grid too small)
   uint32_t iters_done;
   // the iteration as k_commit saw it, read by k_nodesets (whose finaliser
   // rewrites N, it, epoch and done while other blocks may still start)

@@ -1764,6 +1764,159 @@ __device__ __forceinline__ void wait_region(Ctl* c, uint32_t epoch) {
   __syncthreads();
 }
 
+// ---- node-set pass of k_post (Alg. 4) ----
+// A thread's four consecutive old nodes: flag bytes, cells and the two
+// Philox words of each node (demotion draw wd, promotion draw wp).
+struct NodeWords {
+  uint32_t fw;
+  uint32_t cell[4];
+  uint32_t wd[4], wp[4];
+};
+__device__ __forceinline__ void node_fetch(const Dev& d, uint32_t base, int32_t N, NodeWords* w) {
+  w->fw = 0u;
+  w->cell[0] = w->cell[1] = w->cell[2] = w->cell[3] = 0u;
+  if (base >= (uint32_t)N) return;
+  uint32_t f[kFlagWords];
+  load_flag_words(d.flag + base, f);
+  w->fw = f[0];
+  const uint4 cw = *reinterpret_cast<const uint4*>(d.cell + base);
+  w->cell[0] = cw.x;
+  w->cell[1] = cw.y;
+  w->cell[2] = cw.z;
+  w->cell[3] = cw.w;
+}
+__device__ __forceinline__ void node_draws(const Params& p, uint32_t it, uint32_t base, int32_t N,
+                                           NodeWords* w) {
+  if (base >= (uint32_t)N) return;
+  // node pair (2k, 2k+1) shares Philox block (it, k, 0, 3)
+  const U4 wa = philox(it, base >> 1, 0u, 3u, p.key0, p.key1);
+  const U4 wb = philox(it, (base >> 1) + 1u, 0u, 3u, p.key0, p.key1);
+  w->wd[0] = wa.w[0];
+  w->wd[1] = wa.w[2];
+  w->wd[2] = wb.w[0];
+  w->wd[3] = wb.w[2];
+  w->wp[0] = wa.w[1];
+  w->wp[1] = wa.w[3];
+  w->wp[2] = wb.w[1];
+  w->wp[3] = wb.w[3];
+}
+// New V_E membership of the four nodes from their region thresholds (read
+// once the region pass has published them); changed flags are written
+// back.  Returns the V_E bits.
+__device__ __forceinline__ uint32_t node_decide(const Dev& d, uint32_t base, int32_t N, bool goal,
+                                                const NodeWords& w) {
+  if (base >= (uint32_t)N) return 0u;
+  uint32_t nfw = w.fw, eb = 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k >= (uint32_t)N) continue;
+    const unsigned long long t = __hip_atomic_load(&d.thr[w.cell[k] >> 6], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    const bool wasE = ((w.fw >> (8 * k)) & 0xffu) != 0u;
+    const bool stay = wasE && ((unsigned long long)w.wd[k] < t);          // V_E -> V_O w.p. 1-P
+    const bool E = stay || (!goal && ((unsigned long long)w.wp[k] < t));  // V_O -> V_E w.p. P
+    nfw = (nfw & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
+    if (E) eb |= 1u << k;
+  }
+  if (nfw != w.fw) {
+    if (base + 4u <= (uint32_t)N) {
+      store_flag_words(d.flag + base, &nfw);
+    } else {
+      // the word reaches into V_U, whose flags the commit blocks write
+      for (uint32_t k = 0; base + k < (uint32_t)N; ++k)
+        d.flag[base + k] = (uint8_t)((nfw >> (8 * k)) & 0xffu);
+    }
+  }
+  return eb;
+}
+// End of an iteration, by the thread that knows the whole old-node count of
+// the next frontier (upto): |V_U| from the chunk totals, sizes, eq. (6).
+__device__ __forceinline__ void node_finalize(const Params& p, Ctl* c, int32_t N, uint32_t it,
+                                              uint32_t epoch, uint32_t nwt, const uint32_t* ssum,
+                                              bool goal, uint32_t upto) {
+  const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
+  uint32_t nU = 0;
+  for (uint32_t j = 0; j < nch; ++j) nU += ssum[j];
+  const int32_t Nt = N + (int32_t)nU;
+  c->nU = (int32_t)nU;
+  c->N = Nt;
+  if (goal) c->done = KP_SOLVED;
+  finalize_frontier(p, c, upto + nU, Nt);
+  c->f_expl = (int32_t)upto;
+  c->f_base = N;
+  c->it = (int32_t)it + 1;
+  c->epoch = epoch + 1u;
+  c->iters_done += 1u;
+}
+
+// Node sets over a contiguous chunk of `per` tiles (2 .. kChunkTilesMax) per
+// block, with no tile tickets (same-address atomics serialise) and one
+// look-back per chunk.  Chunk indices follow node order and a lower chunk
+// belongs to a block dispatched earlier, so every wait ends whatever the
+// number of blocks resident at once.  Pass 1 decides every node of the
+// chunk and keeps the thread's V_E bits (4 per tile) in one register; the
+// chunk's count gets its global offset from the look-back; pass 2 writes
+// the frontier entries tile by tile, in node order.
+__device__ __forceinline__ void node_chunk(const Params& p, const Dev& d, Ctl* c, uint32_t bi,
+                                           uint32_t per, uint32_t ntiles, int32_t N, uint32_t it,
+                                           uint32_t epoch, uint32_t nwt, const uint32_t* ssum,
+                                           bool goal, uint32_t* s_wt, uint32_t* s_pref) {
+  const uint32_t t0 = bi * per;
+  if (t0 >= ntiles) return;
+  const uint32_t t1 = (t0 + per < ntiles) ? t0 + per : ntiles;
+  const uint32_t lb = threadIdx.x * kNodesPerThread;
+  const uint32_t lane = __lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+  unsigned long long ebits = 0ull;
+  for (uint32_t tile = t0; tile < t1; ++tile) {
+    const uint32_t base = tile * kNodeTile + lb;
+    NodeWords w;
+    node_fetch(d, base, N, &w);
+    node_draws(p, it, base, N, &w);
+    if (tile == t0) wait_region(c, epoch);
+    const uint32_t eb = node_decide(d, base, N, goal, w);
+    ebits |= (unsigned long long)eb << (4u * (tile - t0));
+  }
+  // the chunk's count and its global offset
+  const unsigned long long ws = wave_sum_u64((unsigned long long)__popcll(ebits));
+  if (lane == 0) s_wt[wave] = (uint32_t)ws;
+  __syncthreads();
+  uint32_t agg = 0;
+#pragma unroll
+  for (int k = 0; k < kNodeBlock / 64; ++k) agg += s_wt[k];
+  if (wave == 0) {
+    const uint32_t pre = lookback_prefix_wave(d.st_nodes, bi, agg, epoch, &c->err, 4u);
+    if (lane == 0) *s_pref = pre;
+  }
+  __syncthreads();
+  const uint32_t P = *s_pref;
+  uint32_t acc = 0;
+  for (uint32_t tile = t0; tile < t1; ++tile) {
+    uint32_t eb = (uint32_t)(ebits >> (4u * (tile - t0))) & 0xfu;
+    uint32_t wt;
+    const uint32_t ex = wave_excl_small((uint32_t)__popc(eb), &wt);
+    if (lane == 0) s_wt[wave] = wt;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kNodeBlock / 64; ++k) {
+      const uint32_t t = s_wt[k];
+      off += ((uint32_t)k < wave) ? t : 0u;
+      tot += t;
+    }
+    __syncthreads();
+    uint32_t pos = P + acc + off + ex;
+    const uint32_t base = tile * kNodeTile + lb;
+    while (eb) {
+      const int k = __ffs(eb) - 1;
+      d.F[pos++] = (int32_t)(base + k);
+      eb &= eb - 1u;
+    }
+    acc += tot;
+  }
+  if (t1 == ntiles && threadIdx.x == 0) node_finalize(p, c, N, it, epoch, nwt, ssum, goal, P + agg);
+}
+
 // One post launch's work for block vb of a grid row of vg blocks: nrb
 // region blocks, nc commit blocks, then node-set blocks.  solo: one
 // workgroup plays the three roles in turn (vb = 0, 1, 2 of vg = 3, nc = 1),
@@ -1787,7 +1940,7 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
   const uint32_t lane = __lane_id();
   const uint32_t wave = threadIdx.x >> 6;
   constexpr uint32_t wpb = kCommitBlock / 64;
-  __shared__ uint32_t s_tile, s_pref, s_wt[kNodeBlock / 64];
+  __shared__ uint32_t s_pref, s_wt[kNodeBlock / 64];
 
   // grid row: nrb region blocks, nc commit blocks, then node-set blocks
   const uint32_t nrb = solo ? 1u : (uint32_t)post_region_blocks(p.R);
@@ -1854,93 +2007,34 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
   const uint32_t bi = vb - nrb - (uint32_t)nc;
   const bool goal = c->goal_hit != 0u;
   const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
-  const bool by_ticket = ntiles > nb;
-  uint32_t tile = bi;
-  if (by_ticket) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
-    __syncthreads();
-    tile = s_tile;
-    __syncthreads();
+  if (solo) {
+    // one workgroup: the chunks one after the other
+    for (uint32_t k = 0; k * (uint32_t)kChunkTilesMax < ntiles; ++k)
+      node_chunk(p, d, c, k, kChunkTilesMax, ntiles, N, it, epoch, nwt, ssum, goal, s_wt, &s_pref);
+    return;
   }
-  bool waited = false;
-  for (;;) {
-    if (tile >= ntiles) break;
-    const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
-    const bool in = base < (uint32_t)N;
-    uint32_t fw[kFlagWords] = {};
-    uint32_t cells[4] = {0u, 0u, 0u, 0u};
-    uint32_t wd[4] = {0u, 0u, 0u, 0u}, wp[4] = {0u, 0u, 0u, 0u};
-    if (in) {
-      load_flag_words(d.flag + base, fw);
-      const uint4 cw = *reinterpret_cast<const uint4*>(d.cell + base);
-      cells[0] = cw.x;
-      cells[1] = cw.y;
-      cells[2] = cw.z;
-      cells[3] = cw.w;
-      // node pair (2k, 2k+1) shares Philox block (it, k, 0, 3)
-      const U4 wa = philox(it, base >> 1, 0u, 3u, p.key0, p.key1);
-      const U4 wb = philox(it, (base >> 1) + 1u, 0u, 3u, p.key0, p.key1);
-      wd[0] = wa.w[0];
-      wd[1] = wa.w[2];
-      wd[2] = wb.w[0];
-      wd[3] = wb.w[2];
-      wp[0] = wa.w[1];
-      wp[1] = wa.w[3];
-      wp[2] = wb.w[1];
-      wp[3] = wb.w[3];
-    }
-    if (!waited) {
-      wait_region(c, epoch);
-      waited = true;
-    }
-    uint32_t eb = 0;
-    if (in) {
-      uint32_t nfw = fw[0];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t i = base + k;
-        if (i >= (uint32_t)N) continue;
-        const unsigned long long t = __hip_atomic_load(&d.thr[cells[k] >> 6], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-        const bool wasE = ((fw[0] >> (8 * k)) & 0xffu) != 0u;
-        const bool stay = wasE && ((unsigned long long)wd[k] < t);          // V_E -> V_O w.p. 1-P
-        const bool E = stay || (!goal && ((unsigned long long)wp[k] < t));  // V_O -> V_E w.p. P
-        nfw = (nfw & ~(0xffu << (8 * k))) | ((E ? 1u : 0u) << (8 * k));
-        if (E) eb |= 1u << k;
-      }
-      if (nfw != fw[0]) {
-        if (base + 4u <= (uint32_t)N) {
-          store_flag_words(d.flag + base, &nfw);
-        } else {
-          // the word reaches into V_U, whose flags the commit blocks write
-          for (uint32_t k = 0; base + k < (uint32_t)N; ++k)
-            d.flag[base + k] = (uint8_t)((nfw >> (8 * k)) & 0xffu);
-        }
-      }
-    }
-    const uint32_t upto = compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
-    if (tile == ntiles - 1u && threadIdx.x == 0) {
-      // every old tile has published its count; |V_U| from the chunk totals
-      const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
-      uint32_t nU = 0;
-      for (uint32_t j = 0; j < nch; ++j) nU += ssum[j];
-      const int32_t Nt = N + (int32_t)nU;
-      c->nU = (int32_t)nU;
-      c->N = Nt;
-      if (goal) c->done = KP_SOLVED;
-      finalize_frontier(p, c, upto + nU, Nt);
-      c->f_expl = (int32_t)upto;
-      c->f_base = N;
-      c->it = (int32_t)it + 1;
-      c->epoch = epoch + 1u;
-      c->iters_done += 1u;
-    }
-    if (!by_ticket) break;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&c->tk_nodes, 1u);
-    __syncthreads();
-    tile = s_tile;
-    __syncthreads();
+  // the launcher gives at least one node-set block per kChunkTilesMax tiles
+  // of its bound on |T|; a grid that breaks this is refused (error bit 16)
+  const uint32_t per = (ntiles + nb - 1) / nb;
+  if (per > (uint32_t)kChunkTilesMax) {
+    if (bi == 0 && threadIdx.x == 0) atomicOr(&c->err, 16u);
+    return;
   }
+  if (per > 1u) {
+    node_chunk(p, d, c, bi, per, ntiles, N, it, epoch, nwt, ssum, goal, s_wt, &s_pref);
+    return;
+  }
+  // one tile per block: tile = block index
+  const uint32_t tile = bi;
+  if (tile >= ntiles) return;
+  const uint32_t base = tile * kNodeTile + threadIdx.x * kNodesPerThread;
+  NodeWords w;
+  node_fetch(d, base, N, &w);
+  node_draws(p, it, base, N, &w);
+  wait_region(c, epoch);
+  const uint32_t eb = node_decide(d, base, N, goal, w);
+  const uint32_t upto = compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
+  if (tile == ntiles - 1u && threadIdx.x == 0) node_finalize(p, c, N, it, epoch, nwt, ssum, goal, upto);
 }
 
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
@@ -1961,10 +2055,16 @@ __global__ __launch_bounds__(prop_block(DYN)) __attribute__((amdgpu_waves_per_eu
   propagate_body<DYN, INTEG, SYM, prop_block(DYN)>(env, env->d.trace, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(kCommitBlock) void k_post(const Env* __restrict__ env, int nc) {
+// Waves per SIMD: 8 (at most 64 registers), so two 16-wave blocks share a
+// compute unit: the node-set blocks of a wide tree are twice as many, and a
+// launch's commit blocks do not fill the device on their own.  The batched
+// kernel keeps its default (at 64 registers it would spill).
+__global__ __launch_bounds__(kCommitBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_post(
+    const Env* __restrict__ env, int nc) {
   post_body(env, nc, blockIdx.x, gridDim.x, false);
 }
-__global__ __launch_bounds__(kCommitBlock) void k_post_batch(const Env* const* __restrict__ envs, int nc) {
+__global__ __launch_bounds__(kCommitBlock) void k_post_batch(const Env* const* __restrict__ envs,
+                                                             int nc) {
   post_body(envs[blockIdx.y], nc, blockIdx.x, gridDim.x, false);
 }
 

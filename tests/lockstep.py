@@ -44,6 +44,7 @@ class Report:
         self.max_rel_err = 0.0
         self.learned_lanes = 0
         self.max_lanes = 0
+        self.max_nodes = 0
         self.failures = []
         self.final_status = None
 
@@ -58,7 +59,7 @@ class Report:
     def summary(self):
         s = (f"iterations={self.iterations} lanes={self.lanes} ambiguous={self.ambiguous_lanes} "
              f"ill_conditioned={self.ill_lanes} adopted={self.adopted} "
-             f"max_rel_err={self.max_rel_err:.2e} max_lanes={self.max_lanes} "
+             f"max_rel_err={self.max_rel_err:.2e} max_lanes={self.max_lanes} max_nodes={self.max_nodes} "
              f"status={self.final_status} failures={len(self.failures)}")
         if self.failures:
             s += " first: " + "; ".join(self.failures[:5])
@@ -485,6 +486,7 @@ def run_lockstep_plan(p, iterations, device="cuda:0", reload=False, launch_limit
         W.update_estimates()
         og = W.update_node_sets()
         g = G.copy_tree()
+        rep.max_nodes = max(rep.max_nodes, int(g["N"]))
         compare_state(p, W, g, rep, it, "after kp_plan", gpu_prev)
         # kp_plan stops on its one-iteration budget, or earlier on a goal, or
         # when the next frontier it has just built gives eq. (6) lambda = 0 or

@@ -103,6 +103,9 @@ PLAN_CASES = {
     "di-few-blocks": (lambda: problem_small_di(seed=3, cap=20000, n_obs=20), 40, (2, 1)),
     "quad-few-blocks": (lambda: problem_small_quad(seed=2, cap=24000, n_obs=60, lambda_max=8),
                         14, (3, 2)),
+    # a node-set cap of one block under a tree of more than 16 tiles: the
+    # launcher raises the node-set grid to one block per 16-tile chunk
+    "di-chunk-floor": (lambda: problem_small_di(seed=5, cap=100000, n_obs=20), 80, (4, 1)),
 }
 
 
@@ -120,3 +123,5 @@ def test_lockstep_plan(name, reload):
         assert rep.max_lanes > 16384, rep.summary()
     if name in ("c1", "di-few-blocks"):
         assert rep.final_status == oracle.TREE_FULL, rep.summary()
+    if name == "di-chunk-floor":
+        assert rep.max_nodes > 16 * 4096, rep.summary()
