@@ -922,9 +922,12 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   const uint32_t grp = vb % ng;
   const uint32_t slot = (vg % 8u == 0u) ? (vb % 8u) * (vg / 8u) + vb / 8u : vb;
   if (slot >= ntiles) return;
+  // the obstacle table: coalesced reads of the six component arrays, each
+  // value stored at its box's slot
   for (int k = threadIdx.x; k < 6 * n_obs; k += PB) {
-    const int ob = k / 6, comp = k - 6 * ob;
-    otab[k] = d.obs[(size_t)comp * n_obs + ob];
+    const int comp = (k >= n_obs) + (k >= 2 * n_obs) + (k >= 3 * n_obs) + (k >= 4 * n_obs) +
+                     (k >= 5 * n_obs);
+    otab[6 * (k - comp * n_obs) + comp] = d.obs[k];
   }
   if (use_grid) {
     // the grid's u16 words, copied two at a time (the device copy is padded
@@ -1151,16 +1154,54 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
               const int cy1 = clamp_cell((hy - p.og_org[1]) * gi + 1e-3f, gny);
               const int cz0 = clamp_cell((lz - p.og_org[2]) * gi - 1e-3f, p.og_n[2]);
               const int cz1 = clamp_cell((hz - p.og_org[2]) * gi + 1e-3f, p.og_n[2]);
-              for (int cz = cz0; cz <= cz1; ++cz) {
-                for (int cy = cy0; cy <= cy1; ++cy) {
+              if (__builtin_expect(__ballot(cy1 - cy0 > 1 || cz1 - cz0 > 1) == 0ull, 1)) {
+                // A step shorter than a cell touches at most 2 x 2 rows of
+                // cells.  Their four entry ranges are read at once, and one
+                // flat loop runs over the lane's entries: the wave makes as
+                // many trips as its longest list, not one pass per row with
+                // every lane waiting for the row's longest list.
+                // (every row index is clamped into the range, so the eight
+                // offset reads go out together; a row past the range counts 0)
+                uint32_t kb[4], kn[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int cy = min(cy0 + (r & 1), cy1), cz = min(cz0 + (r >> 1), cz1);
                   const int row = (cz * gny + cy) * gnx;
-                  const uint32_t k1 = goff[row + cx1 + 1];
-                  uint32_t k = goff[row + cx0];
-                  box_tests += k1 - k;
-                  for (; k < k1; ++k) {
-                    const float* o = reinterpret_cast<const float*>(obox + 3 * gent[k]);
-                    hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) &
-                           (lz <= o[5]) & (o[2] <= hz);
+                  kb[r] = goff[row + cx0];
+                  const uint32_t ke = goff[row + cx1 + 1];
+                  const bool in = cy0 + (r & 1) <= cy1 && cz0 + (r >> 1) <= cz1;
+                  kn[r] = in ? ke - kb[r] : 0u;
+                }
+                const uint32_t c1 = kn[0], c2 = c1 + kn[1], c3 = c2 + kn[2], tn = c3 + kn[3];
+                box_tests += tn;
+                auto entry = [&](uint32_t t) {
+                  return t < c1 ? kb[0] + t
+                                : t < c2 ? kb[1] + (t - c1) : t < c3 ? kb[2] + (t - c2) : kb[3] + (t - c3);
+                };
+                // two entries per trip, so that their LDS reads overlap; past
+                // the end the sentinel box n_obs (which nothing touches) stands in
+                for (uint32_t t = 0; t < tn; t += 2) {
+                  const uint32_t ia = gent[entry(t)];
+                  const uint32_t ib = (t + 1 < tn) ? (uint32_t)gent[entry(t + 1)] : (uint32_t)n_obs;
+                  const float* o = reinterpret_cast<const float*>(obox + 3 * ia);
+                  const float* q = reinterpret_cast<const float*>(obox + 3 * ib);
+                  hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) &
+                         (lz <= o[5]) & (o[2] <= hz);
+                  hit |= (lx <= q[3]) & (q[0] <= hx) & (ly <= q[4]) & (q[1] <= hy) &
+                         (lz <= q[5]) & (q[2] <= hz);
+                }
+              } else {
+                for (int cz = cz0; cz <= cz1; ++cz) {
+                  for (int cy = cy0; cy <= cy1; ++cy) {
+                    const int row = (cz * gny + cy) * gnx;
+                    const uint32_t k1 = goff[row + cx1 + 1];
+                    uint32_t k = goff[row + cx0];
+                    box_tests += k1 - k;
+                    for (; k < k1; ++k) {
+                      const float* o = reinterpret_cast<const float*>(obox + 3 * gent[k]);
+                      hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) &
+                             (lz <= o[5]) & (o[2] <= hz);
+                    }
                   }
                 }
               }
