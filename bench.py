@@ -511,7 +511,8 @@ def sweep(workload, seeds, caps, eps_delta, lambdas=(), only_lambda=False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50,
+                    help="queries timed (planner seeds 0 .. steps-1; the paper plans 50 queries per scene)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--profile-steps", type=int, default=-1,
