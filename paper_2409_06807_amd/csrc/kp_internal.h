@@ -15,7 +15,7 @@ namespace kp {
 __host__ __device__ constexpr int prop_block(int) { return 1024; }
 // largest obstacle grid (u16 words: cell offsets and obstacle ids) a
 // double-integrator block stages in LDS
-constexpr int kGridMaxWords = 16384;
+constexpr int kGridMaxWords = 32768;
 // double integrators with more obstacles than this use the grid; with fewer,
 // a wave's candidate list is short or empty and costs less than a grid
 // lookup at every step
