@@ -924,10 +924,23 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
   if (slot >= ntiles) return;
   // the obstacle table: coalesced reads of the six component arrays, each
   // value stored at its box's slot
-  for (int k = threadIdx.x; k < 6 * n_obs; k += PB) {
-    const int comp = (k >= n_obs) + (k >= 2 * n_obs) + (k >= 3 * n_obs) + (k >= 4 * n_obs) +
-                     (k >= 5 * n_obs);
-    otab[6 * (k - comp * n_obs) + comp] = d.obs[k];
+  // (both copies issue eight loads per thread before their LDS stores, so
+  // the loads' round trips overlap instead of following one another)
+  constexpr int kStage = 8;
+  for (int k0 = threadIdx.x; k0 < 6 * n_obs; k0 += kStage * PB) {
+    float v[kStage];
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+      const int k = k0 + j * PB;
+      v[j] = (k < 6 * n_obs) ? d.obs[k] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+      const int k = k0 + j * PB;
+      const int comp = (k >= n_obs) + (k >= 2 * n_obs) + (k >= 3 * n_obs) + (k >= 4 * n_obs) +
+                       (k >= 5 * n_obs);
+      if (k < 6 * n_obs) otab[6 * (k - comp * n_obs) + comp] = v[j];
+    }
   }
   if (use_grid) {
     // the grid's u16 words, copied two at a time (the device copy is padded
@@ -935,7 +948,19 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     const int nw2 = (p.og_words + 1) >> 1;
     const uint32_t* src = reinterpret_cast<const uint32_t*>(d.og);
     uint32_t* dst = reinterpret_cast<uint32_t*>(goff);
-    for (int k = threadIdx.x; k < nw2; k += PB) dst[k] = src[k];
+    for (int k0 = threadIdx.x; k0 < nw2; k0 += kStage * PB) {
+      uint32_t v[kStage];
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) {
+        const int k = k0 + j * PB;
+        v[j] = (k < nw2) ? src[k] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < kStage; ++j) {
+        const int k = k0 + j * PB;
+        if (k < nw2) dst[k] = v[j];
+      }
+    }
   }
   if (threadIdx.x < 6) otab[6 * n_obs + threadIdx.x] = (threadIdx.x < 3) ? 3.0e38f : -3.0e38f;
   if (threadIdx.x < (unsigned)n) {
