@@ -1264,8 +1264,10 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       cl = fin ? cell_of(p, x[0], x[1], x[2]) : d.cell[f];
       if (valid) {
         const uint32_t r = cl >> 6;
-        const bool unvisited = ((d.visited[r] >> (cl & 63u)) & 1ull) == 0ull;
-        accept = unvisited || ((unsigned long long)w_acc < d.thr[r]);
+        // both words are requested before either is used (one round trip)
+        const unsigned long long vis = d.visited[r], thr = d.thr[r];
+        const bool unvisited = ((vis >> (cl & 63u)) & 1ull) == 0ull;
+        accept = unvisited || ((unsigned long long)w_acc < thr);
         const float dx = x[0] - p.goal_c[0], dy = x[1] - p.goal_c[1], dz = x[2] - p.goal_c[2];
         goal = accept && (dx * dx + dy * dy + dz * dz <= p.goal_r2);
         if (goal) c->goal_hit = 1u;
