@@ -1401,7 +1401,13 @@ __device__ __forceinline__ void commit_tiles(const Params& p, const Dev& d, Ctl*
     unsigned long long part = 0;
     const uint32_t* ssum = d.ssum + (size_t)(k.it & 1u) * (size_t)d.nchunk;
     for (uint32_t j = lane; j < ch; j += 64u) part += ssum[j];
-    for (uint32_t j = ch * kChunkTiles + lane; j < wt; j += 64u) part += d.scount[j];
+    // the (at most kChunkTiles - 1) earlier counts of the chunk: all loads issued at once
+    const uint32_t c0 = ch * kChunkTiles + lane;
+#pragma unroll
+    for (int q = 0; q < kChunkTiles / 64; ++q) {
+      const uint32_t j = c0 + 64u * (uint32_t)q;
+      part += (j < wt) ? d.scount[j] : 0u;
+    }
     const uint32_t pre = (uint32_t)wave_sum_u64(part);
     if (mine) {
       const int32_t id = k.N + (int32_t)(pre + lane);
@@ -1897,14 +1903,17 @@ __device__ __forceinline__ uint32_t node_decide(const Dev& d, uint32_t base, int
   }
   return eb;
 }
-// End of an iteration, by the thread that knows the whole old-node count of
-// the next frontier (upto): |V_U| from the chunk totals, sizes, eq. (6).
+// End of an iteration, by wave 0 of the block that knows the whole old-node
+// count of the next frontier (upto, the same in every lane): |V_U| from the
+// chunk totals (one load per lane), then lane 0 sets the sizes, eq. (6).
 __device__ __forceinline__ void node_finalize(const Params& p, Ctl* c, int32_t N, uint32_t it,
                                               uint32_t epoch, uint32_t nwt, const uint32_t* ssum,
                                               bool goal, uint32_t upto) {
   const uint32_t nch = (nwt + kChunkTiles - 1) / kChunkTiles;
-  uint32_t nU = 0;
-  for (uint32_t j = 0; j < nch; ++j) nU += ssum[j];
+  unsigned long long part = 0;
+  for (uint32_t j = __lane_id(); j < nch; j += 64u) part += ssum[j];
+  const uint32_t nU = (uint32_t)wave_sum_u64(part);
+  if (__lane_id() != 0) return;
   const int32_t Nt = N + (int32_t)nU;
   c->nU = (int32_t)nU;
   c->N = Nt;
@@ -1982,7 +1991,7 @@ __device__ __forceinline__ void node_chunk(const Params& p, const Dev& d, Ctl* c
     }
     acc += tot;
   }
-  if (t1 == ntiles && threadIdx.x == 0) node_finalize(p, c, N, it, epoch, nwt, ssum, goal, P + agg);
+  if (t1 == ntiles && threadIdx.x < 64u) node_finalize(p, c, N, it, epoch, nwt, ssum, goal, P + agg);
 }
 
 // One post launch's work for block vb of a grid row of vg blocks: nrb
@@ -2102,7 +2111,7 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
   wait_region(c, epoch);
   const uint32_t eb = node_decide(d, base, N, goal, w);
   const uint32_t upto = compact_frontier(d, d.st_nodes, eb, base, tile, epoch, s_wt, &s_pref);
-  if (tile == ntiles - 1u && threadIdx.x == 0) node_finalize(p, c, N, it, epoch, nwt, ssum, goal, upto);
+  if (tile == ntiles - 1u && threadIdx.x < 64u) node_finalize(p, c, N, it, epoch, nwt, ssum, goal, upto);
 }
 
 // One problem per launch, or one problem per grid row (blockIdx.y) of a
