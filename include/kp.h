@@ -302,8 +302,10 @@ kp_status kp_set_trace(kp_problem* h, void* dev_trace);
 /* Caps on the workgroups of every launch of the handle: prop_blocks for the
  * expansion, node_blocks for the V_U commit and the node passes (0 = the
  * occupancy maximum, the default).  Kernels take their work from ticket
- * counters and read their sizes from device memory, so the results do not
- * depend on these caps; small caps make one block serve many tiles. */
+ * counters or contiguous chunks and read their sizes from device memory, so
+ * the results do not depend on these caps; small caps make one block serve
+ * many tiles.  The node-set pass of kp_plan keeps at least one block per 16
+ * node tiles (65,536 nodes) of the tree's bound, above the cap if need be. */
 kp_status kp_set_launch_limits(kp_problem* h, int32_t prop_blocks, int32_t node_blocks);
 
 const char* kp_status_str(kp_status s);
