@@ -141,8 +141,9 @@ __device__ __forceinline__ uint32_t wave_excl_small(uint32_t c, uint32_t* total)
 
 // Decoupled look-back over per-tile status words: (30-bit epoch tag | 2-bit
 // flag | 32-bit value); flag 1 = tile aggregate, 2 = inclusive prefix.  Run by
-// one whole wave: lane l inspects tile (t - 1 - l), so one probe covers 64
-// predecessors; the nearest inclusive prefix ends the walk.  A tile only waits
+// one whole wave: lane l inspects tiles (t - 1 - l - 64 q), q < 4, so one
+// probe round covers 256 predecessors; the nearest inclusive prefix ends the
+// walk.  A tile only waits
 // for tiles with smaller tickets, all held by running blocks, so the wait
 // always ends; the spin bound only guards against a broken invariant.
 __device__ uint32_t lookback_prefix_wave(unsigned long long* st, uint32_t tile, uint32_t agg,
@@ -158,30 +159,49 @@ __device__ uint32_t lookback_prefix_wave(unsigned long long* st, uint32_t tile, 
   if (lane == 0)
     __hip_atomic_store(&st[tile], tag | (1ull << 32) | agg, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
+  // kLookWindows windows of 64 predecessors are requested per probe round, so
+  // a walk past many unresolved tiles takes a quarter of the round trips;
+  // the windows are then taken nearest first, and a window that is not yet
+  // complete is requested again in the next round.
+  constexpr int kLookWindows = 4;
   uint32_t excl = 0;
   int32_t base = (int32_t)tile - 1;
   uint32_t spins = 0;
+  bool found = false;
   for (;;) {
-    const int32_t j = base - lane;
-    unsigned long long w = tag | (2ull << 32);  // before tile 0: an empty prefix
-    if (j >= 0) w = __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t fl = (uint32_t)(w >> 32) & 3u;
-    const bool ready = ((uint32_t)(w >> 34) == (epoch & 0x3fffffffu)) && fl != 0u;
-    const unsigned long long pm = __ballot(ready && fl == 2u);
-    const unsigned long long rm = __ballot(ready);
-    const int limit = pm ? (__ffsll((long long)pm) - 1) : 63;
-    const unsigned long long need = (limit == 63) ? ~0ull : ((1ull << (limit + 1)) - 1ull);
-    if ((rm & need) != need) {
+    unsigned long long w[kLookWindows];
+#pragma unroll
+    for (int q = 0; q < kLookWindows; ++q) {
+      const int32_t j = base - lane - 64 * q;
+      w[q] = tag | (2ull << 32);  // before tile 0: an empty prefix
+      if (j >= 0) w[q] = __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bool stalled = false;
+#pragma unroll
+    for (int q = 0; q < kLookWindows; ++q) {
+      if (found || stalled) continue;  // wave-uniform (from ballots)
+      const uint32_t fl = (uint32_t)(w[q] >> 32) & 3u;
+      const bool ready = ((uint32_t)(w[q] >> 34) == (epoch & 0x3fffffffu)) && fl != 0u;
+      const unsigned long long pm = __ballot(ready && fl == 2u);
+      const unsigned long long rm = __ballot(ready);
+      const int limit = pm ? (__ffsll((long long)pm) - 1) : 63;
+      const unsigned long long need = (limit == 63) ? ~0ull : ((1ull << (limit + 1)) - 1ull);
+      if ((rm & need) != need) {
+        stalled = true;
+        continue;
+      }
+      excl += (uint32_t)wave_sum_u64(lane <= limit ? (unsigned long long)(uint32_t)w[q] : 0ull);
+      if (pm) found = true;
+      else base -= 64;
+    }
+    if (found) break;
+    if (stalled) {
       if (++spins > (1u << 22)) {
         if (lane == 0) atomicOr(err, err_bit);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    excl += (uint32_t)wave_sum_u64(lane <= limit ? (unsigned long long)(uint32_t)w : 0ull);
-    if (pm) break;
-    base -= 64;
   }
   if (lane == 0)
     __hip_atomic_store(&st[tile], tag | (2ull << 32) | (unsigned long long)(excl + agg),
