@@ -2039,8 +2039,14 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
   constexpr uint32_t wpb = kCommitBlock / 64;
   __shared__ uint32_t s_pref, s_wt[kNodeBlock / 64];
 
-  // grid row: nrb region blocks, nc commit blocks, then node-set blocks
+  // grid row: nrb region blocks, the node-set blocks, then nc commit blocks
+  // (solo: region, commit, node-set).  The node-set blocks carry the
+  // iteration's end, so they are dispatched right after the region blocks;
+  // the commit blocks only have to finish before the launch does.
   const uint32_t nrb = solo ? 1u : (uint32_t)post_region_blocks(p.R);
+  const uint32_t nb = vg - nrb - (uint32_t)nc;
+  const bool commit_role = solo ? vb == 1u : vb >= nrb + nb;
+  const uint32_t bi = solo ? 0u : vb - nrb;
   if (vb < nrb) {
     // ---- UpdateEstimates; and the counters of the next expansion ----
     if (vb == 0) {
@@ -2060,8 +2066,8 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
     }
     return;
   }
-  if (vb < nrb + (uint32_t)nc) {
-    const uint32_t ci = vb - nrb;
+  if (commit_role) {
+    const uint32_t ci = solo ? 0u : vb - nrb - nb;
     // ---- V_U ----
     CommitCtx k;
     k.N = N;
@@ -2100,8 +2106,6 @@ __device__ __forceinline__ void post_body(const Env* __restrict__ env, int nc, u
     return;
   }
   // ---- UpdateNodeSets over the old nodes ----
-  const uint32_t nb = vg - nrb - (uint32_t)nc;
-  const uint32_t bi = vb - nrb - (uint32_t)nc;
   const bool goal = c->goal_hit != 0u;
   const uint32_t ntiles = done ? 0u : (uint32_t)((N + kNodeTile - 1) / kNodeTile);
   if (solo) {
