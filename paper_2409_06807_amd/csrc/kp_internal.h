@@ -26,7 +26,7 @@ constexpr int kNodeTile = kNodeBlock * kNodesPerThread;  // nodes per node-pass 
 constexpr int kChunkTiles = 256;     // 64-lane wave tiles per accepted-sample chunk sum
 constexpr int kChunkTilesMax = 16;   // node tiles a k_post block takes as one chunk (4 V_E bits each in a u64)
 constexpr int kRegionBlock = 1024;   // threads of the single region-estimate block
-constexpr int kRegionsPerBlock = 4 * 1024;  // regions per region block of k_post (4 per thread)
+constexpr int kRegionsPerBlock = 4 * 1024;  // regions per region block of k_post (4 per thread of 1024)
 // region blocks at the start of a k_post grid row
 __host__ __device__ constexpr int post_region_blocks(int R) {
   return (R + kRegionsPerBlock - 1) / kRegionsPerBlock;

@@ -1633,7 +1633,7 @@ __device__ __forceinline__ void wait_count(Ctl* c, uint32_t* ctr, uint32_t n) {
 }
 
 // UpdateEstimates in k_post, over nrb blocks of NT threads: block b holds
-// regions b * kRegionsPerBlock + threadIdx.x + k * NT (k < 4) in registers.
+// regions b * kRegionsPerBlock + threadIdx.x + k * NT (k < kRegionsPerBlock / NT) in registers.
 // The largest score and the exact sum of the scaled scores are combined
 // across the blocks with device atomics (a maximum and an integer sum give
 // the same result in any order), so the thresholds are those of the
@@ -1641,17 +1641,18 @@ __device__ __forceinline__ void wait_count(Ctl* c, uint32_t* ctr, uint32_t n) {
 // epoch in region_ready.
 template <int NT>
 __device__ void region_part(const Env* __restrict__ env, uint32_t b, uint32_t nrb, uint32_t epoch) {
-  static_assert(kRegionsPerBlock == 4 * NT, "four regions per thread");
+  constexpr int kRT = kRegionsPerBlock / NT;  // regions per thread, held in registers
+  static_assert(kRegionsPerBlock == kRT * NT && kRT >= 1, "whole regions per thread");
   const Params& p = env->p;
   const Dev& d = env->d;
   Ctl* c = d.ctl;
   __shared__ double s_max[NT / 64];
   __shared__ unsigned long long s_sum[NT / 64];
   const int wave = threadIdx.x >> 6;
-  double sc[4];
+  double sc[kRT];
   double mx = 0.0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kRT; ++k) {
     const int r = (int)b * kRegionsPerBlock + threadIdx.x + k * NT;
     sc[k] = -1.0;
     if (r < p.R && d.avail[r])
@@ -1677,7 +1678,7 @@ __device__ void region_part(const Env* __restrict__ env, uint32_t b, uint32_t nr
   const int e = (mx > 0.0) ? ilogb(mx) : 0;
   unsigned long long q = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < kRT; ++k)
     if (sc[k] >= 0.0) q += (unsigned long long)floor(ldexp(sc[k], 46 - e));
   q = wave_sum_u64(q);
   if (__lane_id() == 0) s_sum[wave] = q;
@@ -1694,7 +1695,7 @@ __device__ void region_part(const Env* __restrict__ env, uint32_t b, uint32_t nr
     Q = __hip_atomic_load(&c->rg_sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kRT; ++k) {
     const int r = (int)b * kRegionsPerBlock + threadIdx.x + k * NT;
     if (r < p.R && sc[k] >= 0.0) d.thr[r] = region_thr(sc[k], e, Q, p.eps);
   }
