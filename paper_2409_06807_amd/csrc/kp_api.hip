@@ -402,6 +402,26 @@ void fill_params(kp_problem* h) {
   double rc = d.steps * per_step * (1.0 + 1e-4) + 1e-3;
   if (!std::isfinite(rc)) rc = 3.0e38;
   p.rc = (float)rc;
+  // Quadcopter: how far accelerations move a position over a whole segment,
+  // away from the straight line of the start velocity.  The acceleration is
+  // thrust / m times a column of a rotation matrix (entries in [-1, 1]) less
+  // g along z, so per axis it lies in [-A, A] (x, y) and [-A - g, A - g] (z),
+  // A = max |thrust| / m; j steps add at most a (j h)^2 / 2 of either sign.
+  if (d.dynamics == KP_DYN_QUAD12) {
+    const double tk = d.steps * hh;
+    const double A = std::fmax(std::fabs((double)d.u_lo[0]), std::fabs((double)d.u_hi[0])) /
+                     std::fabs((double)d.dyn_params[0]);
+    const double g = d.dyn_params[1];
+    for (int a = 0; a < 3; ++a) {
+      const double alo = -A - (a == 2 ? g : 0.0), ahi = A - (a == 2 ? g : 0.0);
+      double lo = std::fmin(alo, 0.0) * 0.5 * tk * tk * (1.0 + 1e-4) - 1e-4;
+      double hi = std::fmax(ahi, 0.0) * 0.5 * tk * tk * (1.0 + 1e-4) + 1e-4;
+      if (!std::isfinite(lo)) lo = -3.0e38;
+      if (!std::isfinite(hi)) hi = 3.0e38;
+      p.ra_lo[a] = (float)lo;
+      p.ra_hi[a] = (float)hi;
+    }
+  }
 }
 
 void carve(kp_problem* h, void* ws) {

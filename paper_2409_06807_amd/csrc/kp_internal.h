@@ -97,6 +97,9 @@ struct Params {
   int32_t G[3];
   int32_t na[3];        // fine cells per axis = G * S
   float h, margin, goal_r2, rc;
+  // quadcopter: a segment's displacement from accelerations, per axis, lies
+  // in [ra_lo, ra_hi] (a_lo (K h)^2 / 2 .. a_hi (K h)^2 / 2 around 0)
+  float ra_lo[3], ra_hi[3];
   float goal_c[3];
   float w_lo[3];        // workspace lower corner
   float inv_w[3];       // fine cells per unit length

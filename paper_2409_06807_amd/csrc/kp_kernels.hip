@@ -1051,7 +1051,8 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     // the box of the whole segment's positions (segment_box_di).
     // Quadcopter: until its first failing step a segment stays within rc
     // (per axis) of its parent, since every checked step starts from a state
-    // inside the velocity bounds.  Obstacles that overlap the union of the
+    // inside the velocity bounds, and near the straight line of its parent's
+    // velocity (the accelerations are bounded).  Obstacles that overlap the union of the
     // wave's reach boxes grown by the margin form the wave's union list.  The
     // parents of one tile can lie far apart, and then the union box covers
     // much of the scene; one such tile ran several times longer than the
@@ -1061,16 +1062,27 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
     const uint16_t* my = cand;  // this lane's candidate list and its length
     uint32_t mycnt = 0;
     uint32_t kmax = 0;          // every list is read to this even length
+    uint32_t ij01 = 0;          // the list's first two entries
     if (!use_grid) {
       const float big = 3.0e38f;
       float rlo[3], rhi[3];
       if constexpr (DYN == KP_DYN_DI6) {
         segment_box_di<INTEG>(x, u, K, sc.h, rlo, rhi);
       } else {
+        // An RK4 (or Euler) step moves a position by h v plus a weighted sum
+        // of stage accelerations, and the velocity by such a sum, with
+        // non-negative weights: after j steps p_j - p_0 - j h v_0 is (j h)^2 / 2
+        // times a mean of accelerations, inside [ra_lo, ra_hi] per axis
+        // whatever the attitude.  So the positions lie within those offsets
+        // of the line from p_0 to p_0 + K h v_0.  The reach box is that,
+        // widened by a bound on the FP32 rounding of K steps, and cut to rc.
+        const float tk = (float)K * p.h;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          rlo[a] = x[a] - p.rc;
-          rhi[a] = x[a] + p.rc;
+          const float dv = tk * x[6 + a];
+          const float eps = 1e-3f + (float)(K + 4) * 1e-6f * (1.0f + fabsf(x[a]) + p.rc);
+          rlo[a] = x[a] + fmaxf(fminf(dv, 0.0f) + p.ra_lo[a] - eps, -p.rc);
+          rhi[a] = x[a] + fminf(fmaxf(dv, 0.0f) + p.ra_hi[a] + eps, p.rc);
         }
       }
 #pragma unroll
@@ -1152,6 +1164,7 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
         const_cast<uint16_t*>(my)[k] = (uint16_t)n_obs;
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
+      ij01 = *reinterpret_cast<const uint32_t*>(my);
     }
 
     // x' = PropagateODE(x, u, dt): every lane integrates its whole segment.
@@ -1251,16 +1264,25 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
                 }
               }
             } else {
-              // two candidates per trip (one 32-bit read of their indices)
-              // so that their LDS reads overlap
+              // two candidates per trip (one 32-bit read of their indices) so
+              // that their LDS reads overlap.  The first pair's indices stay
+              // in a register for the whole segment, and each trip reads the
+              // next pair's together with its own boxes, so a trip waits for
+              // one LDS round trip, not two.  (The read past the last pair
+              // stays inside this wave's lists: a group list has room for
+              // kGroupCap + 2 entries and the union list is followed by the
+              // group lists; its value is not used.)
+              const uint32_t* my32 = reinterpret_cast<const uint32_t*>(my);
+              uint32_t ij = ij01;
               for (uint32_t q = 0; q < kmax; q += 2) {
-                const uint32_t ij = *reinterpret_cast<const uint32_t*>(my + q);
+                const uint32_t ijn = my32[(q >> 1) + 1];
                 const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
                 const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
                 hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
                        (o[2] <= hz);
                 hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
                        (r[2] <= hz);
+                ij = ijn;
               }
               box_tests += mycnt;
             }

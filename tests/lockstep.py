@@ -146,7 +146,11 @@ def compare_expansion(p, W, recs, tr, rep, it, gpu_prev=None):
     lanes = len(recs)
     if not (np.array_equal(tr["parent"], recs["parent"]) and
             np.array_equal(tr["sample"], recs["sample"])):
-        rep.fail(f"it{it}: lane order (parent, sample) differs")
+        bad = np.nonzero((tr["parent"] != recs["parent"]) | (tr["sample"] != recs["sample"]))[0]
+        k = int(bad[0])
+        rep.fail(f"it{it}: lane order (parent, sample) differs at {len(bad)} of {lanes} lanes, "
+                 f"first lane {k} (tile {k // 64}): gpu ({tr['parent'][k]}, {tr['sample'][k]}) "
+                 f"oracle ({recs['parent'][k]}, {recs['sample'][k]}), last lane {int(bad[-1])}")
         return recs
     gu = np.ascontiguousarray(tr["u"][:, :m]).view(np.uint32)
     ou = np.ascontiguousarray(recs["u"][:, :m]).view(np.uint32)

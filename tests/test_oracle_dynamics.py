@@ -201,3 +201,41 @@ def test_di_euler_vs_exact_deviation_bound():
     x = integrate(p, x0, u, 10)
     exact = 0.5 * u * (10 * h) ** 2
     np.testing.assert_allclose(exact - x[:3], u * h * h * 10 / 2, atol=1e-12)
+
+
+@pytest.mark.parametrize("integrator", [RK4, EULER])
+def test_quad_displacement_bound(integrator):
+    """The bound the expansion's obstacle culling rests on.  The acceleration
+    is thrust / m times a rotation-matrix column, less g along z, so per axis
+    it lies in [-A, A] (x, y) and [-A - g, A - g] (z), A = max thrust / m; then
+    after j steps p_j - p0 - j h v0 lies in [a_lo, a_hi] (j h)^2 / 2 per axis,
+    from any start state (angles and rates unbounded) and any admissible
+    control."""
+    from workloads import problem_c2
+    p = problem_c2(integrator=integrator)
+    h = float(np.float32(p["h"]))
+    K = int(p["steps"])
+    A = float(p["u_hi"][0]) / float(p["dyn_params"][0])
+    g = float(p["dyn_params"][1])
+    a_lo = np.array([-A, -A, -A - g])
+    a_hi = np.array([A, A, A - g])
+    rng = np.random.default_rng(7)
+    worst_lo = worst_hi = 0.0
+    for _ in range(150):
+        x0 = np.zeros(12)
+        x0[:3] = rng.uniform(20.0, 80.0, 3)
+        x0[3:6] = rng.uniform(-3.0, 3.0, 3)
+        x0[6:9] = rng.uniform(-10.0, 10.0, 3)
+        x0[9:] = rng.uniform(-8.0, 8.0, 3)
+        u = rng.uniform(p["u_lo"], p["u_hi"])
+        x = x0.copy()
+        for j in range(1, K + 1):
+            x = oracle.step(p, x, u)
+            dev = x[:3] - x0[:3] - j * h * x0[6:9]
+            w = (j * h) ** 2 / 2
+            assert np.all(dev >= a_lo * w - 1e-12 * (1 + np.abs(a_lo * w))), (j, dev, a_lo * w)
+            assert np.all(dev <= a_hi * w + 1e-12 * (1 + np.abs(a_hi * w))), (j, dev, a_hi * w)
+            worst_lo = max(worst_lo, float(np.max(dev[:2] / (a_lo[:2] * w))))
+            worst_hi = max(worst_hi, float(np.max(dev[:2] / (a_hi[:2] * w))))
+    # not vacuous: horizontal displacements come within a factor 3 of both ends
+    assert worst_lo > 1.0 / 3.0 and worst_hi > 1.0 / 3.0
