@@ -1196,8 +1196,10 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
             const float lx = fminf(px, x[0]) - margin, hx = fmaxf(px, x[0]) + margin;
             const float ly = fminf(py, x[1]) - margin, hy = fmaxf(py, x[1]) + margin;
             const float lz = fminf(pz, x[2]) - margin, hz = fmaxf(pz, x[2]) + margin;
-            // six comparisons per candidate (closed boxes: touching is a hit);
-            // measured faster here than the separation form used for culling.
+            // closed boxes: touching is a hit.  Each candidate takes the
+            // separation form (the same decisions as six comparisons), whose
+            // maxima stay on the vector unit instead of joining six lane
+            // masks on the scalar unit.
             bool hit = false;
             if (use_grid) {
               // the obstacles listed in the grid cells the swept box touches:
@@ -1241,12 +1243,9 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
                 for (uint32_t t = 0; t < tn; t += 2) {
                   const uint32_t ia = gent[entry(t)];
                   const uint32_t ib = (t + 1 < tn) ? (uint32_t)gent[entry(t + 1)] : (uint32_t)n_obs;
-                  const float* o = reinterpret_cast<const float*>(obox + 3 * ia);
-                  const float* q = reinterpret_cast<const float*>(obox + 3 * ib);
-                  hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) &
-                         (lz <= o[5]) & (o[2] <= hz);
-                  hit |= (lx <= q[3]) & (q[0] <= hx) & (ly <= q[4]) & (q[1] <= hy) &
-                         (lz <= q[5]) & (q[2] <= hz);
+                  const float sa = box_separation(lx, ly, lz, hx, hy, hz, obox + 3 * ia);
+                  const float sb = box_separation(lx, ly, lz, hx, hy, hz, obox + 3 * ib);
+                  hit |= fminf(sa, sb) <= 0.0f;
                 }
               } else {
                 for (int cz = cz0; cz <= cz1; ++cz) {
@@ -1255,11 +1254,8 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
                     const uint32_t k1 = goff[row + cx1 + 1];
                     uint32_t k = goff[row + cx0];
                     box_tests += k1 - k;
-                    for (; k < k1; ++k) {
-                      const float* o = reinterpret_cast<const float*>(obox + 3 * gent[k]);
-                      hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) &
-                             (lz <= o[5]) & (o[2] <= hz);
-                    }
+                    for (; k < k1; ++k)
+                      hit |= box_separation(lx, ly, lz, hx, hy, hz, obox + 3 * gent[k]) <= 0.0f;
                   }
                 }
               }
@@ -1276,12 +1272,9 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
               uint32_t ij = ij01;
               for (uint32_t q = 0; q < kmax; q += 2) {
                 const uint32_t ijn = my32[(q >> 1) + 1];
-                const float* o = reinterpret_cast<const float*>(obox + 3 * (ij & 0xffffu));
-                const float* r = reinterpret_cast<const float*>(obox + 3 * (ij >> 16));
-                hit |= (lx <= o[3]) & (o[0] <= hx) & (ly <= o[4]) & (o[1] <= hy) & (lz <= o[5]) &
-                       (o[2] <= hz);
-                hit |= (lx <= r[3]) & (r[0] <= hx) & (ly <= r[4]) & (r[1] <= hy) & (lz <= r[5]) &
-                       (r[2] <= hz);
+                const float sa = box_separation(lx, ly, lz, hx, hy, hz, obox + 3 * (ij & 0xffffu));
+                const float sb = box_separation(lx, ly, lz, hx, hy, hz, obox + 3 * (ij >> 16));
+                hit |= fminf(sa, sb) <= 0.0f;
                 ij = ijn;
               }
               box_tests += mycnt;
