@@ -1,23 +1,25 @@
 // Kino-PAX iteration kernels for gfx950 (CDNA4, wave64).
 //
-// One iteration of the main loop (Alg. 1) is three launches on one stream:
+// The planning loop (kp_plan, Alg. 1) runs each iteration as two launches on
+// one stream:
 //   k_propagate  Alg. 2 + the branching factor of eq. (6): one lane per
 //                (frontier node, sample); Philox controls; Euler / RK4
-//                segment integration with per-step validity (state box +
-//                swept box against LDS-staged obstacles, culled per wave);
-//                sub-region map; wave-aggregated n_valid / n_invalid atomics;
-//                acceptance; stable compaction of accepted samples (ballot +
-//                wave scan + decoupled look-back across tiles) straight into
-//                the tree tail.
-//   k_region     Alg. 3: FreeVol, Cov, Score (eqs. 3-4) and P_accept (eq. 5)
-//                for R_avail in one workgroup; the score sum is an exact
-//                integer sum, so the result is independent of thread order.
-//   k_nodesets   Alg. 4: demote / admit (visited, R_avail, goal) / promote in
-//                one pass over the tree, fused with the frontier compaction
-//                for the next iteration; the last block applies eq. (6).
-// All kernels are persistent: blocks take tiles from an atomic ticket, so a
-// grid sized from occupancy covers any |V_E| * lambda or |T| read from device
-// memory, and the host never needs these sizes to launch.
+//                integration of the whole segment (x'), with per-step validity
+//                up to the first failing step (state box, then the swept box
+//                against LDS-staged obstacles: a uniform grid for a double
+//                integrator among many boxes, else candidate lists culled per
+//                wave and per group of four lanes); sub-region map;
+//                wave-aggregated n_valid / n_invalid atomics; acceptance; the
+//                accepted samples staged per 64-lane wave tile.
+//   k_post       the rest of the iteration in one launch: Alg. 3 (FreeVol,
+//                Cov, Score and P_accept, eqs. 3-5, with an exact integer
+//                score sum) in the region blocks; Alg. 4 (demote / promote)
+//                fused with the compaction of the next frontier in the
+//                node-set blocks, whose last chunk applies eq. (6); the
+//                commit of V_U (ids in lane order) in the commit blocks.
+// The step entry points run the same work as k_propagate + k_commit,
+// k_region and k_nodesets.  Every kernel reads its sizes from device memory,
+// so the host can enqueue several iterations without knowing them.
 #include "kp_internal.h"
 
 #include <hip/hip_ext.h>
@@ -1361,7 +1363,12 @@ __device__ __forceinline__ void propagate_body(const Env* __restrict__ env, Trac
       t->accept = accept ? 1 : 0;
       t->new_id = id;
     }
-    {
+    // the group's tickets hand out tiles nwaves + grp, nwaves + ng + grp, ...;
+    // when the first of them is past the end (a launch with fewer tiles than
+    // the grid has waves) the wave is done without the atomic's round trip
+    if (nwaves + grp >= ntiles) {
+      next = ntiles;
+    } else {
       uint32_t tk = 0;
       if (__lane_id() == 0) tk = atomicAdd(&c->tkp[grp].v, 1u);
       next = nwaves + ng * __builtin_amdgcn_readfirstlane(tk) + grp;
