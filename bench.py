@@ -120,7 +120,7 @@ def gpu_workload(name: str, seed: int = 0):
 
 def host_cores() -> int:
     """Threads the oracle may use: the CPUs this process may run on, bounded
-    by OMP_NUM_THREADS when it is set (the GPU machine sets it to its CPU share)."""
+    by OMP_NUM_THREADS when it is set (a host may set it to its CPU share)."""
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit() and int(env) > 0:
@@ -550,8 +550,8 @@ def main():
                          "traffic, used to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only; run it with --gpus 1 (the planner does not "
+              "shard a query over several GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import torch
