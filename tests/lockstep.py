@@ -477,6 +477,17 @@ def run_lockstep_plan(p, iterations, device="cuda:0", reload=False, launch_limit
             break
         tr = G.trace(trace, len(recs))
         gs1 = G.stats()
+        if not (np.array_equal(tr["parent"], recs["parent"]) and
+                np.array_equal(tr["sample"], recs["sample"])):
+            # diagnosis only (the comparison below still fails): does a second
+            # read of the same trace, after another synchronisation, agree?
+            torch.cuda.synchronize()
+            tr2 = G.trace(trace, len(recs))
+            same2 = (np.array_equal(tr2["parent"], recs["parent"]) and
+                     np.array_equal(tr2["sample"], recs["sample"]))
+            print(f"it{it}: trace lane order differs; a second read of the trace "
+                  f"{'matches the oracle' if same2 else 'differs too'}; the tree after this "
+                  f"call is compared below", flush=True)
         checked = np.where(tr["valid"] == 1, tr["steps"], tr["fail_step"]).astype(np.int64)
         got = (gs1["lanes_total"] - gs["lanes_total"], gs1["valid_total"] - gs["valid_total"],
                gs1["steps_total"] - gs["steps_total"],
